@@ -1,0 +1,255 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module holds only input generation: voxel media, grid geometry,
+source/receiver locations, the source wavelet and random test matrices.
+It contains none of the reduced-order method's arithmetic (no operator
+assembly, splitting, Krylov, Lanczos or time stepping), so importing it
+from both the CPU oracle and the GPU path shares no method code.
+
+Workload shapes follow the paper's numerical section (Sec. 9): 3D acoustic
+media on a Cartesian grid with Dirichlet walls, split into cubic coarse
+cells, point sources and receivers on the partition skeleton (Sec. 2,
+eq. gsupport), and a band-limited wavelet (Sec. 1).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "gaussian_field", "acoustic_medium", "layered_medium", "ricker",
+    "Workload", "workload", "face_interior_nodes", "random_spd",
+]
+
+
+# --------------------------------------------------------------------------
+# media
+# --------------------------------------------------------------------------
+
+def gaussian_field(shape: Tuple[int, ...], ell: float, rng: np.random.Generator,
+                   uniform: bool = False) -> np.ndarray:
+    """Smooth random field on a periodic voxel grid, min-max scaled to [0, 1].
+
+    White noise (standard normal, or U[0,1] when ``uniform``) is filtered in
+    Fourier space by exp(-2 pi^2 ell^2 |k|^2) (k in cycles per voxel), i.e. a
+    Gaussian kernel with standard deviation ``ell`` voxels.
+    """
+    noise = rng.random(shape) if uniform else rng.standard_normal(shape)
+    spec = np.fft.fftn(noise)
+    k2 = np.zeros(shape)
+    for ax, n in enumerate(shape):
+        k = np.fft.fftfreq(n)
+        sh = [1] * len(shape)
+        sh[ax] = n
+        k2 = k2 + (k.reshape(sh)) ** 2
+    f = np.real(np.fft.ifftn(spec * np.exp(-2.0 * np.pi ** 2 * ell ** 2 * k2)))
+    lo, hi = f.min(), f.max()
+    return (f - lo) / (hi - lo) if hi > lo else np.zeros(shape)
+
+
+def acoustic_medium(nvox: Tuple[int, int, int], seed: int,
+                    sigma_range=(1.0, 4.0), rho_range=(1.0, 2.0),
+                    ell_sigma: float = 6.0, ell_rho: float = 2.0):
+    """Per-voxel stiffness sigma and density rho, arrays indexed [x, y, z].
+
+    sigma = lo * (hi/lo)^f with f a smooth Gaussian field (log-uniform range,
+    the exponential of a smooth field); rho = lo + (hi-lo) * smooth(U[0,1]).
+    sigma is drawn before rho from one PCG64 stream seeded with ``seed``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = gaussian_field(tuple(nvox), ell_sigma, rng)
+    s0, s1 = sigma_range
+    sigma = s0 * (s1 / s0) ** f
+    r = gaussian_field(tuple(nvox), ell_rho, rng, uniform=True)
+    r0, r1 = rho_range
+    rho = r0 + (r1 - r0) * r
+    return np.ascontiguousarray(sigma), np.ascontiguousarray(rho)
+
+
+def layered_medium(nvox: Tuple[int, int, int], seed: int,
+                   z_bounds: Sequence[int], contrast: float = 3.0,
+                   perturb: float = 0.10, ell: float = 6.0):
+    """Horizontally layered medium with a smooth multiplicative perturbation.
+
+    Layer j gets sigma = contrast^(j/(L-1)) in a seeded order, rho ~ U[1,2]
+    per layer; both are multiplied by (1 + perturb * (2 f - 1)) with f a
+    smooth field of correlation length ``ell``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nz = nvox[2]
+    edges = [0] + list(z_bounds) + [nz]
+    L = len(edges) - 1
+    order = rng.permutation(L)
+    sig_layer = contrast ** (order / max(L - 1, 1))
+    rho_layer = 1.0 + rng.random(L)
+    sigma = np.empty(nvox)
+    rho = np.empty(nvox)
+    for j in range(L):
+        sigma[:, :, edges[j]:edges[j + 1]] = sig_layer[j]
+        rho[:, :, edges[j]:edges[j + 1]] = rho_layer[j]
+    f1 = gaussian_field(tuple(nvox), ell, rng)
+    f2 = gaussian_field(tuple(nvox), ell, rng)
+    sigma *= 1.0 + perturb * (2.0 * f1 - 1.0)
+    rho *= 1.0 + perturb * (2.0 * f2 - 1.0)
+    return np.ascontiguousarray(sigma), np.ascontiguousarray(rho)
+
+
+# --------------------------------------------------------------------------
+# wavelet
+# --------------------------------------------------------------------------
+
+def ricker(n_steps: int, dt: float, f_p: float) -> np.ndarray:
+    """Ricker wavelet samples w[n] = w(n dt), n = 0..n_steps-1.
+
+    w(t) = (1 - 2 pi^2 f_p^2 tau^2) exp(-pi^2 f_p^2 tau^2), tau = t - t0,
+    t0 = 1.5 / f_p, and w = 0 exactly for t > 2 t0 (so energy tests see a
+    source-free tail).
+    """
+    t = np.arange(n_steps, dtype=np.float64) * dt
+    t0 = 1.5 / f_p
+    tau = t - t0
+    a = (np.pi * f_p * tau) ** 2
+    w = (1.0 - 2.0 * a) * np.exp(-a)
+    w[t > 2.0 * t0] = 0.0
+    return w
+
+
+# --------------------------------------------------------------------------
+# geometry helpers (plain coordinate logic)
+# --------------------------------------------------------------------------
+
+def face_interior_nodes(nvox, cuts) -> np.ndarray:
+    """All grid nodes (x, y, z) strictly inside the domain that lie on exactly
+    one interior cut plane. Returns an (n, 3) int64 array in x-fastest order."""
+    out = []
+    cutsets = [set(int(c) for c in cuts[a]) for a in range(3)]
+    nx, ny, nz = nvox
+    for z in range(1, nz):
+        for y in range(1, ny):
+            for x in range(1, nx):
+                k = (x in cutsets[0]) + (y in cutsets[1]) + (z in cutsets[2])
+                if k == 1:
+                    out.append((x, y, z))
+    return np.array(out, dtype=np.int64).reshape(-1, 3)
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    """One synthetic workload: medium, partition geometry, ROM sizes,
+    sources, receivers and time stepping parameters."""
+    name: str
+    nvox: Tuple[int, int, int]
+    sigma: np.ndarray
+    rho: np.ndarray
+    cuts: Tuple[np.ndarray, np.ndarray, np.ndarray]   # interior cut planes per axis
+    m: int                                           # S-fraction layers (Krylov blocks)
+    modes_face: int
+    modes_edge: int
+    sources: np.ndarray                              # (n_s, 3) node coords
+    receivers: np.ndarray                            # (n_r, 3) node coords
+    n_steps: int
+    f_p: float                                       # Ricker peak frequency
+    omega_max: float                                 # band edge 2 pi f_max
+    shift: float                                     # Krylov shift s < 0
+    cfl_fraction: float = 0.5
+    seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+def _band(c_min: float, ppw: float = 10.0):
+    """Ricker peak frequency for ``ppw`` points per shortest wavelength on a
+    unit grid: f_max = 2.5 f_p and c_min / f_max = ppw."""
+    f_max = c_min / ppw
+    f_p = f_max / 2.5
+    omega_max = 2.0 * np.pi * f_max
+    return f_p, omega_max
+
+
+def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optional[int] = None,
+             m: Optional[int] = None, n_steps: Optional[int] = None,
+             n_sources: Optional[int] = None, n_receivers: Optional[int] = None,
+             realisation: int = 0, ppw: float = 10.0) -> Workload:
+    """Build a named workload.
+
+    ``tiny``   : 16^3 voxels, 2^3 cells of 8^3 (fast CPU tests)
+    ``small``  : 32^3 voxels, 4^3 cells of 8^3, one source, 64 receivers,
+                 1500 steps (the FP64 case)
+    ``medium`` : 64^3 voxels, 8^3 cells, 16 sources (parity case that spans
+                 many cells but stays within seconds for the oracle)
+    ``large``  : 128^3 voxels, 16^3 cells of 8^3, 64 sources on an 8x8 grid,
+                 1024 receivers, 4000 steps (the batched FP32 case)
+    """
+    mf = 9 if modes_face is None else modes_face
+    me = 2 if modes_edge is None else modes_edge
+    c_min = np.sqrt(1.0 / 2.0)        # sqrt(sigma_lo / rho_hi) of the generator bounds
+    f_p, omega_max = _band(c_min, ppw)
+    shift = -omega_max ** 2 / 10.0
+    if name == "tiny":
+        nvox = (16, 16, 16)
+        seed = 9001 + realisation
+        sigma, rho = acoustic_medium(nvox, seed)
+        cuts = tuple(np.array([8]) for _ in range(3))
+        src = np.array([[5, 3, 8]], dtype=np.int64)
+        rec_all = face_interior_nodes(nvox, cuts)
+        rng = np.random.Generator(np.random.PCG64(seed + 100))
+        nr = 16 if n_receivers is None else n_receivers
+        rec = rec_all[np.sort(rng.choice(len(rec_all), size=nr, replace=False))]
+        return Workload(name, nvox, sigma, rho, cuts, m or 3, mf, me, src, rec,
+                        n_steps or 400, f_p, omega_max, shift, seed=seed)
+    if name == "small":
+        nvox = (32, 32, 32)
+        seed = 1001 + realisation
+        sigma, rho = acoustic_medium(nvox, seed)
+        cuts = tuple(np.array([8, 16, 24]) for _ in range(3))
+        src = np.array([[20, 20, 16]], dtype=np.int64)
+        rec_all = face_interior_nodes(nvox, cuts)
+        rng = np.random.Generator(np.random.PCG64(1101 + realisation))
+        nr = 64 if n_receivers is None else n_receivers
+        rec = rec_all[np.sort(rng.choice(len(rec_all), size=nr, replace=False))]
+        return Workload(name, nvox, sigma, rho, cuts, m or 4, mf, me, src, rec,
+                        n_steps or 1500, f_p, omega_max, shift, seed=seed)
+    if name == "medium":
+        nvox = (64, 64, 64)
+        seed = 3001 + realisation
+        sigma, rho = acoustic_medium(nvox, seed)
+        cuts = tuple(np.arange(8, 64, 8) for _ in range(3))
+        a = np.arange(4)
+        src = np.array([[12 + 16 * i, 12 + 16 * j, 56] for j in a for i in a], dtype=np.int64)
+        if n_sources is not None:
+            src = src[:n_sources]
+        b = np.arange(16)
+        rec = np.array([[2 + 4 * i, 2 + 4 * j, 56] for j in b for i in b], dtype=np.int64)
+        return Workload(name, nvox, sigma, rho, cuts, m or 4, mf, me, src, rec,
+                        n_steps or 600, f_p, omega_max, shift, seed=seed)
+    if name == "large":
+        nvox = (128, 128, 128)
+        seed = 2001 + realisation
+        sigma, rho = acoustic_medium(nvox, seed)
+        cuts = tuple(np.arange(8, 128, 8) for _ in range(3))
+        a = np.arange(8)
+        src = np.array([[12 + 16 * i, 12 + 16 * j, 120] for j in a for i in a], dtype=np.int64)
+        if n_sources is not None:
+            src = src[:n_sources]
+        b = np.arange(32)
+        rec = np.array([[2 + 4 * i, 2 + 4 * j, 120] for j in b for i in b], dtype=np.int64)
+        return Workload(name, nvox, sigma, rho, cuts, m or 4, mf, me, src, rec,
+                        n_steps or 4000, f_p, omega_max, shift, seed=seed)
+    raise ValueError(f"unknown workload {name!r}")
+
+
+# --------------------------------------------------------------------------
+# random test matrices
+# --------------------------------------------------------------------------
+
+def random_spd(n: int, rng: np.random.Generator, cond: float = 10.0, scale: float = 1.0) -> np.ndarray:
+    """Random symmetric positive definite n x n matrix with eigenvalues
+    log-spaced in [scale/cond, scale]."""
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = scale * np.logspace(-np.log10(cond), 0.0, n)
+    return (q * ev) @ q.T
