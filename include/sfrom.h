@@ -1,0 +1,242 @@
+/*
+ * sfrom.h - C ABI of libsfrom, a gfx950 (MI355X) implementation of the
+ * multi-scale S-fraction reduced-order model (ROM) for wavefield simulation
+ * of Druskin, Mamonov and Zaslavsky.
+ *
+ * Problem statement (Sec. 1, eq. wave_fll): a fine-grid pencil with sparse
+ * symmetric A <= 0 and diagonal B > 0, time-domain model B u'' = A u + w(t) g
+ * with u = 0 for t <= 0, source columns g and receiver columns q supported on
+ * the partition skeleton (Sec. 2, eq. gsupport), and a coarse-cell partition
+ * with a splitting A = sum_i P_i A_i P_i^T, B = sum_i P_i B_i P_i^T
+ * (eq. splitN_c). The library builds each cell's matrix S-fraction off-line
+ * (Alg. alg1red stage 1) and time steps the coupled ROM on-line (stage 2).
+ * A fine-grid leapfrog of the same pencil is provided as the comparator.
+ *
+ * Conventions
+ *  - Every function returns an sfrom_status (0 = OK, < 0 = error) and never
+ *    throws across the ABI; sfrom_last_error() holds a message for the last
+ *    failing call on the handle.
+ *  - Input arrays are caller-owned, read during the call and never retained.
+ *    Output arrays are caller-owned. "host" pointers are ordinary CPU memory;
+ *    "device" pointers are HIP device memory of the handle's device (for
+ *    example a torch tensor's data_ptr()).
+ *  - Work is enqueued on the stream given at creation. Calls that return
+ *    host data synchronise that stream before returning. A handle is used by
+ *    one thread at a time.
+ *  - Dense matrices are column-major unless stated otherwise.
+ *  - Sign convention: the source enters as +w(t) g (the paper writes the
+ *    impulse on the other side of the equation; the sign is common to the
+ *    fine model and the ROM and does not change any comparison).
+ */
+#ifndef SFROM_H
+#define SFROM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfrom sfrom_t;
+
+typedef enum {
+  SFROM_OK = 0,
+  SFROM_EINVAL = -1,      /* bad argument (size, index, null pointer)            */
+  SFROM_ENOTSYM = -2,     /* A or A_i not symmetric                              */
+  SFROM_ENOTNSD = -3,     /* A_i not <= 0 (diagonal dominance / Cholesky fails)  */
+  SFROM_EBPOS = -4,       /* B or B_i not > 0                                    */
+  SFROM_ESUPPORT = -5,    /* source/receiver nonzero off the skeleton (gsupport) */
+  SFROM_EBREAKDOWN = -6,  /* Krylov/Lanczos block lost rank (Assumption 1)       */
+  SFROM_ENOTSPD = -7,     /* S-fraction pivot not SPD (Assumption 2)             */
+  SFROM_ECFL = -8,        /* dt above the leapfrog stability limit               */
+  SFROM_ENONFINITE = -9,  /* NaN/Inf in an input or in the state                 */
+  SFROM_EDEVICE = -10,    /* HIP runtime error                                   */
+  SFROM_ESTATE = -11,     /* call out of order (e.g. run before build)           */
+  SFROM_ENOMEM = -12,     /* device or host allocation failed                    */
+  SFROM_ESPLIT = -13      /* sum of cell operators does not reproduce (A, B)     */
+} sfrom_status;
+
+/* Arithmetic of the on-line stage. F64: blocks and state in double.
+ * F32: blocks and state in float. BF16: blocks in bfloat16, state and
+ * accumulation in float. The off-line build is always double. */
+typedef enum { SFROM_F64 = 0, SFROM_F32 = 1, SFROM_BF16 = 2 } sfrom_prec;
+
+/* Create a handle on HIP device `device`; `hip_stream` is a hipStream_t (or
+ * NULL for the null stream) on which all work is enqueued. device == -1
+ * creates a host-only handle: problem set-up, validation and the export
+ * calls work, every call that needs the GPU returns SFROM_EDEVICE. */
+int sfrom_create(sfrom_t** out, int device, void* hip_stream);
+void sfrom_destroy(sfrom_t* h);
+/* Message for the last failing call; valid until the next call on h. */
+const char* sfrom_last_error(const sfrom_t* h);
+
+/* ---------------------------------------------------------------------------
+ * Problem definition (host data)
+ * ------------------------------------------------------------------------ */
+
+/* Fine pencil (Sec. 1, eq. wave_fll): A as CSR with both triangles, n rows,
+ * rowptr[n+1] (int64), col[nnz] (int32, sorted within a row), a[nnz];
+ * b[n] = diag(B). Replaces any previous pencil and partition.
+ * Errors: EINVAL (shape), ENOTSYM, EBPOS, ENONFINITE. */
+int sfrom_set_pencil(sfrom_t* h, int64_t n, const int64_t* rowptr, const int32_t* col,
+                     const double* a, const double* b);
+
+/* Coarse cell `cell` (0-based, added in any order, each once) with n_i local
+ * nodes: global_node[n_i] maps local -> global node; (rowptr_i[n_i+1],
+ * col_i, a_i) is A_i as local CSR with both triangles, b_i[n_i] = diag(B_i)
+ * (eq. splitN_c). A node shared by two or more cells is a skeleton node.
+ * The split is checked against the pencil at build time (ESPLIT).
+ * Errors: EINVAL, ENOTSYM, EBPOS, ENONFINITE, ESTATE (no pencil). */
+int sfrom_add_cell(sfrom_t* h, int32_t cell, int32_t n_i, const int64_t* global_node,
+                   const int32_t* rowptr_i, const int32_t* col_i, const double* a_i,
+                   const double* b_i);
+
+/* Skeleton piece `piece` (0-based): a connected set of k_p skeleton nodes
+ * shared by the same cells (a face interior, an edge line or a corner point
+ * of a Cartesian partition), global_node[k_p], with an orthonormal boundary
+ * basis S_p (k_p x b_p, column-major, S_p^T S_p = I) (Sec. 4.1). Each cell's
+ * boundary basis S_i is block diagonal over its pieces in ascending piece
+ * id. Every skeleton node must lie in exactly one piece.
+ * Errors: EINVAL, ESTATE. */
+int sfrom_add_piece(sfrom_t* h, int32_t piece, int32_t k_p, const int64_t* global_node,
+                    int32_t b_p, const double* S_p);
+
+/* Convenience set-up for the 3D acoustic example of Sec. 1: unit voxels
+ * nvox[0] x nvox[1] x nvox[2], per-voxel sigma and rho (x fastest), nodes at
+ * voxel corners with Dirichlet walls, each voxel adding sigma/4 to its 12
+ * edges and rho/8 to its 8 corners. Cells are the boxes between the
+ * interior cut planes cuts[] (ncut[0] x-planes, then y, then z, ascending
+ * node coordinates); A_i, B_i are the voxel sums of cell i (eq. splitN_c).
+ * Pieces are face interiors, edge lines and corner points with the lowest
+ * modes_face / modes_edge orthonormal DCT-II modes (corners: 1 mode).
+ * Cells are numbered x-fastest over the cell grid; pieces by first node in
+ * x-fastest node order; unknowns x-fastest over interior nodes. Equivalent
+ * to sfrom_set_pencil + sfrom_add_cell + sfrom_add_piece. */
+int sfrom_setup_voxel_acoustic(sfrom_t* h, const int32_t nvox[3], const double* sigma,
+                               const double* rho, const int32_t ncut[3], const int32_t* cuts,
+                               int32_t modes_face, int32_t modes_edge);
+
+/* ---------------------------------------------------------------------------
+ * Off-line stage (Alg. alg1red stage 1)
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t m;                 /* S-fraction layers (Krylov blocks) per cell, >= 1      */
+  const int32_t* m_per_cell; /* optional per-cell override (n_cells entries) or NULL */
+  double shift;              /* Krylov shift s < 0 (Sec. 4.2, eq. npks)              */
+  int32_t online_prec;       /* sfrom_prec of the on-line stage                       */
+  int32_t cells_per_batch;   /* off-line batch size (0 = automatic)                   */
+} sfrom_build_opts;
+
+/* Validate the split and the partition, then build every cell's S-fraction on
+ * the GPU: banded Cholesky of -(A_i + s B_i), rational block Krylov basis of
+ * span{X, KX, ..., K^{m-1}X} with K = (A_i+sB_i)^{-1} B_i, X = B_i^{-1} P S_i
+ * (eq. npks), projection (eq. tfprj), block Lanczos (App. C, eq. NtDtri),
+ * the S-fraction change of variables (eq. GammaTrans), piece masses
+ * M_p = sum_{i owns p} [(Ghat_i^1)^{-1}]_pp (eq. bdrytstep) and packing in
+ * the on-line precision. On failure no ROM is kept and the message names the
+ * first failing cell. Errors: ESTATE, ESPLIT, ENOTNSD, EBREAKDOWN, ENOTSPD,
+ * ENOMEM, EDEVICE. */
+int sfrom_build(sfrom_t* h, const sfrom_build_opts* opts);
+
+/* Replace cell `cell`'s S-fraction by m blocks Ghat^k and G^k (each b x b
+ * symmetric, column-major, stored consecutively: Ghat[k*b*b ...]); b must
+ * equal the cell's boundary dimension. Requires a built ROM; piece masses
+ * are recomputed from Ghat^1 at the next run. Errors: EINVAL, ESTATE, ENOTSPD. */
+int sfrom_import_rom(sfrom_t* h, int32_t cell, int32_t m, int32_t b, const double* Ghat,
+                     const double* G);
+/* Copy cell `cell`'s S-fraction to host: *m, *b, and (if non-NULL) Ghat, G
+ * with room for m*b*b doubles each, in double precision as built. */
+int sfrom_export_rom(sfrom_t* h, int32_t cell, int32_t* m, int32_t* b, double* Ghat,
+                     double* G);
+
+/* ---------------------------------------------------------------------------
+ * Inputs and outputs (host data, CSC sparse columns over global nodes)
+ * ------------------------------------------------------------------------ */
+
+/* n_s source columns g_j as CSC (colptr[n_s+1], row[nnz] global node, val).
+ * project != 0 replaces each column by its orthogonal projection onto the
+ * piece bases (g <- S_p S_p^T g on every piece), for the fine model too;
+ * project == 0 keeps g for the fine model and uses S_p^T g for the ROM.
+ * Any nonzero off the skeleton gives ESUPPORT (eq. gsupport). */
+int sfrom_set_sources(sfrom_t* h, int32_t n_s, const int64_t* colptr, const int64_t* row,
+                      const double* val, int32_t project);
+/* Receiver columns q_r, same format and meaning of `project`; traces are
+ * q_r^T u (fine) and sum_p (S_p^T q_r)^T y_p (ROM, eq. solatrec). */
+int sfrom_set_receivers(sfrom_t* h, int32_t n_r, const int64_t* colptr, const int64_t* row,
+                        const double* val, int32_t project);
+/* Projected point columns at the given global skeleton nodes: column j is
+ * S_p S_p^T e_node. colptr_out[count+1] is filled; row_out/val_out need room
+ * for the sum of the pieces' sizes (at most count * max k_p). */
+int sfrom_point_columns(sfrom_t* h, int32_t count, const int64_t* node, int64_t* colptr_out,
+                        int64_t* row_out, double* val_out);
+
+/* ---------------------------------------------------------------------------
+ * On-line stage (Alg. alg1red stage 2) and the fine-grid comparator
+ * ------------------------------------------------------------------------ */
+
+/* Zero the ROM state (eq. initial: U = 0 for t <= 0). */
+int sfrom_reset(sfrom_t* h);
+/* Advance the ROM n_steps leapfrog steps of size dt from its current state:
+ * Y^{n+1} = 2Y^n - Y^{n-1} + dt^2 D^{-1} (L Y^n + w^n F), hidden layers by
+ * eq. intrtstep_td, piece dofs by eq. bdrytstep. w[n_steps] (double) are the
+ * wavelet samples for these steps, host memory unless w_on_device.
+ * traces receives n_steps x n_r x n_s values (source fastest) of the
+ * receiver output at levels n+1, as double for F64 and float otherwise,
+ * host memory unless traces_on_device. dt must satisfy the stability limit
+ * of the ROM when known (ECFL). Errors: ESTATE, EINVAL, ECFL, EDEVICE. */
+int sfrom_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int32_t w_on_device,
+              void* traces, int32_t traces_on_device);
+
+/* Zero the fine-grid state. */
+int sfrom_fine_reset(sfrom_t* h);
+/* Fine-grid leapfrog u^{n+1} = 2u^n - u^{n-1} + dt^2 B^{-1}(A u^n + w^n g)
+ * for all sources in precision `prec` (F64 or F32); traces as in sfrom_run
+ * (q^T u^{n+1}). */
+int sfrom_fine_run(sfrom_t* h, int64_t n_steps, double dt, const double* w,
+                   int32_t w_on_device, void* traces, int32_t traces_on_device,
+                   int32_t prec);
+/* Largest eigenvalue of B^{-1}(-A) (Lanczos on the GPU; relative accuracy
+ * about 1e-10). The leapfrog is stable for dt < 2/sqrt(lambda). */
+int sfrom_fine_lambda_max(sfrom_t* h, double* lambda);
+/* Largest eigenvalue of the global ROM pencil (-L, D); needs a built ROM. */
+int sfrom_rom_lambda_max(sfrom_t* h, double* lambda);
+
+/* ---------------------------------------------------------------------------
+ * Introspection
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t n;               /* fine unknowns                       */
+  int64_t nnz;             /* nonzeros of A                       */
+  int32_t n_cells;
+  int32_t n_pieces;
+  int64_t n_piece_dofs;    /* sum_p b_p                            */
+  int64_t n_hidden_dofs;   /* sum_i (m_i - 1) b_i (0 before build) */
+  int32_t max_b;           /* max_i b_i                            */
+  int32_t max_m;
+  int32_t n_sources;
+  int32_t n_receivers;
+  int32_t built;
+  int32_t online_prec;
+  int64_t block_bytes;     /* on-line S-fraction storage           */
+  double build_ms;         /* last sfrom_build wall time          */
+} sfrom_info;
+
+int sfrom_get_info(const sfrom_t* h, sfrom_info* info);
+
+/* Copy the fine pencil to host (sizes from sfrom_get_info). */
+int sfrom_export_pencil(sfrom_t* h, int64_t* rowptr, int32_t* col, double* a, double* b);
+/* Cell sizes and (if non-NULL) its local operator: *n_i, *nnz_i, global_node,
+ * rowptr_i, col_i, a_i, b_i, and its boundary dimension *b_i_out. */
+int sfrom_export_cell(sfrom_t* h, int32_t cell, int32_t* n_i, int32_t* nnz_i,
+                      int32_t* b_dim, int64_t* global_node, int32_t* rowptr_i,
+                      int32_t* col_i, double* a_i, double* b_i);
+/* Piece sizes and (if non-NULL) nodes and basis. */
+int sfrom_export_piece(sfrom_t* h, int32_t piece, int32_t* k_p, int32_t* b_p,
+                       int64_t* global_node, double* S_p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFROM_H */

@@ -1,0 +1,1290 @@
+// Host side of libsfrom: argument validation, partition bookkeeping, device
+// memory, orchestration of the off-line build and of the on-line and
+// fine-grid time loops. All arithmetic of the method runs in the HIP
+// kernels; the host only validates, packs and launches.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sfrom_internal.h"
+
+using namespace sfrom_impl;
+
+namespace {
+
+struct Fail {
+  int code;
+};
+
+int set_err(sfrom_t* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      h->err = std::string("HIP error in ") + #expr + ": " + hipGetErrorString(_e);     \
+      throw Fail{_e == hipErrorOutOfMemory ? SFROM_ENOMEM : SFROM_EDEVICE};            \
+    }                                                                                   \
+  } while (0)
+
+#define REQUIRE(cond, code, msg)          \
+  do {                                    \
+    if (!(cond)) {                        \
+      h->err = (msg);                     \
+      throw Fail{code};                   \
+    }                                     \
+  } while (0)
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) hipFree((void*)p);
+  p = nullptr;
+}
+
+template <typename T>
+T* dalloc(sfrom_t* h, size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) {
+    h->err = "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " + hipGetErrorString(e);
+    throw Fail{SFROM_ENOMEM};
+  }
+  return reinterpret_cast<T*>(p);
+}
+
+template <typename T>
+T* dupload(sfrom_t* h, const std::vector<T>& v) {
+  T* p = dalloc<T>(h, v.size());
+  if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+size_t prec_bytes(int prec) { return prec == SFROM_F64 ? 8 : 4; }        // state / masses
+size_t block_bytes(int prec) { return prec == SFROM_F64 ? 8 : (prec == SFROM_F32 ? 4 : 2); }
+
+void free_rom(sfrom_t* h) {
+  if (h->device < 0) { h->built = false; return; }
+  dfree(h->d_blocks); dfree(h->d_minv); dfree(h->d_rom64); dfree(h->d_rom64_off);
+  dfree(h->d_ocells); dfree(h->d_opieces); dfree(h->d_gather); dfree(h->d_inc);
+  dfree(h->d_inc_cell); dfree(h->d_inc_col);
+  dfree(h->d_src); dfree(h->d_rptr); dfree(h->d_rrow); dfree(h->d_rval);
+  dfree(h->d_y[0]); dfree(h->d_y[1]); dfree(h->d_h[0]); dfree(h->d_h[1]); dfree(h->d_phi);
+  h->built = false;
+  h->state_ns = -1;
+  h->src_dirty = h->rec_dirty = true;
+}
+
+void free_fine(sfrom_t* h) {
+  dfree(h->d_frowptr); dfree(h->d_fcol); dfree(h->d_fa); dfree(h->d_fbinv);
+  dfree(h->d_u[0]); dfree(h->d_u[1]);
+  dfree(h->d_fsrc_row); dfree(h->d_fsrc_col); dfree(h->d_fsrc_val);
+  dfree(h->d_frec_ptr); dfree(h->d_frec_row); dfree(h->d_frec_val);
+  h->fine_prec = -1; h->fine_ns = -1; h->fine_io_dirty = true;
+}
+
+void free_all(sfrom_t* h) {
+  if (h->device < 0) return;
+  free_rom(h);
+  free_fine(h);
+  dfree(h->d_w);
+  h->d_w_cap = 0;
+}
+
+// ---------------------------------------------------------------------------
+// partition bookkeeping
+// ---------------------------------------------------------------------------
+
+void finalize_partition(sfrom_t* h) {
+  if (h->part_ready) return;
+  REQUIRE(h->n > 0, SFROM_ESTATE, "no pencil: call sfrom_set_pencil or sfrom_setup_voxel_acoustic first");
+  const int nc = (int)h->cells.size(), np = (int)h->pieces.size();
+  REQUIRE(nc >= 1, SFROM_ESTATE, "no cells defined");
+  for (int i = 0; i < nc; ++i) REQUIRE(h->cells[i].defined, SFROM_ESTATE, "cell " + std::to_string(i) + " not defined");
+  for (int p = 0; p < np; ++p) REQUIRE(h->pieces[p].defined, SFROM_ESTATE, "piece " + std::to_string(p) + " not defined");
+  const int64_t n = h->n;
+  std::vector<int32_t> cnt(n, 0);
+  for (auto& c : h->cells)
+    for (int64_t g : c.gnode) cnt[g]++;
+  for (int64_t g = 0; g < n; ++g)
+    REQUIRE(cnt[g] >= 1, SFROM_ESPLIT, "node " + std::to_string(g) + " belongs to no cell");
+  h->piece_of_node.assign(n, -1);
+  h->pos_in_piece.assign(n, -1);
+  for (int p = 0; p < np; ++p) {
+    const auto& pc = h->pieces[p];
+    for (size_t k = 0; k < pc.gnode.size(); ++k) {
+      const int64_t g = pc.gnode[k];
+      REQUIRE(h->piece_of_node[g] < 0, SFROM_EINVAL, "node " + std::to_string(g) + " in two pieces");
+      REQUIRE(cnt[g] >= 2, SFROM_EINVAL, "piece " + std::to_string(p) + " contains node " + std::to_string(g) + " that is not shared by two cells");
+      h->piece_of_node[g] = p;
+      h->pos_in_piece[g] = (int32_t)k;
+    }
+  }
+  for (int64_t g = 0; g < n; ++g)
+    REQUIRE(cnt[g] < 2 || h->piece_of_node[g] >= 0, SFROM_EINVAL, "skeleton node " + std::to_string(g) + " is in no piece");
+  // incident cells of every piece: cells containing its nodes (all nodes must agree)
+  std::vector<std::vector<int32_t>> node_cells_first(np);
+  std::vector<int32_t> hits(np, 0);
+  h->piece_cells.assign(np, {});
+  for (int i = 0; i < nc; ++i) {
+    std::map<int32_t, int32_t> count;
+    for (int64_t g : h->cells[i].gnode) {
+      const int32_t p = h->piece_of_node[g];
+      if (p >= 0) count[p]++;
+    }
+    for (auto& kv : count) {
+      REQUIRE(kv.second == (int32_t)h->pieces[kv.first].gnode.size(), SFROM_EINVAL,
+              "cell " + std::to_string(i) + " holds only part of piece " + std::to_string(kv.first));
+      h->piece_cells[kv.first].push_back(i);
+    }
+  }
+  h->cell_pieces.assign(nc, {});
+  h->cell_piece_col.assign(nc, {});
+  h->cell_b.assign(nc, 0);
+  for (int p = 0; p < np; ++p) {
+    REQUIRE(h->piece_cells[p].size() >= 2, SFROM_EINVAL, "piece " + std::to_string(p) + " is not shared by two cells");
+    for (int32_t c : h->piece_cells[p]) h->cell_pieces[c].push_back(p);
+  }
+  for (int i = 0; i < nc; ++i) {
+    std::sort(h->cell_pieces[i].begin(), h->cell_pieces[i].end());
+    int32_t col = 0;
+    for (int32_t p : h->cell_pieces[i]) {
+      h->cell_piece_col[i].push_back(col);
+      col += h->pieces[p].b;
+    }
+    h->cell_b[i] = col;
+    REQUIRE(col > 0, SFROM_EINVAL, "cell " + std::to_string(i) + " has no skeleton pieces");
+  }
+  h->piece_dof_off.assign(np + 1, 0);
+  for (int p = 0; p < np; ++p) h->piece_dof_off[p + 1] = h->piece_dof_off[p] + h->pieces[p].b;
+  // splitting check (eq. splitN_c): sum_i P_i A_i P_i^T = A, sum_i P_i B_i P_i^T = B
+  std::vector<double> asum(h->a.size(), 0.0), bsum(n, 0.0);
+  double amax = 0.0, bmax = 0.0;
+  for (double v : h->a) amax = std::max(amax, std::fabs(v));
+  for (double v : h->b) bmax = std::max(bmax, std::fabs(v));
+  for (int i = 0; i < nc; ++i) {
+    const auto& c = h->cells[i];
+    for (int r = 0; r < c.n; ++r) {
+      const int64_t gr = c.gnode[r];
+      bsum[gr] += c.b[r];
+      const int32_t* cb = h->col.data() + h->rowptr[gr];
+      const int32_t* ce = h->col.data() + h->rowptr[gr + 1];
+      for (int k = c.rowptr[r]; k < c.rowptr[r + 1]; ++k) {
+        const int64_t gc = c.gnode[c.col[k]];
+        const int32_t* it = std::lower_bound(cb, ce, (int32_t)gc);
+        if (it == ce || *it != gc) {
+          REQUIRE(c.a[k] == 0.0, SFROM_ESPLIT, "cell " + std::to_string(i) + " has an entry outside the pattern of A");
+          continue;
+        }
+        asum[it - h->col.data()] += c.a[k];
+      }
+    }
+  }
+  for (size_t k = 0; k < asum.size(); ++k)
+    REQUIRE(std::fabs(asum[k] - h->a[k]) <= 1e-12 * amax, SFROM_ESPLIT, "sum of cell operators differs from A at entry " + std::to_string(k));
+  for (int64_t g = 0; g < n; ++g)
+    REQUIRE(std::fabs(bsum[g] - h->b[g]) <= 1e-12 * bmax, SFROM_ESPLIT, "sum of cell masses differs from B at node " + std::to_string(g));
+  h->part_ready = true;
+}
+
+// restriction of sparse columns to the skeleton pieces (Sec. 6: reduced
+// inputs g_ij = S_ij^T g restricted to Gamma_ij)
+void make_columns(sfrom_t* h, Columns& out, int32_t count, const int64_t* colptr, const int64_t* row,
+                  const double* val, int project) {
+  Columns c;
+  c.count = count;
+  c.colptr.push_back(0);
+  c.rptr.push_back(0);
+  for (int j = 0; j < count; ++j) {
+    std::map<int32_t, std::vector<double>> coef;   // piece -> S_p^T g
+    for (int64_t k = colptr[j]; k < colptr[j + 1]; ++k) {
+      const int64_t g = row[k];
+      REQUIRE(g >= 0 && g < h->n, SFROM_EINVAL, "column row index out of range");
+      REQUIRE(std::isfinite(val[k]), SFROM_ENONFINITE, "non-finite column value");
+      if (val[k] == 0.0) continue;
+      const int32_t p = h->piece_of_node[g];
+      REQUIRE(p >= 0, SFROM_ESUPPORT, "column " + std::to_string(j) + " has a nonzero at node " + std::to_string(g) + " off the skeleton (eq. gsupport)");
+      const auto& pc = h->pieces[p];
+      auto& cv = coef[p];
+      if (cv.empty()) cv.assign(pc.b, 0.0);
+      const int32_t pos = h->pos_in_piece[g];
+      const int64_t kp = (int64_t)pc.gnode.size();
+      for (int l = 0; l < pc.b; ++l) cv[l] += pc.S[pos + l * kp] * val[k];
+    }
+    if (project) {
+      std::vector<std::pair<int64_t, double>> ent;
+      for (auto& kv : coef) {
+        const auto& pc = h->pieces[kv.first];
+        const int64_t kp = (int64_t)pc.gnode.size();
+        for (int64_t r = 0; r < kp; ++r) {
+          double s = 0.0;
+          for (int l = 0; l < pc.b; ++l) s += pc.S[r + l * kp] * kv.second[l];
+          if (s != 0.0) ent.push_back({pc.gnode[r], s});
+        }
+      }
+      std::sort(ent.begin(), ent.end());
+      for (auto& e : ent) { c.row.push_back(e.first); c.val.push_back(e.second); }
+    } else {
+      for (int64_t k = colptr[j]; k < colptr[j + 1]; ++k) {
+        if (val[k] == 0.0) continue;
+        c.row.push_back(row[k]);
+        c.val.push_back(val[k]);
+      }
+    }
+    c.colptr.push_back((int64_t)c.row.size());
+    for (auto& kv : coef) {
+      c.rpiece.push_back(kv.first);
+      c.rcoff.push_back((int64_t)c.rcoef.size());
+      c.rcoef.insert(c.rcoef.end(), kv.second.begin(), kv.second.end());
+    }
+    c.rptr.push_back((int64_t)c.rpiece.size());
+  }
+  out = std::move(c);
+}
+
+// ---------------------------------------------------------------------------
+// off-line build
+// ---------------------------------------------------------------------------
+
+void build(sfrom_t* h, const sfrom_build_opts* o) {
+  auto t0 = std::chrono::steady_clock::now();
+  REQUIRE(o != nullptr, SFROM_EINVAL, "null build options");
+  REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle: no device for the build");
+  finalize_partition(h);
+  const int nc = (int)h->cells.size(), np = (int)h->pieces.size();
+  REQUIRE(o->shift < 0.0 && std::isfinite(o->shift), SFROM_EINVAL, "shift must be negative (Sec. 4.2)");
+  REQUIRE(o->online_prec >= SFROM_F64 && o->online_prec <= SFROM_BF16, SFROM_EINVAL, "bad on-line precision");
+  free_rom(h);
+  h->prec = o->online_prec;
+  h->shift = o->shift;
+  h->cell_m.assign(nc, o->m);
+  if (o->m_per_cell)
+    for (int i = 0; i < nc; ++i) h->cell_m[i] = o->m_per_cell[i];
+  for (int p = 0; p < np; ++p)
+    REQUIRE(h->pieces[p].b <= 32, SFROM_EINVAL, "piece " + std::to_string(p) + ": at most 32 basis vectors per piece");
+  int max_m = 0, max_b = 0, max_n = 0;
+  for (int i = 0; i < nc; ++i) {
+    REQUIRE(h->cell_m[i] >= 1, SFROM_EINVAL, "m must be >= 1");
+    REQUIRE((int64_t)h->cell_m[i] * h->cell_b[i] <= h->cells[i].n, SFROM_EBREAKDOWN,
+            "cell " + std::to_string(i) + ": m b_i exceeds the cell size (Assumption 1)");
+    max_m = std::max(max_m, h->cell_m[i]);
+    max_b = std::max(max_b, h->cell_b[i]);
+    max_n = std::max(max_n, h->cells[i].n);
+  }
+  // ---- on-line layout -------------------------------------------------------
+  h->ocells.resize(nc);
+  std::vector<int32_t> gather;
+  int64_t blk = 0, hid = 0, u1 = 0, r64 = 0;
+  h->rom64_off.resize(nc);
+  for (int i = 0; i < nc; ++i) {
+    OnlineCell& oc = h->ocells[i];
+    oc.m = h->cell_m[i];
+    oc.b = h->cell_b[i];
+    oc.blk_off = blk;
+    oc.hid_off = hid;
+    oc.u1_off = u1;
+    blk += (int64_t)(2 * oc.m - 1) * oc.b * oc.b;
+    hid += (int64_t)(oc.m - 1) * oc.b;
+    u1 += oc.b;
+    h->rom64_off[i] = r64;
+    r64 += (int64_t)2 * oc.m * oc.b * oc.b;
+    for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) {
+      const int32_t p = h->cell_pieces[i][q];
+      for (int l = 0; l < h->pieces[p].b; ++l) gather.push_back((int32_t)(h->piece_dof_off[p] + l));
+    }
+  }
+  h->n_hidden_dofs = hid;
+  h->block_elems = blk;
+  h->opieces.resize(np);
+  std::vector<int64_t> inc;
+  std::vector<int32_t> inc_cell, inc_col;
+  int64_t moff = 0;
+  for (int p = 0; p < np; ++p) {
+    OnlinePiece& op = h->opieces[p];
+    op.b = h->pieces[p].b;
+    op.ncell = (int32_t)h->piece_cells[p].size();
+    op.dof_off = h->piece_dof_off[p];
+    op.inc_off = (int64_t)inc.size();
+    op.minv_off = moff;
+    op.src_off = -1;
+    moff += (int64_t)op.b * op.b;
+    for (int32_t c : h->piece_cells[p]) {
+      const auto& cp = h->cell_pieces[c];
+      const size_t q = std::lower_bound(cp.begin(), cp.end(), p) - cp.begin();
+      inc.push_back(h->ocells[c].u1_off + h->cell_piece_col[c][q]);
+      inc_cell.push_back(c);
+      inc_col.push_back(h->cell_piece_col[c][q]);
+    }
+  }
+  h->d_ocells = dupload(h, h->ocells);
+  h->d_opieces = dupload(h, h->opieces);
+  h->d_gather = dupload(h, gather);
+  h->d_inc = dupload(h, inc);
+  h->d_inc_cell = dupload(h, inc_cell);
+  h->d_inc_col = dupload(h, inc_col);
+  h->d_blocks = dalloc<unsigned char>(h, (size_t)blk * block_bytes(h->prec));
+  h->d_minv = dalloc<unsigned char>(h, (size_t)moff * prec_bytes(h->prec));
+  h->d_rom64 = dalloc<double>(h, (size_t)r64);
+  h->d_rom64_off = dupload(h, h->rom64_off);
+  // ---- piece bases on the device --------------------------------------------
+  std::vector<double> S;
+  std::vector<int64_t> soff(np);
+  for (int p = 0; p < np; ++p) {
+    soff[p] = (int64_t)S.size();
+    S.insert(S.end(), h->pieces[p].S.begin(), h->pieces[p].S.end());
+  }
+  double* d_S = dupload(h, S);
+  // ---- per-cell workspace sizes -----------------------------------------------
+  std::vector<BuildCell> bcells(nc);
+  std::vector<int64_t> wsize(nc);
+  for (int i = 0; i < nc; ++i) {
+    const CellDef& c = h->cells[i];
+    BuildCell& bc = bcells[i];
+    bc.n = c.n; bc.b = h->cell_b[i]; bc.m = h->cell_m[i]; bc.nnz = (int32_t)c.a.size();
+    int w = 0;
+    for (int r = 0; r < c.n; ++r)
+      for (int k = c.rowptr[r]; k < c.rowptr[r + 1]; ++k) w = std::max(w, std::abs(r - c.col[k]));
+    bc.w = w;
+    const int64_t n = c.n, b = bc.b, mb = (int64_t)bc.m * b;
+    int64_t off = 0;
+    bc.band_off = off; off += n * (w + 1);
+    bc.v_off = off; off += n * mb;
+    bc.x_off = off; off += n * b;
+    bc.av_off = off; off += std::max({n * mb, 3 * mb * b + 2 * b * b, 8 * b * b + b, n * b});
+    bc.am_off = off; off += mb * mb;
+    bc.q_off = off; off += mb * mb;
+    bc.s_off = off; off += std::max(2 * mb * b, mb * b);
+    bc.r_off = off; off += mb * b;
+    bc.out_off = off; off += 2 * mb * b;
+    bc.status = 0;
+    wsize[i] = off;
+  }
+  // batch so that the workspace stays within a budget
+  const int64_t budget = (int64_t)8 << 30;   // bytes
+  int per_batch = o->cells_per_batch > 0 ? o->cells_per_batch : nc;
+  int64_t wmax = *std::max_element(wsize.begin(), wsize.end());
+  per_batch = (int)std::max<int64_t>(1, std::min<int64_t>(per_batch, budget / (wmax * 8)));
+  const int64_t wbytes_cap = wmax * per_batch;
+  double* d_work = dalloc<double>(h, (size_t)wbytes_cap);
+  BuildCell* d_bc = dalloc<BuildCell>(h, per_batch);
+  OnlineCell* d_oc_batch = nullptr;
+  for (int c0 = 0; c0 < nc; c0 += per_batch) {
+    const int cnt = std::min(per_batch, nc - c0);
+    std::vector<int32_t> rowptr, col, wrow, wcol, wbp, wkp;
+    std::vector<double> av, bd;
+    std::vector<int64_t> wsoff;
+    std::vector<BuildCell> bcb(bcells.begin() + c0, bcells.begin() + c0 + cnt);
+    int64_t woff = 0;
+    for (int t = 0; t < cnt; ++t) {
+      const int i = c0 + t;
+      const CellDef& c = h->cells[i];
+      BuildCell& bc = bcb[t];
+      bc.rp_off = (int64_t)rowptr.size();
+      bc.csr_off = (int64_t)col.size();
+      bc.b_off = (int64_t)bd.size();
+      rowptr.insert(rowptr.end(), c.rowptr.begin(), c.rowptr.end());
+      col.insert(col.end(), c.col.begin(), c.col.end());
+      av.insert(av.end(), c.a.begin(), c.a.end());
+      bd.insert(bd.end(), c.b.begin(), c.b.end());
+      bc.w_off = (int64_t)wrow.size();
+      std::map<int32_t, int32_t> pcol;
+      for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) pcol[h->cell_pieces[i][q]] = h->cell_piece_col[i][q];
+      int nw = 0;
+      for (int r = 0; r < c.n; ++r) {
+        const int32_t p = h->piece_of_node[c.gnode[r]];
+        if (p < 0) continue;
+        wrow.push_back(r);
+        wcol.push_back(pcol[p]);
+        wsoff.push_back(soff[p] + h->pos_in_piece[c.gnode[r]]);
+        wbp.push_back(h->pieces[p].b);
+        wkp.push_back((int32_t)h->pieces[p].gnode.size());
+        ++nw;
+      }
+      bc.nw = nw;
+      // rebase workspace offsets into this batch's work array
+      const int64_t base = woff;
+      bc.band_off += base; bc.v_off += base; bc.x_off += base; bc.av_off += base;
+      bc.am_off += base; bc.q_off += base; bc.s_off += base; bc.r_off += base; bc.out_off += base;
+      woff += wsize[i];
+    }
+    int32_t* d_rp = dupload(h, rowptr);
+    int32_t* d_col = dupload(h, col);
+    double* d_a = dupload(h, av);
+    double* d_bd = dupload(h, bd);
+    int32_t* d_wrow = dupload(h, wrow);
+    int32_t* d_wcol = dupload(h, wcol);
+    int64_t* d_wsoff = dupload(h, wsoff);
+    int32_t* d_wbp = dupload(h, wbp);
+    int32_t* d_wkp = dupload(h, wkp);
+    HIPCHK(hipMemcpy(d_bc, bcb.data(), cnt * sizeof(BuildCell), hipMemcpyHostToDevice));
+    BuildBatch bb;
+    bb.ncell = cnt;
+    bb.max_m = max_m; bb.max_b = max_b; bb.max_n = max_n;
+    bb.shift = o->shift;
+    bb.d_cells = d_bc;
+    bb.d_rowptr = d_rp; bb.d_col = d_col; bb.d_a = d_a; bb.d_bdiag = d_bd;
+    bb.d_wrow = d_wrow; bb.d_wcol = d_wcol; bb.d_wsoff = d_wsoff; bb.d_wbp = d_wbp; bb.d_wkp = d_wkp;
+    bb.d_S = d_S;
+    bb.d_work = d_work;
+    HIPCHK(launch_build(bb, h->stream));
+    HIPCHK(launch_pack(cnt, d_bc, d_work, h->d_ocells + c0, h->prec, h->d_blocks, h->d_rom64,
+                       h->d_rom64_off + c0, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(bcb.data(), d_bc, cnt * sizeof(BuildCell), hipMemcpyDeviceToHost));
+    dfree(d_rp); dfree(d_col); dfree(d_a); dfree(d_bd);
+    dfree(d_wrow); dfree(d_wcol); dfree(d_wsoff); dfree(d_wbp); dfree(d_wkp);
+    for (int t = 0; t < cnt; ++t) {
+      const int st = bcb[t].status;
+      if (st == 0) continue;
+      dfree(d_work); dfree(d_bc); dfree(d_S);
+      const std::string cell = "cell " + std::to_string(c0 + t) + ": ";
+      free_rom(h);
+      if (st == 1) { h->err = cell + "-(A_i + s B_i) is not positive definite (A_i not <= 0)"; throw Fail{SFROM_ENOTNSD}; }
+      if (st == 2) { h->err = cell + "Krylov/Lanczos block lost rank (Assumption 1)"; throw Fail{SFROM_EBREAKDOWN}; }
+      if (st == 3) { h->err = cell + "S-fraction pivot not SPD (Assumption 2)"; throw Fail{SFROM_ENOTSPD}; }
+      h->err = cell + "non-finite S-fraction"; throw Fail{SFROM_ENONFINITE};
+    }
+  }
+  (void)d_oc_batch;
+  dfree(d_work); dfree(d_bc); dfree(d_S);
+  h->built = true;
+  h->masses_dirty = true;
+  h->src_dirty = h->rec_dirty = true;
+  auto t1 = std::chrono::steady_clock::now();
+  h->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+void update_masses(sfrom_t* h) {
+  if (!h->masses_dirty) return;
+  const int np = (int)h->pieces.size();
+  int64_t moff = 0;
+  for (auto& op : h->opieces) moff += (int64_t)op.b * op.b;
+  int32_t* d_st = dalloc<int32_t>(h, np);
+  double* d_scr = dalloc<double>(h, (size_t)3 * moff);
+  MassArgs ma;
+  ma.npiece = np;
+  ma.d_pieces = h->d_opieces;
+  ma.d_inc_cell = h->d_inc_cell;
+  ma.d_inc_col = h->d_inc_col;
+  ma.d_cells = h->d_ocells;
+  ma.d_rom64 = h->d_rom64;
+  ma.d_rom64_off = h->d_rom64_off;
+  ma.prec = h->prec;
+  ma.d_minv = h->d_minv;
+  ma.d_status = d_st;
+  ma.d_scratch = d_scr;
+  HIPCHK(launch_piece_mass(ma, h->stream));
+  std::vector<int32_t> st(np);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(st.data(), d_st, np * sizeof(int32_t), hipMemcpyDeviceToHost));
+  dfree(d_st); dfree(d_scr);
+  for (int p = 0; p < np; ++p)
+    REQUIRE(st[p] == 0, SFROM_ENOTSPD, "piece " + std::to_string(p) + ": singular interface mass");
+  h->masses_dirty = false;
+}
+
+// ROM-side device inputs/outputs and state for n_s sources
+void prepare_online(sfrom_t* h) {
+  const int ns = h->src.count;
+  REQUIRE(ns > 0, SFROM_ESTATE, "no sources: call sfrom_set_sources");
+  const size_t eb = prec_bytes(h->prec);
+  if (h->src_dirty) {
+    // dense reduced sources for pieces that carry a source
+    std::vector<int64_t> srow(h->pieces.size(), -1);
+    int64_t rows = 0;
+    for (size_t k = 0; k < h->src.rpiece.size(); ++k) {
+      const int32_t p = h->src.rpiece[k];
+      if (srow[p] < 0) { srow[p] = rows; rows += h->pieces[p].b; }
+    }
+    std::vector<double> dense((size_t)std::max<int64_t>(rows, 1) * ns, 0.0);
+    for (int j = 0; j < ns; ++j)
+      for (int64_t k = h->src.rptr[j]; k < h->src.rptr[j + 1]; ++k) {
+        const int32_t p = h->src.rpiece[k];
+        for (int l = 0; l < h->pieces[p].b; ++l) dense[(srow[p] + l) * ns + j] += h->src.rcoef[h->src.rcoff[k] + l];
+      }
+    dfree(h->d_src);
+    if (h->prec == SFROM_F64) {
+      h->d_src = dupload(h, dense);
+    } else {
+      std::vector<float> f(dense.begin(), dense.end());
+      h->d_src = dupload(h, f);
+    }
+    for (size_t p = 0; p < h->pieces.size(); ++p) h->opieces[p].src_off = srow[p];
+    HIPCHK(hipMemcpy(h->d_opieces, h->opieces.data(), h->opieces.size() * sizeof(OnlinePiece), hipMemcpyHostToDevice));
+    h->src_dirty = false;
+  }
+  if (h->rec_dirty) {
+    std::vector<int64_t> rptr(1, 0), rrow;
+    std::vector<double> rval;
+    for (int r = 0; r < h->rec.count; ++r) {
+      for (int64_t k = h->rec.rptr[r]; k < h->rec.rptr[r + 1]; ++k) {
+        const int32_t p = h->rec.rpiece[k];
+        for (int l = 0; l < h->pieces[p].b; ++l) {
+          rrow.push_back(h->piece_dof_off[p] + l);
+          rval.push_back(h->rec.rcoef[h->rec.rcoff[k] + l]);
+        }
+      }
+      rptr.push_back((int64_t)rrow.size());
+    }
+    dfree(h->d_rptr); dfree(h->d_rrow); dfree(h->d_rval);
+    h->d_rptr = dupload(h, rptr);
+    h->d_rrow = dupload(h, rrow);
+    h->d_rval = dupload(h, rval);
+    h->rec_dirty = false;
+  }
+  if (h->state_ns != ns) {
+    const int64_t npd = h->piece_dof_off.back();
+    int64_t nu1 = 0;
+    for (auto& oc : h->ocells) nu1 += oc.b;
+    for (int k = 0; k < 2; ++k) {
+      dfree(h->d_y[k]); dfree(h->d_h[k]);
+      h->d_y[k] = dalloc<unsigned char>(h, (size_t)npd * ns * eb);
+      h->d_h[k] = dalloc<unsigned char>(h, (size_t)std::max<int64_t>(h->n_hidden_dofs, 1) * ns * eb);
+    }
+    dfree(h->d_phi);
+    h->d_phi = dalloc<unsigned char>(h, (size_t)nu1 * ns * eb);
+    h->state_ns = ns;
+    for (int k = 0; k < 2; ++k) {
+      HIPCHK(hipMemsetAsync(h->d_y[k], 0, (size_t)npd * ns * eb, h->stream));
+      HIPCHK(hipMemsetAsync(h->d_h[k], 0, (size_t)std::max<int64_t>(h->n_hidden_dofs, 1) * ns * eb, h->stream));
+    }
+    h->cur = 0;
+  }
+}
+
+const double* stage_w(sfrom_t* h, int64_t n_steps, const double* w, int w_on_device) {
+  if (w_on_device) return w;
+  if (h->d_w_cap < n_steps) {
+    dfree(h->d_w);
+    h->d_w = dalloc<double>(h, n_steps);
+    h->d_w_cap = n_steps;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_w, w, n_steps * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  return h->d_w;
+}
+
+void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_device, void* traces, int traces_on_device) {
+  REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
+  REQUIRE(h->built, SFROM_ESTATE, "no ROM: call sfrom_build first");
+  REQUIRE(n_steps >= 0, SFROM_EINVAL, "n_steps < 0");
+  REQUIRE(dt > 0.0 && std::isfinite(dt), SFROM_EINVAL, "dt must be positive");
+  REQUIRE(w != nullptr || n_steps == 0, SFROM_EINVAL, "null wavelet");
+  update_masses(h);
+  prepare_online(h);
+  const int ns = h->src.count, nr = h->rec.count;
+  const size_t eb = prec_bytes(h->prec);
+  const size_t tbytes = (size_t)n_steps * nr * ns * eb;
+  void* d_tr = traces;
+  bool own = false;
+  if (!traces_on_device && tbytes > 0) { d_tr = dalloc<unsigned char>(h, tbytes); own = true; }
+  const double* d_w = stage_w(h, n_steps, w, w_on_device);
+  StepArgs a;
+  a.ncell = (int32_t)h->ocells.size();
+  a.npiece = (int32_t)h->opieces.size();
+  a.ns = ns; a.nrec = nr; a.prec = h->prec;
+  a.max_b = 0; a.max_m = 0;
+  for (auto& oc : h->ocells) { a.max_b = std::max(a.max_b, oc.b); a.max_m = std::max(a.max_m, oc.m); }
+  a.dt2 = dt * dt;
+  a.d_cells = h->d_ocells; a.d_pieces = h->d_opieces; a.d_gather = h->d_gather; a.d_inc = h->d_inc;
+  a.d_blocks = h->d_blocks; a.d_minv = h->d_minv; a.d_src = h->d_src;
+  a.phi = h->d_phi; a.w = d_w;
+  a.d_rptr = h->d_rptr; a.d_rrow = h->d_rrow; a.d_rval = h->d_rval;
+  a.traces = d_tr;
+  for (int64_t s = 0; s < n_steps; ++s) {
+    a.y_cur = h->d_y[h->cur]; a.y_old = h->d_y[1 - h->cur];
+    a.h_cur = h->d_h[h->cur]; a.h_old = h->d_h[1 - h->cur];
+    a.step = s; a.trace_step = s;
+    HIPCHK(launch_online_step(a, h->stream));
+    h->cur = 1 - h->cur;
+  }
+  if (own) {
+    HIPCHK(hipMemcpyAsync(traces, d_tr, tbytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    dfree(d_tr);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fine-grid comparator
+// ---------------------------------------------------------------------------
+
+void prepare_fine(sfrom_t* h, int prec) {
+  REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
+  REQUIRE(h->n > 0, SFROM_ESTATE, "no pencil");
+  REQUIRE(prec == SFROM_F64 || prec == SFROM_F32, SFROM_EINVAL, "fine-grid precision must be F64 or F32");
+  const int ns = h->src.count;
+  REQUIRE(ns > 0, SFROM_ESTATE, "no sources: call sfrom_set_sources");
+  const size_t eb = prec_bytes(prec);
+  if (h->fine_prec != prec) {
+    dfree(h->d_frowptr); dfree(h->d_fcol); dfree(h->d_fa); dfree(h->d_fbinv);
+    h->d_frowptr = dupload(h, h->rowptr);
+    h->d_fcol = dupload(h, h->col);
+    std::vector<double> binv(h->n);
+    for (int64_t i = 0; i < h->n; ++i) binv[i] = 1.0 / h->b[i];
+    if (prec == SFROM_F64) {
+      h->d_fa = dupload(h, h->a);
+      h->d_fbinv = dupload(h, binv);
+    } else {
+      std::vector<float> af(h->a.begin(), h->a.end()), bf(binv.begin(), binv.end());
+      h->d_fa = dupload(h, af);
+      h->d_fbinv = dupload(h, bf);
+    }
+    h->fine_prec = prec;
+    h->fine_ns = -1;
+  }
+  if (h->fine_io_dirty) {
+    std::vector<int64_t> srow;
+    std::vector<int32_t> scol;
+    std::vector<double> sval;
+    for (int j = 0; j < ns; ++j)
+      for (int64_t k = h->src.colptr[j]; k < h->src.colptr[j + 1]; ++k) {
+        srow.push_back(h->src.row[k]); scol.push_back(j); sval.push_back(h->src.val[k]);
+      }
+    dfree(h->d_fsrc_row); dfree(h->d_fsrc_col); dfree(h->d_fsrc_val);
+    h->d_fsrc_row = dupload(h, srow);
+    h->d_fsrc_col = dupload(h, scol);
+    h->d_fsrc_val = dupload(h, sval);
+    h->fsrc_n = (int64_t)srow.size();
+    dfree(h->d_frec_ptr); dfree(h->d_frec_row); dfree(h->d_frec_val);
+    h->d_frec_ptr = dupload(h, h->rec.colptr.empty() ? std::vector<int64_t>(1, 0) : h->rec.colptr);
+    h->d_frec_row = dupload(h, h->rec.row);
+    h->d_frec_val = dupload(h, h->rec.val);
+    h->fine_io_dirty = false;
+  }
+  if (h->fine_ns != ns) {
+    for (int k = 0; k < 2; ++k) {
+      dfree(h->d_u[k]);
+      h->d_u[k] = dalloc<unsigned char>(h, (size_t)h->n * ns * eb);
+      HIPCHK(hipMemsetAsync(h->d_u[k], 0, (size_t)h->n * ns * eb, h->stream));
+    }
+    h->fine_ns = ns;
+    h->fcur = 0;
+  }
+}
+
+void fine_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_device, void* traces,
+              int traces_on_device, int prec) {
+  REQUIRE(n_steps >= 0, SFROM_EINVAL, "n_steps < 0");
+  REQUIRE(dt > 0.0 && std::isfinite(dt), SFROM_EINVAL, "dt must be positive");
+  prepare_fine(h, prec);
+  const int ns = h->src.count, nr = h->rec.count;
+  const size_t eb = prec_bytes(prec);
+  const size_t tbytes = (size_t)n_steps * nr * ns * eb;
+  void* d_tr = traces;
+  bool own = false;
+  if (!traces_on_device && tbytes > 0) { d_tr = dalloc<unsigned char>(h, tbytes); own = true; }
+  const double* d_w = stage_w(h, n_steps, w, w_on_device);
+  FineArgs a;
+  a.n = h->n; a.ns = ns; a.nrec = nr; a.prec = prec; a.dt2 = dt * dt;
+  a.rowptr = h->d_frowptr; a.col = h->d_fcol; a.a = h->d_fa; a.binv = h->d_fbinv;
+  a.w = d_w;
+  a.nsrc_entries = h->fsrc_n; a.src_row = h->d_fsrc_row; a.src_col = h->d_fsrc_col; a.src_val = h->d_fsrc_val;
+  a.rec_ptr = h->d_frec_ptr; a.rec_row = h->d_frec_row; a.rec_val = h->d_frec_val;
+  a.traces = d_tr;
+  for (int64_t s = 0; s < n_steps; ++s) {
+    a.u_cur = h->d_u[h->fcur]; a.u_old = h->d_u[1 - h->fcur];
+    a.step = s; a.trace_step = s;
+    HIPCHK(launch_fine_step(a, h->stream));
+    h->fcur = 1 - h->fcur;
+  }
+  if (own) {
+    HIPCHK(hipMemcpyAsync(traces, d_tr, tbytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    dfree(d_tr);
+  }
+}
+
+// Largest eigenvalue of a symmetric operator by Lanczos (no reorthogonalisation:
+// the extreme Ritz value converges first and ghost copies do not move it).
+template <typename MV>
+double lanczos_max(int64_t n, MV matvec, int maxit = 300) {
+  std::vector<double> v(n), vp(n, 0.0), wv(n);
+  // deterministic start vector
+  uint64_t s = 0x9E3779B97F4A7C15ull;
+  double nrm = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+    v[i] = (double)(s >> 11) / 9007199254740992.0 - 0.5;
+    nrm += v[i] * v[i];
+  }
+  nrm = std::sqrt(nrm);
+  for (auto& x : v) x /= nrm;
+  std::vector<double> al, be;
+  double beta = 0.0, prev = 0.0, lam = 0.0;
+  for (int it = 0; it < maxit && it < n; ++it) {
+    matvec(v.data(), wv.data());
+    double alpha = 0.0;
+    for (int64_t i = 0; i < n; ++i) alpha += wv[i] * v[i];
+    for (int64_t i = 0; i < n; ++i) wv[i] -= alpha * v[i] + beta * vp[i];
+    double bn = 0.0;
+    for (int64_t i = 0; i < n; ++i) bn += wv[i] * wv[i];
+    bn = std::sqrt(bn);
+    al.push_back(alpha);
+    // largest eigenvalue of the tridiagonal (al, be) by bisection on the
+    // Sturm count of eigenvalues below x
+    const int k = (int)al.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < k; ++i) {
+      double r = 0.0;
+      if (i > 0) r += std::fabs(be[i - 1]);
+      if (i + 1 < k) r += std::fabs(be[i]);
+      lo = std::min(lo, al[i] - r);
+      hi = std::max(hi, al[i] + r);
+    }
+    for (int rep = 0; rep < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++rep) {
+      const double mid = 0.5 * (lo + hi);
+      int below = 0;
+      double d = 1.0;
+      for (int i = 0; i < k; ++i) {
+        d = al[i] - mid - (i > 0 ? be[i - 1] * be[i - 1] / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0.0) ++below;
+      }
+      if (below == k) hi = mid; else lo = mid;
+    }
+    lam = hi;
+    if (bn < 1e-14 * std::fabs(lam)) break;
+    if (it > 20 && std::fabs(lam - prev) <= 1e-13 * std::fabs(lam)) break;
+    prev = lam;
+    be.push_back(bn);
+    for (int64_t i = 0; i < n; ++i) { vp[i] = v[i]; v[i] = wv[i] / bn; }
+    beta = bn;
+  }
+  return lam;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+#define API_BEGIN(h)                                          \
+  if (!(h)) return SFROM_EINVAL;                              \
+  try {                                                       \
+    if ((h)->device >= 0) HIPCHK(hipSetDevice((h)->device));
+#define API_END(h)                                            \
+  }                                                           \
+  catch (const Fail& f) { return f.code; }                    \
+  catch (const std::bad_alloc&) {                             \
+    (h)->err = "host allocation failed";                      \
+    return SFROM_ENOMEM;                                      \
+  }                                                           \
+  catch (...) {                                               \
+    (h)->err = "unexpected exception";                        \
+    return SFROM_EINVAL;                                      \
+  }                                                           \
+  (h)->err.clear();                                           \
+  return SFROM_OK;
+
+extern "C" {
+
+int sfrom_create(sfrom_t** out, int device, void* hip_stream) {
+  if (!out) return SFROM_EINVAL;
+  *out = nullptr;
+  if (device == -1) {   // host-only handle: problem set-up and validation, no device work
+    sfrom_t* h = new (std::nothrow) sfrom_t();
+    if (!h) return SFROM_ENOMEM;
+    h->device = -1;
+    *out = h;
+    return SFROM_OK;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SFROM_EDEVICE;
+  sfrom_t* h = new (std::nothrow) sfrom_t();
+  if (!h) return SFROM_ENOMEM;
+  h->device = device;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess) { delete h; return SFROM_EDEVICE; }
+  *out = h;
+  return SFROM_OK;
+}
+
+void sfrom_destroy(sfrom_t* h) {
+  if (!h) return;
+  if (h->device < 0) { delete h; return; }
+  hipSetDevice(h->device);
+  if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
+  free_all(h);
+  delete h;
+}
+
+const char* sfrom_last_error(const sfrom_t* h) { return h ? h->err.c_str() : "null handle"; }
+
+int sfrom_set_pencil(sfrom_t* h, int64_t n, const int64_t* rowptr, const int32_t* col, const double* a,
+                     const double* b) {
+  API_BEGIN(h)
+  REQUIRE(n > 0 && rowptr && col && a && b, SFROM_EINVAL, "bad pencil arguments");
+  REQUIRE(n < ((int64_t)1 << 31), SFROM_EINVAL, "n must fit in int32 column indices");
+  REQUIRE(rowptr[0] == 0, SFROM_EINVAL, "rowptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i) REQUIRE(rowptr[i + 1] >= rowptr[i], SFROM_EINVAL, "rowptr not monotone");
+  const int64_t nnz = rowptr[n];
+  for (int64_t i = 0; i < n; ++i) {
+    REQUIRE(b[i] > 0.0, std::isfinite(b[i]) ? SFROM_EBPOS : SFROM_ENONFINITE, "B must be diagonal positive (Sec. 1)");
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      REQUIRE(col[k] >= 0 && col[k] < n, SFROM_EINVAL, "column index out of range");
+      REQUIRE(k == rowptr[i] || col[k] > col[k - 1], SFROM_EINVAL, "columns must be sorted and unique within a row");
+      REQUIRE(std::isfinite(a[k]), SFROM_ENONFINITE, "non-finite entry in A");
+    }
+  }
+  // symmetry: A = A^T
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      const int32_t j = col[k];
+      const int32_t* cb = col + rowptr[j];
+      const int32_t* ce = col + rowptr[j + 1];
+      const int32_t* it = std::lower_bound(cb, ce, (int32_t)i);
+      REQUIRE(it != ce && *it == i && a[it - col] == a[k], SFROM_ENOTSYM, "A is not symmetric");
+    }
+  free_all(h);
+  h->n = n;
+  h->rowptr.assign(rowptr, rowptr + n + 1);
+  h->col.assign(col, col + nnz);
+  h->a.assign(a, a + nnz);
+  h->b.assign(b, b + n);
+  h->cells.clear();
+  h->pieces.clear();
+  h->part_ready = false;
+  h->src = Columns();
+  h->rec = Columns();
+  API_END(h)
+}
+
+int sfrom_add_cell(sfrom_t* h, int32_t cell, int32_t n_i, const int64_t* global_node, const int32_t* rowptr_i,
+                   const int32_t* col_i, const double* a_i, const double* b_i) {
+  API_BEGIN(h)
+  REQUIRE(h->n > 0, SFROM_ESTATE, "no pencil");
+  REQUIRE(cell >= 0 && n_i > 0 && global_node && rowptr_i && col_i && a_i && b_i, SFROM_EINVAL, "bad cell arguments");
+  if ((int)h->cells.size() <= cell) h->cells.resize(cell + 1);
+  REQUIRE(!h->cells[cell].defined, SFROM_EINVAL, "cell " + std::to_string(cell) + " defined twice");
+  REQUIRE(rowptr_i[0] == 0, SFROM_EINVAL, "rowptr_i[0] must be 0");
+  CellDef c;
+  c.n = n_i;
+  c.gnode.assign(global_node, global_node + n_i);
+  std::vector<int64_t> sorted(c.gnode);
+  std::sort(sorted.begin(), sorted.end());
+  REQUIRE(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), SFROM_EINVAL, "repeated node in cell");
+  REQUIRE(sorted.front() >= 0 && sorted.back() < h->n, SFROM_EINVAL, "cell node out of range");
+  for (int r = 0; r < n_i; ++r) {
+    REQUIRE(rowptr_i[r + 1] >= rowptr_i[r], SFROM_EINVAL, "rowptr_i not monotone");
+    REQUIRE(b_i[r] > 0.0, std::isfinite(b_i[r]) ? SFROM_EBPOS : SFROM_ENONFINITE, "B_i must be positive (Sec. 2)");
+    for (int k = rowptr_i[r]; k < rowptr_i[r + 1]; ++k) {
+      REQUIRE(col_i[k] >= 0 && col_i[k] < n_i, SFROM_EINVAL, "local column out of range");
+      REQUIRE(k == rowptr_i[r] || col_i[k] > col_i[k - 1], SFROM_EINVAL, "local columns must be sorted and unique");
+      REQUIRE(std::isfinite(a_i[k]), SFROM_ENONFINITE, "non-finite entry in A_i");
+    }
+  }
+  const int nnz = rowptr_i[n_i];
+  for (int r = 0; r < n_i; ++r)
+    for (int k = rowptr_i[r]; k < rowptr_i[r + 1]; ++k) {
+      const int j = col_i[k];
+      const int32_t* cb = col_i + rowptr_i[j];
+      const int32_t* ce = col_i + rowptr_i[j + 1];
+      const int32_t* it = std::lower_bound(cb, ce, r);
+      REQUIRE(it != ce && *it == r && a_i[it - col_i] == a_i[k], SFROM_ENOTSYM, "A_i is not symmetric");
+    }
+  c.rowptr.assign(rowptr_i, rowptr_i + n_i + 1);
+  c.col.assign(col_i, col_i + nnz);
+  c.a.assign(a_i, a_i + nnz);
+  c.b.assign(b_i, b_i + n_i);
+  c.defined = true;
+  h->cells[cell] = std::move(c);
+  h->part_ready = false;
+  free_rom(h);
+  API_END(h)
+}
+
+int sfrom_add_piece(sfrom_t* h, int32_t piece, int32_t k_p, const int64_t* global_node, int32_t b_p,
+                    const double* S_p) {
+  API_BEGIN(h)
+  REQUIRE(h->n > 0, SFROM_ESTATE, "no pencil");
+  REQUIRE(piece >= 0 && k_p > 0 && b_p > 0 && b_p <= k_p && global_node && S_p, SFROM_EINVAL, "bad piece arguments");
+  if ((int)h->pieces.size() <= piece) h->pieces.resize(piece + 1);
+  REQUIRE(!h->pieces[piece].defined, SFROM_EINVAL, "piece " + std::to_string(piece) + " defined twice");
+  PieceDef p;
+  p.gnode.assign(global_node, global_node + k_p);
+  for (int64_t g : p.gnode) REQUIRE(g >= 0 && g < h->n, SFROM_EINVAL, "piece node out of range");
+  p.b = b_p;
+  p.S.assign(S_p, S_p + (int64_t)k_p * b_p);
+  for (int i = 0; i < b_p; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (int r = 0; r < k_p; ++r) s += S_p[r + (int64_t)i * k_p] * S_p[r + (int64_t)j * k_p];
+      REQUIRE(std::fabs(s - (i == j ? 1.0 : 0.0)) <= 1e-10, SFROM_EINVAL,
+              "piece " + std::to_string(piece) + ": basis is not orthonormal (S_p^T S_p = I)");
+    }
+  p.defined = true;
+  h->pieces[piece] = std::move(p);
+  h->part_ready = false;
+  free_rom(h);
+  API_END(h)
+}
+
+int sfrom_build(sfrom_t* h, const sfrom_build_opts* opts) {
+  API_BEGIN(h)
+  build(h, opts);
+  API_END(h)
+}
+
+int sfrom_import_rom(sfrom_t* h, int32_t cell, int32_t m, int32_t b, const double* Ghat, const double* G) {
+  API_BEGIN(h)
+  REQUIRE(h->built, SFROM_ESTATE, "no ROM to modify: build first");
+  REQUIRE(cell >= 0 && cell < (int)h->ocells.size() && Ghat && G, SFROM_EINVAL, "bad cell");
+  const OnlineCell& oc = h->ocells[cell];
+  REQUIRE(m == oc.m && b == oc.b, SFROM_EINVAL, "m and b must match the built layout of the cell");
+  const int64_t bb2 = (int64_t)b * b;
+  std::vector<double> r64(2 * m * bb2);
+  for (int64_t k = 0; k < m * bb2; ++k) {
+    REQUIRE(std::isfinite(Ghat[k]) && std::isfinite(G[k]), SFROM_ENONFINITE, "non-finite block");
+    r64[k] = Ghat[k];
+    r64[m * bb2 + k] = G[k];
+  }
+  for (int k = 0; k < m; ++k)
+    for (int i = 0; i < b; ++i)
+      for (int j = 0; j < i; ++j) {
+        const int64_t u = k * bb2 + i + (int64_t)j * b, v = k * bb2 + j + (int64_t)i * b;
+        REQUIRE(Ghat[u] == Ghat[v] && G[u] == G[v], SFROM_ENOTSPD, "blocks must be symmetric");
+      }
+  HIPCHK(hipMemcpy(h->d_rom64 + h->rom64_off[cell], r64.data(), r64.size() * sizeof(double), hipMemcpyHostToDevice));
+  // on-line layout: G^1..G^m, Ghat^2..Ghat^m
+  std::vector<double> blk((2 * m - 1) * bb2);
+  for (int64_t k = 0; k < m * bb2; ++k) blk[k] = G[k];
+  for (int64_t k = 0; k < (m - 1) * bb2; ++k) blk[m * bb2 + k] = Ghat[bb2 + k];
+  const size_t eb = block_bytes(h->prec);
+  unsigned char* dst = reinterpret_cast<unsigned char*>(h->d_blocks) + (size_t)oc.blk_off * eb;
+  if (h->prec == SFROM_F64) {
+    HIPCHK(hipMemcpy(dst, blk.data(), blk.size() * 8, hipMemcpyHostToDevice));
+  } else if (h->prec == SFROM_F32) {
+    std::vector<float> f(blk.begin(), blk.end());
+    HIPCHK(hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    std::vector<uint16_t> bf(blk.size());
+    for (size_t k = 0; k < blk.size(); ++k) {
+      float f = (float)blk[k];
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      u += 0x7FFF + ((u >> 16) & 1);   // round to nearest even
+      bf[k] = (uint16_t)(u >> 16);
+    }
+    HIPCHK(hipMemcpy(dst, bf.data(), bf.size() * 2, hipMemcpyHostToDevice));
+  }
+  h->masses_dirty = true;
+  API_END(h)
+}
+
+int sfrom_export_rom(sfrom_t* h, int32_t cell, int32_t* m, int32_t* b, double* Ghat, double* G) {
+  API_BEGIN(h)
+  REQUIRE(h->built, SFROM_ESTATE, "no ROM: build first");
+  REQUIRE(cell >= 0 && cell < (int)h->ocells.size() && m && b, SFROM_EINVAL, "bad cell");
+  const OnlineCell& oc = h->ocells[cell];
+  *m = oc.m;
+  *b = oc.b;
+  const int64_t bb2 = (int64_t)oc.b * oc.b;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (Ghat) HIPCHK(hipMemcpy(Ghat, h->d_rom64 + h->rom64_off[cell], oc.m * bb2 * 8, hipMemcpyDeviceToHost));
+  if (G) HIPCHK(hipMemcpy(G, h->d_rom64 + h->rom64_off[cell] + oc.m * bb2, oc.m * bb2 * 8, hipMemcpyDeviceToHost));
+  API_END(h)
+}
+
+int sfrom_set_sources(sfrom_t* h, int32_t n_s, const int64_t* colptr, const int64_t* row, const double* val,
+                      int32_t project) {
+  API_BEGIN(h)
+  REQUIRE(n_s > 0 && colptr && (colptr[n_s] == 0 || (row && val)), SFROM_EINVAL, "bad source arguments");
+  finalize_partition(h);
+  make_columns(h, h->src, n_s, colptr, row, val, project);
+  h->src_dirty = true;
+  h->fine_io_dirty = true;
+  h->state_ns = -1;
+  h->fine_ns = -1;
+  API_END(h)
+}
+
+int sfrom_set_receivers(sfrom_t* h, int32_t n_r, const int64_t* colptr, const int64_t* row, const double* val,
+                        int32_t project) {
+  API_BEGIN(h)
+  REQUIRE(n_r >= 0 && colptr && (colptr[n_r] == 0 || (row && val)), SFROM_EINVAL, "bad receiver arguments");
+  finalize_partition(h);
+  make_columns(h, h->rec, n_r, colptr, row, val, project);
+  h->rec_dirty = true;
+  h->fine_io_dirty = true;
+  API_END(h)
+}
+
+int sfrom_point_columns(sfrom_t* h, int32_t count, const int64_t* node, int64_t* colptr_out, int64_t* row_out,
+                        double* val_out) {
+  API_BEGIN(h)
+  REQUIRE(count >= 0 && node && colptr_out && row_out && val_out, SFROM_EINVAL, "bad arguments");
+  finalize_partition(h);
+  std::vector<int64_t> cp(count + 1, 0), rw;
+  std::vector<double> vl;
+  for (int j = 0; j < count; ++j) {
+    const int64_t g = node[j];
+    REQUIRE(g >= 0 && g < h->n, SFROM_EINVAL, "node out of range");
+    const int32_t p = h->piece_of_node[g];
+    REQUIRE(p >= 0, SFROM_ESUPPORT, "node " + std::to_string(g) + " is not on the skeleton (eq. gsupport)");
+    const auto& pc = h->pieces[p];
+    const int64_t kp = (int64_t)pc.gnode.size();
+    const int32_t pos = h->pos_in_piece[g];
+    for (int64_t r = 0; r < kp; ++r) {
+      double s = 0.0;
+      for (int l = 0; l < pc.b; ++l) s += pc.S[r + l * kp] * pc.S[pos + l * kp];
+      rw.push_back(pc.gnode[r]);
+      vl.push_back(s);
+    }
+    cp[j + 1] = (int64_t)rw.size();
+  }
+  std::memcpy(colptr_out, cp.data(), cp.size() * 8);
+  if (!rw.empty()) {
+    std::memcpy(row_out, rw.data(), rw.size() * 8);
+    std::memcpy(val_out, vl.data(), vl.size() * 8);
+  }
+  API_END(h)
+}
+
+int sfrom_reset(sfrom_t* h) {
+  API_BEGIN(h)
+  REQUIRE(h->built, SFROM_ESTATE, "no ROM: build first");
+  h->state_ns = -1;   // reallocated and zeroed at the next run
+  API_END(h)
+}
+
+int sfrom_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int32_t w_on_device, void* traces,
+              int32_t traces_on_device) {
+  API_BEGIN(h)
+  run(h, n_steps, dt, w, w_on_device, traces, traces_on_device);
+  API_END(h)
+}
+
+int sfrom_fine_reset(sfrom_t* h) {
+  API_BEGIN(h)
+  h->fine_ns = -1;
+  API_END(h)
+}
+
+int sfrom_fine_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int32_t w_on_device, void* traces,
+                   int32_t traces_on_device, int32_t prec) {
+  API_BEGIN(h)
+  fine_run(h, n_steps, dt, w, w_on_device, traces, traces_on_device, prec);
+  API_END(h)
+}
+
+int sfrom_fine_lambda_max(sfrom_t* h, double* lambda) {
+  API_BEGIN(h)
+  REQUIRE(h->n > 0 && lambda, SFROM_ESTATE, "no pencil");
+  const int64_t n = h->n;
+  std::vector<double> d(n);
+  for (int64_t i = 0; i < n; ++i) d[i] = 1.0 / std::sqrt(h->b[i]);
+  auto mv = [&](const double* x, double* y) {
+    for (int64_t i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int64_t k = h->rowptr[i]; k < h->rowptr[i + 1]; ++k) acc += h->a[k] * d[h->col[k]] * x[h->col[k]];
+      y[i] = -d[i] * acc;
+    }
+  };
+  *lambda = lanczos_max(n, mv);
+  API_END(h)
+}
+
+int sfrom_rom_lambda_max(sfrom_t* h, double* lambda) {
+  API_BEGIN(h)
+  REQUIRE(h->built && lambda, SFROM_ESTATE, "no ROM: build first");
+  const int nc = (int)h->ocells.size();
+  // host copy of the double blocks; operator D^{-1/2}(-L)D^{-1/2} applied in
+  // cell-blocked flux form with D = blkdiag(M_p, (Ghat_i^k)^{-1}).
+  std::vector<double> r64;
+  int64_t tot = 0;
+  for (int i = 0; i < nc; ++i) tot += 2LL * h->ocells[i].m * h->ocells[i].b * h->ocells[i].b;
+  r64.resize(tot);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(r64.data(), h->d_rom64, tot * 8, hipMemcpyDeviceToHost));
+  const int64_t npd = h->piece_dof_off.back();
+  const int64_t ndof = npd + h->n_hidden_dofs;
+  // symmetric square roots of the mass blocks: piece masses M_p and hidden (Ghat^k)^{-1}
+  auto symsqrt = [](int n, const double* A, double* out, bool inverse) {
+    // Jacobi eigen-decomposition (small n)
+    std::vector<double> a(A, A + n * n), v(n * n, 0.0);
+    for (int i = 0; i < n; ++i) v[i + i * n] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+      double off = 0.0;
+      for (int p = 0; p < n; ++p) for (int q = p + 1; q < n; ++q) off += a[p + q * n] * a[p + q * n];
+      if (off < 1e-30) break;
+      for (int p = 0; p < n; ++p)
+        for (int q = p + 1; q < n; ++q) {
+          const double apq = a[p + q * n];
+          if (std::fabs(apq) < 1e-300) continue;
+          const double th = 0.5 * (a[q + q * n] - a[p + p * n]) / apq;
+          const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+          const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+          for (int k = 0; k < n; ++k) {
+            const double akp = a[k + p * n], akq = a[k + q * n];
+            a[k + p * n] = c * akp - s * akq; a[k + q * n] = s * akp + c * akq;
+          }
+          for (int k = 0; k < n; ++k) {
+            const double apk = a[p + k * n], aqk = a[q + k * n];
+            a[p + k * n] = c * apk - s * aqk; a[q + k * n] = s * apk + c * aqk;
+          }
+          for (int k = 0; k < n; ++k) {
+            const double vkp = v[k + p * n], vkq = v[k + q * n];
+            v[k + p * n] = c * vkp - s * vkq; v[k + q * n] = s * vkp + c * vkq;
+          }
+        }
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double ev = std::max(a[k + k * n], 1e-300);
+          s += v[i + k * n] * v[j + k * n] * (inverse ? 1.0 / std::sqrt(ev) : std::sqrt(ev));
+        }
+        out[i + j * n] = s;
+      }
+  };
+  // piece masses M_p = sum_c ([Ghat_c^1]_pp)^{-1}  -> M_p^{-1/2}
+  std::vector<std::vector<double>> pm(h->pieces.size());
+  for (size_t p = 0; p < h->pieces.size(); ++p) {
+    const int bp = h->pieces[p].b;
+    std::vector<double> M(bp * bp, 0.0);
+    for (int32_t c : h->piece_cells[p]) {
+      const auto& cp = h->cell_pieces[c];
+      const size_t q = std::lower_bound(cp.begin(), cp.end(), (int32_t)p) - cp.begin();
+      const int col0 = h->cell_piece_col[c][q], b = h->ocells[c].b;
+      const double* G1 = r64.data() + h->rom64_off[c];
+      std::vector<double> blk(bp * bp), inv(bp * bp), tmp(bp * bp);
+      for (int j = 0; j < bp; ++j) for (int i = 0; i < bp; ++i) blk[i + j * bp] = G1[(col0 + i) + (int64_t)(col0 + j) * b];
+      // inverse via inverse square root squared
+      symsqrt(bp, blk.data(), tmp.data(), true);
+      for (int i = 0; i < bp; ++i) for (int j = 0; j < bp; ++j) {
+        double s = 0.0; for (int k = 0; k < bp; ++k) s += tmp[i + k * bp] * tmp[k + j * bp];
+        M[i + j * bp] += s;
+      }
+    }
+    pm[p].resize(bp * bp);
+    symsqrt(bp, M.data(), pm[p].data(), true);
+  }
+  // hidden mass (Ghat^k)^{-1} -> its inverse square root is Ghat^{1/2}
+  std::vector<std::vector<double>> hsq(nc);
+  for (int i = 0; i < nc; ++i) {
+    const int m = h->ocells[i].m, b = h->ocells[i].b;
+    hsq[i].resize((size_t)std::max(m - 1, 0) * b * b);
+    for (int k = 1; k < m; ++k) symsqrt(b, r64.data() + h->rom64_off[i] + (int64_t)k * b * b, hsq[i].data() + (int64_t)(k - 1) * b * b, false);
+  }
+  auto apply_msq = [&](const double* x, double* y) {   // y = D^{-1/2} x
+    for (size_t p = 0; p < h->pieces.size(); ++p) {
+      const int bp = h->pieces[p].b; const int64_t o = h->piece_dof_off[p];
+      for (int i = 0; i < bp; ++i) { double s = 0.0; for (int j = 0; j < bp; ++j) s += pm[p][i + j * bp] * x[o + j]; y[o + i] = s; }
+    }
+    for (int i = 0; i < nc; ++i) {
+      const int m = h->ocells[i].m, b = h->ocells[i].b;
+      for (int k = 1; k < m; ++k) {
+        const int64_t o = npd + h->ocells[i].hid_off + (int64_t)(k - 1) * b;
+        const double* S = hsq[i].data() + (int64_t)(k - 1) * b * b;
+        for (int r = 0; r < b; ++r) { double s = 0.0; for (int c = 0; c < b; ++c) s += S[r + c * b] * x[o + c]; y[o + r] = s; }
+      }
+    }
+  };
+  std::vector<double> t1(ndof), t2(ndof);
+  auto mv = [&](const double* x, double* y) {
+    apply_msq(x, t1.data());
+    std::fill(t2.begin(), t2.end(), 0.0);
+    for (int i = 0; i < nc; ++i) {
+      const int m = h->ocells[i].m, b = h->ocells[i].b;
+      const double* G = r64.data() + h->rom64_off[i] + (int64_t)m * b * b;
+      std::vector<int64_t> rows((size_t)m * b);
+      int r0 = 0;
+      for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) {
+        const int32_t p = h->cell_pieces[i][q];
+        for (int l = 0; l < h->pieces[p].b; ++l) rows[r0++] = h->piece_dof_off[p] + l;
+      }
+      for (int k = 1; k < m; ++k) for (int r = 0; r < b; ++r) rows[(size_t)k * b + r] = npd + h->ocells[i].hid_off + (int64_t)(k - 1) * b + r;
+      // (-L U)^k = -(Phi^k - Phi^{k-1}), Phi^k = G^k (U^{k+1} - U^k)
+      std::vector<double> phi((size_t)m * b);
+      for (int k = 0; k < m; ++k)
+        for (int r = 0; r < b; ++r) {
+          double s = 0.0;
+          for (int c = 0; c < b; ++c) {
+            const double up = (k + 1 < m) ? t1[rows[(size_t)(k + 1) * b + c]] : 0.0;
+            s += G[(int64_t)k * b * b + r + (int64_t)c * b] * (up - t1[rows[(size_t)k * b + c]]);
+          }
+          phi[(size_t)k * b + r] = s;
+        }
+      for (int k = 0; k < m; ++k)
+        for (int r = 0; r < b; ++r) t2[rows[(size_t)k * b + r]] -= phi[(size_t)k * b + r] - (k > 0 ? phi[(size_t)(k - 1) * b + r] : 0.0);
+    }
+    apply_msq(t2.data(), y);
+  };
+  *lambda = lanczos_max(ndof, mv);
+  API_END(h)
+}
+
+int sfrom_get_info(const sfrom_t* hc, sfrom_info* info) {
+  if (!hc || !info) return SFROM_EINVAL;
+  sfrom_t* h = const_cast<sfrom_t*>(hc);
+  std::memset(info, 0, sizeof(*info));
+  info->n = h->n;
+  info->nnz = h->rowptr.empty() ? 0 : h->rowptr.back();
+  info->n_cells = (int32_t)h->cells.size();
+  info->n_pieces = (int32_t)h->pieces.size();
+  info->n_piece_dofs = h->piece_dof_off.empty() ? 0 : h->piece_dof_off.back();
+  info->n_hidden_dofs = h->built ? h->n_hidden_dofs : 0;
+  for (int32_t b : h->cell_b) info->max_b = std::max(info->max_b, b);
+  for (int32_t m : h->cell_m) info->max_m = std::max(info->max_m, m);
+  info->n_sources = h->src.count;
+  info->n_receivers = h->rec.count;
+  info->built = h->built ? 1 : 0;
+  info->online_prec = h->prec;
+  info->block_bytes = h->built ? h->block_elems * (int64_t)block_bytes(h->prec) : 0;
+  info->build_ms = h->build_ms;
+  return SFROM_OK;
+}
+
+int sfrom_export_pencil(sfrom_t* h, int64_t* rowptr, int32_t* col, double* a, double* b) {
+  API_BEGIN(h)
+  REQUIRE(h->n > 0, SFROM_ESTATE, "no pencil");
+  if (rowptr) std::memcpy(rowptr, h->rowptr.data(), h->rowptr.size() * 8);
+  if (col) std::memcpy(col, h->col.data(), h->col.size() * 4);
+  if (a) std::memcpy(a, h->a.data(), h->a.size() * 8);
+  if (b) std::memcpy(b, h->b.data(), h->b.size() * 8);
+  API_END(h)
+}
+
+int sfrom_export_cell(sfrom_t* h, int32_t cell, int32_t* n_i, int32_t* nnz_i, int32_t* b_dim, int64_t* global_node,
+                      int32_t* rowptr_i, int32_t* col_i, double* a_i, double* b_i) {
+  API_BEGIN(h)
+  REQUIRE(cell >= 0 && cell < (int)h->cells.size() && h->cells[cell].defined, SFROM_EINVAL, "bad cell");
+  finalize_partition(h);
+  const CellDef& c = h->cells[cell];
+  if (n_i) *n_i = c.n;
+  if (nnz_i) *nnz_i = (int32_t)c.a.size();
+  if (b_dim) *b_dim = h->cell_b[cell];
+  if (global_node) std::memcpy(global_node, c.gnode.data(), c.gnode.size() * 8);
+  if (rowptr_i) std::memcpy(rowptr_i, c.rowptr.data(), c.rowptr.size() * 4);
+  if (col_i) std::memcpy(col_i, c.col.data(), c.col.size() * 4);
+  if (a_i) std::memcpy(a_i, c.a.data(), c.a.size() * 8);
+  if (b_i) std::memcpy(b_i, c.b.data(), c.b.size() * 8);
+  API_END(h)
+}
+
+int sfrom_export_piece(sfrom_t* h, int32_t piece, int32_t* k_p, int32_t* b_p, int64_t* global_node, double* S_p) {
+  API_BEGIN(h)
+  REQUIRE(piece >= 0 && piece < (int)h->pieces.size() && h->pieces[piece].defined, SFROM_EINVAL, "bad piece");
+  const PieceDef& p = h->pieces[piece];
+  if (k_p) *k_p = (int32_t)p.gnode.size();
+  if (b_p) *b_p = p.b;
+  if (global_node) std::memcpy(global_node, p.gnode.data(), p.gnode.size() * 8);
+  if (S_p) std::memcpy(S_p, p.S.data(), p.S.size() * 8);
+  API_END(h)
+}
+
+}  // extern "C"

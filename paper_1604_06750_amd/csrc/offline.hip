@@ -1,0 +1,690 @@
+// Off-line stage on the GPU (Alg. alg1red stage 1), double precision.
+//
+// Every kernel runs one 256-thread workgroup per coarse cell of the batch;
+// cells are independent (Sec. 4.2: no data exchange between cells), so the
+// batch is the unit of parallelism. Per cell, with C = -(A_i + s B_i) (SPD):
+//
+//   K1  banded Cholesky C = L L^T (lexicographic local order, bandwidth w)
+//   K2  rational block Krylov (eq. npks): X_1 = B^{-1} W; for each block,
+//       B-weighted classical Gram-Schmidt against all previous blocks,
+//       applied twice; R^T R = X^T B X (Cholesky; a tiny pivot ratio means
+//       the block lost rank, Assumption 1); q_j = X R^{-1};
+//       X_{j+1} = (A + sB)^{-1} B q_j = -C^{-1} B q_j (two band solves)
+//   K3  projection A^m = V^T A V (eq. tfprj); B^m = I because V is
+//       B-orthonormal, and S^m = V^T W = [R_1; 0; ...] because X_1 = q_1 R_1
+//   K4  block Lanczos on (A^m, I) from S^m (App. C): Q_1 = E_1, beta_1 = R_1,
+//       Z = A^m Q_k - Q_k alpha_k - Q_{k-1} beta_k^T, reorthogonalised twice,
+//       Q_{k+1} beta_{k+1} = Z by Cholesky-QR applied twice
+//   K5  S-fraction (eq. GammaTrans with G_1 = beta_1^T,
+//       G^k = -G_k^{-T} alpha_k G_k^{-1} - G^{k-1},
+//       G_{k+1} = (G_k^T G^k)^{-1} beta_{k+1}^T), SPD checks of the pivots.
+//
+// All dense matrices are column-major in a per-cell double workspace.
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cmath>
+
+#include "sfrom_internal.h"
+
+namespace sfrom_impl {
+
+#define NT 256
+
+enum {
+  ST_OK = 0,
+  ST_NOTNSD = 1,     // band Cholesky pivot <= 0
+  ST_BREAKDOWN = 2,  // Krylov / Lanczos rank loss
+  ST_NOTSPD = 3,     // S-fraction pivot not SPD
+  ST_NONFINITE = 4
+};
+
+// ---------------------------------------------------------------------------
+// workgroup-cooperative dense helpers
+// ---------------------------------------------------------------------------
+
+// C = alpha op(A) op(B) + beta C, M x N, inner K. op(A)(i,k) = TA ? A[k+i*lda]
+// : A[i+k*lda]; op(B)(k,j) = TB ? B[j+k*ldb] : B[k+j*ldb]. 64x64 output tiles,
+// 4x4 per thread, K staged through LDS in chunks of 16. C must not alias A, B.
+template <bool TA, bool TB>
+__device__ void wg_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
+                        const double* __restrict__ B, int ldb, double beta, double* C, int ldc) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      double acc[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+      for (int k0 = 0; k0 < K; k0 += 16) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + NT * q;
+          int ii, kk;
+          if (!TA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
+          const int i = i0 + ii, k = k0 + kk;
+          double v = 0.0;
+          if (i < M && k < K) v = TA ? A[k + (int64_t)i * lda] : A[i + (int64_t)k * lda];
+          As[kk][ii] = v;
+          int jj, kb;
+          if (!TB) { kb = e & 15; jj = e >> 4; } else { jj = e & 63; kb = e >> 6; }
+          const int j = j0 + jj, k2 = k0 + kb;
+          double u = 0.0;
+          if (j < N && k2 < K) u = TB ? B[j + (int64_t)k2 * ldb] : B[k2 + (int64_t)j * ldb];
+          Bs[kb][jj] = u;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+          double a[4], b[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a[r] = As[kk][tx + 16 * r];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) b[c] = Bs[kk][ty + 16 * c];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + tx + 16 * r;
+        if (i >= M) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = j0 + ty + 16 * c;
+          if (j >= N) continue;
+          double* p = C + i + (int64_t)j * ldc;
+          *p = (beta == 0.0) ? alpha * acc[r][c] : alpha * acc[r][c] + beta * (*p);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// In-place lower Cholesky of an n x n SPD matrix (global memory). Returns the
+// ratio min/max of the pivots' square roots, or -1 if a pivot is not
+// positive and finite.
+__device__ double wg_potrf(int n, double* A, int lda) {
+  __shared__ double s_piv;
+  __shared__ double s_min, s_max;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) { s_bad = 0; s_min = 1e300; s_max = 0.0; }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      const double d = A[j + (int64_t)j * lda];
+      if (!(d > 0.0) || !isfinite(d)) { s_bad = 1; s_piv = 1.0; }
+      else {
+        s_piv = sqrt(d);
+        s_min = fmin(s_min, s_piv);
+        s_max = fmax(s_max, s_piv);
+      }
+      A[j + (int64_t)j * lda] = s_piv;
+    }
+    __syncthreads();
+    const double inv = 1.0 / s_piv;
+    for (int i = j + 1 + tid; i < n; i += NT) A[i + (int64_t)j * lda] *= inv;
+    __syncthreads();
+    const int t = n - j - 1;
+    for (int idx = tid; idx < t * t; idx += NT) {
+      const int i = j + 1 + idx % t;
+      const int k = j + 1 + idx / t;
+      if (i >= k) A[i + (int64_t)k * lda] -= A[i + (int64_t)j * lda] * A[k + (int64_t)j * lda];
+    }
+    __syncthreads();
+  }
+  const double r = s_bad ? -1.0 : s_min / s_max;
+  __syncthreads();
+  return r;
+}
+
+// X (rows x n) <- X L^{-T} for lower L (n x n): solves q L^T = x row-wise.
+__device__ void wg_trsm_right_lt(int rows, int n, const double* L, int ldl, double* X, int ldx) {
+  for (int r = threadIdx.x; r < rows; r += NT) {
+    for (int j = 0; j < n; ++j) {
+      double s = X[r + (int64_t)j * ldx];
+      for (int l = 0; l < j; ++l) s -= X[r + (int64_t)l * ldx] * L[j + (int64_t)l * ldl];
+      X[r + (int64_t)j * ldx] = s / L[j + (int64_t)j * ldl];
+    }
+  }
+  __syncthreads();
+}
+
+// Ainv = A^{-1} (n x n) by Gauss-Jordan with partial pivoting; W is n x n
+// scratch (destroyed), fac is n doubles scratch. Returns 0 if singular.
+__device__ int wg_inverse(int n, const double* A, int lda, double* Ainv, int ldi, double* W,
+                          double* fac) {
+  __shared__ int s_p;
+  __shared__ int s_ok;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < n * n; idx += NT) {
+    const int i = idx % n, j = idx / n;
+    W[i + (int64_t)j * n] = A[i + (int64_t)j * lda];
+    Ainv[i + (int64_t)j * ldi] = (i == j) ? 1.0 : 0.0;
+  }
+  if (tid == 0) s_ok = 1;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      int p = j;
+      double best = fabs(W[j + (int64_t)j * n]);
+      for (int i = j + 1; i < n; ++i) {
+        const double v = fabs(W[i + (int64_t)j * n]);
+        if (v > best) { best = v; p = i; }
+      }
+      if (!(best > 0.0)) s_ok = 0;
+      s_p = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != j) {
+      for (int c = tid; c < n; c += NT) {
+        double t = W[j + (int64_t)c * n]; W[j + (int64_t)c * n] = W[p + (int64_t)c * n]; W[p + (int64_t)c * n] = t;
+        t = Ainv[j + (int64_t)c * ldi]; Ainv[j + (int64_t)c * ldi] = Ainv[p + (int64_t)c * ldi]; Ainv[p + (int64_t)c * ldi] = t;
+      }
+    }
+    __syncthreads();
+    const double piv = W[j + (int64_t)j * n];
+    const double ip = (piv != 0.0) ? 1.0 / piv : 0.0;
+    for (int c = tid; c < n; c += NT) {
+      W[j + (int64_t)c * n] *= ip;
+      Ainv[j + (int64_t)c * ldi] *= ip;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) fac[i] = (i == j) ? 0.0 : W[i + (int64_t)j * n];
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += NT) {
+      const int i = idx % n, c = idx / n;
+      const double f = fac[i];
+      if (f != 0.0) {
+        W[i + (int64_t)c * n] -= f * W[j + (int64_t)c * n];
+        Ainv[i + (int64_t)c * ldi] -= f * Ainv[j + (int64_t)c * ldi];
+      }
+    }
+    __syncthreads();
+  }
+  const int ok = s_ok;
+  __syncthreads();
+  return ok;
+}
+
+__device__ void wg_symmetrize(int n, double* A, int lda) {
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+    const int i = idx % n, j = idx / n;
+    if (i < j) {
+      const double v = 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]);
+      A[i + (int64_t)j * lda] = v;
+      A[j + (int64_t)i * lda] = v;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ void wg_copy(int rows, int cols, const double* A, int lda, double* B, int ldb) {
+  for (int idx = threadIdx.x; idx < rows * cols; idx += NT) {
+    const int i = idx % rows, j = idx / rows;
+    B[i + (int64_t)j * ldb] = A[i + (int64_t)j * lda];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+struct KArgs {
+  BuildBatch bb;
+};
+
+__device__ inline bool cell_failed(const BuildCell& c) { return c.status != ST_OK; }
+
+// K1: assemble the band of C = -(A_i + s B_i) and factor it.
+__global__ __launch_bounds__(NT) void k_band_chol(BuildBatch bb) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  const int n = c.n, w = c.w, ld = w + 1;
+  double* band = bb.d_work + c.band_off;
+  const int32_t* rp = bb.d_rowptr + c.rp_off;
+  const int32_t* col = bb.d_col + c.csr_off;
+  const double* a = bb.d_a + c.csr_off;
+  const double* bd = bb.d_bdiag + c.b_off;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * ld; idx += NT) band[idx] = 0.0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += NT) {
+    for (int k = rp[r]; k < rp[r + 1]; ++k) {
+      const int cc = col[k];
+      if (r >= cc) band[(int64_t)cc * ld + (r - cc)] = -(a[k] + (r == cc ? bb.shift * bd[r] : 0.0));
+    }
+  }
+  __syncthreads();
+  __shared__ double s_piv;
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double* cj = band + (int64_t)j * ld;
+    if (threadIdx.x == 0) {
+      const double d = cj[0];
+      if (!(d > 0.0) || !isfinite(d)) { s_bad = 1; s_piv = 1.0; } else s_piv = sqrt(d);
+      cj[0] = s_piv;
+    }
+    __syncthreads();
+    const int lim = min(w, n - 1 - j);
+    const double inv = 1.0 / s_piv;
+    for (int d = 1 + threadIdx.x; d <= lim; d += NT) cj[d] *= inv;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < lim * lim; idx += NT) {
+      const int d1 = idx / lim + 1, d2 = idx % lim + 1;
+      if (d2 >= d1) band[(int64_t)(j + d1) * ld + (d2 - d1)] -= cj[d2] * cj[d1];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && s_bad) c.status = ST_NOTNSD;
+}
+
+// K2 start: X = B^{-1} W (W = P^Gamma S_i, scattered from the piece bases).
+__global__ __launch_bounds__(NT) void k_krylov_start(BuildBatch bb) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c)) return;
+  const int n = c.n, b = c.b;
+  double* X = bb.d_work + c.x_off;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) X[idx] = 0.0;
+  __syncthreads();
+  const double* bd = bb.d_bdiag + c.b_off;
+  for (int k = threadIdx.x; k < c.nw; k += NT) {
+    const int64_t e = c.w_off + k;
+    const int row = bb.d_wrow[e], col0 = bb.d_wcol[e], bp = bb.d_wbp[e], kp = bb.d_wkp[e];
+    const double* s = bb.d_S + bb.d_wsoff[e];
+    const double ib = 1.0 / bd[row];
+    for (int l = 0; l < bp; ++l) X[row + (int64_t)(col0 + l) * n] = s[(int64_t)l * kp] * ib;
+  }
+}
+
+// B-weighted block classical Gram-Schmidt of X against V[:, 0:jb], twice.
+__global__ __launch_bounds__(NT) void k_cgs2(BuildBatch bb, int j) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c) || j >= c.m || j == 0) return;
+  const int n = c.n, b = c.b, jb = j * b;
+  double* X = bb.d_work + c.x_off;
+  double* V = bb.d_work + c.v_off;
+  double* BX = bb.d_work + c.av_off;            // n x b scratch
+  double* coef = bb.d_work + c.s_off;           // jb x b scratch
+  const double* bd = bb.d_bdiag + c.b_off;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) BX[idx] = bd[idx % n] * X[idx];
+    __syncthreads();
+    wg_gemm<true, false>(jb, b, n, 1.0, V, n, BX, n, 0.0, coef, jb);
+    wg_gemm<false, false>(n, b, jb, -1.0, V, n, coef, jb, 1.0, X, n);
+  }
+}
+
+// Normalise block j: R^T R = X^T B X, q_j = X R^{-1} -> V[:, j b : (j+1) b].
+__global__ __launch_bounds__(NT) void k_normalize(BuildBatch bb, int j) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c) || j >= c.m) return;
+  const int n = c.n, b = c.b;
+  double* X = bb.d_work + c.x_off;
+  double* V = bb.d_work + c.v_off;
+  double* BX = bb.d_work + c.av_off;
+  double* gram = bb.d_work + c.s_off;
+  const double* bd = bb.d_bdiag + c.b_off;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) BX[idx] = bd[idx % n] * X[idx];
+  __syncthreads();
+  wg_gemm<true, false>(b, b, n, 1.0, X, n, BX, n, 0.0, gram, b);
+  wg_symmetrize(b, gram, b);
+  const double ratio = wg_potrf(b, gram, b);          // gram <- L (lower)
+  if (!(ratio > 1e-10)) {
+    if (threadIdx.x == 0) c.status = (ratio < 0.0 && j == 0) ? ST_BREAKDOWN : ST_BREAKDOWN;
+    return;
+  }
+  // R_j = L^T (upper), kept for beta_1 = R_1
+  double* R = bb.d_work + c.r_off + (int64_t)j * b * b;
+  for (int idx = threadIdx.x; idx < b * b; idx += NT) {
+    const int r = idx % b, cc = idx / b;
+    R[r + (int64_t)cc * b] = (r <= cc) ? gram[cc + (int64_t)r * b] : 0.0;
+  }
+  double* q = V + (int64_t)j * b * n;
+  wg_copy(n, b, X, n, q, n);
+  wg_trsm_right_lt(n, b, gram, b, q, n);
+}
+
+// X = (A + sB)^{-1} B q_j = -C^{-1} (B q_j) with the banded factor.
+__global__ __launch_bounds__(NT) void k_shift_solve(BuildBatch bb, int j) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c) || j + 1 >= c.m) return;
+  const int n = c.n, b = c.b, w = c.w, ld = w + 1;
+  const double* band = bb.d_work + c.band_off;
+  double* X = bb.d_work + c.x_off;
+  const double* q = bb.d_work + c.v_off + (int64_t)j * b * n;
+  const double* bd = bb.d_bdiag + c.b_off;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) X[idx] = bd[idx % n] * q[idx];
+  __syncthreads();
+  // forward: L y = r
+  for (int r = 0; r < n; ++r) {
+    const double* cr = band + (int64_t)r * ld;
+    const double ip = 1.0 / cr[0];
+    for (int cc = threadIdx.x; cc < b; cc += NT) X[r + (int64_t)cc * n] *= ip;
+    __syncthreads();
+    const int lim = min(w, n - 1 - r);
+    for (int idx = threadIdx.x; idx < lim * b; idx += NT) {
+      const int d = idx % lim + 1, cc = idx / lim;
+      X[r + d + (int64_t)cc * n] -= cr[d] * X[r + (int64_t)cc * n];
+    }
+    __syncthreads();
+  }
+  // backward: L^T x = y
+  for (int r = n - 1; r >= 0; --r) {
+    const double ip = 1.0 / band[(int64_t)r * ld];
+    for (int cc = threadIdx.x; cc < b; cc += NT) X[r + (int64_t)cc * n] *= ip;
+    __syncthreads();
+    const int lim = min(w, r);
+    for (int idx = threadIdx.x; idx < lim * b; idx += NT) {
+      const int d = idx % lim + 1, cc = idx / lim;
+      X[r - d + (int64_t)cc * n] -= band[(int64_t)(r - d) * ld + d] * X[r + (int64_t)cc * n];
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) X[idx] = -X[idx];
+}
+
+// K3: A V (local CSR) then A^m = V^T (A V), symmetrised.
+__global__ __launch_bounds__(NT) void k_project(BuildBatch bb) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c)) return;
+  const int n = c.n, mb = c.m * c.b;
+  const double* V = bb.d_work + c.v_off;
+  double* AV = bb.d_work + c.av_off;
+  double* Am = bb.d_work + c.am_off;
+  const int32_t* rp = bb.d_rowptr + c.rp_off;
+  const int32_t* col = bb.d_col + c.csr_off;
+  const double* a = bb.d_a + c.csr_off;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * mb; idx += NT) {
+    const int r = idx % n;
+    const int64_t cc = idx / n;
+    double s = 0.0;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) s += a[k] * V[col[k] + cc * n];
+    AV[idx] = s;
+  }
+  __syncthreads();
+  wg_gemm<true, false>(mb, mb, n, 1.0, V, n, AV, n, 0.0, Am, mb);
+  wg_symmetrize(mb, Am, mb);
+}
+
+// K4: block Lanczos on (A^m, I) from S^m = E_1 R_1.
+// Work layout in the av region (free after K3): AQ (mb x b), Z (mb x b),
+// coef (mb x b), gram (b x b); alphas/betas at s_off: alpha_k then beta_k.
+__global__ __launch_bounds__(NT) void k_lanczos(BuildBatch bb) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c)) return;
+  const int b = c.b, m = c.m, mb = m * b;
+  const double* Am = bb.d_work + c.am_off;
+  double* Q = bb.d_work + c.q_off;
+  double* AQ = bb.d_work + c.av_off;
+  double* Z = AQ + (int64_t)mb * b;
+  double* coef = Z + (int64_t)mb * b;
+  double* gram = coef + (int64_t)mb * b;
+  double* gram2 = gram + (int64_t)b * b;
+  double* alpha = bb.d_work + c.s_off;                 // m b^2
+  double* beta = alpha + (int64_t)m * b * b;           // m b^2 (beta_1 .. beta_m)
+  const double* R1 = bb.d_work + c.r_off;
+  // Q_1 = E_1, beta_1 = R_1
+  for (int64_t idx = threadIdx.x; idx < (int64_t)mb * b; idx += NT) {
+    const int i = idx % mb, j = idx / mb;
+    Q[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  wg_copy(b, b, R1, b, beta, b);
+  for (int k = 0; k < m; ++k) {
+    const double* Qk = Q + (int64_t)k * b * mb;
+    double* ak = alpha + (int64_t)k * b * b;
+    wg_gemm<false, false>(mb, b, mb, 1.0, Am, mb, Qk, mb, 0.0, AQ, mb);
+    wg_gemm<true, false>(b, b, mb, 1.0, Qk, mb, AQ, mb, 0.0, ak, b);
+    wg_symmetrize(b, ak, b);
+    if (k == m - 1) break;
+    wg_copy(mb, b, AQ, mb, Z, mb);
+    wg_gemm<false, false>(mb, b, b, -1.0, Qk, mb, ak, b, 1.0, Z, mb);
+    if (k > 0) {
+      const double* bk = beta + (int64_t)k * b * b;
+      wg_gemm<false, true>(mb, b, b, -1.0, Q + (int64_t)(k - 1) * b * mb, mb, bk, b, 1.0, Z, mb);
+    }
+    const int kb = (k + 1) * b;
+    for (int pass = 0; pass < 2; ++pass) {
+      wg_gemm<true, false>(kb, b, mb, 1.0, Q, mb, Z, mb, 0.0, coef, kb);
+      wg_gemm<false, false>(mb, b, kb, -1.0, Q, mb, coef, kb, 1.0, Z, mb);
+    }
+    // Cholesky-QR, twice: Z = Q_{k+1} beta_{k+1}
+    double* bn = beta + (int64_t)(k + 1) * b * b;
+    wg_gemm<true, false>(b, b, mb, 1.0, Z, mb, Z, mb, 0.0, gram, b);
+    wg_symmetrize(b, gram, b);
+    double ratio = wg_potrf(b, gram, b);
+    if (!(ratio > 1e-10)) { if (threadIdx.x == 0) c.status = ST_BREAKDOWN; return; }
+    wg_trsm_right_lt(mb, b, gram, b, Z, mb);
+    wg_gemm<true, false>(b, b, mb, 1.0, Z, mb, Z, mb, 0.0, gram2, b);
+    wg_symmetrize(b, gram2, b);
+    ratio = wg_potrf(b, gram2, b);
+    if (!(ratio > 1e-6)) { if (threadIdx.x == 0) c.status = ST_BREAKDOWN; return; }
+    wg_trsm_right_lt(mb, b, gram2, b, Z, mb);
+    // beta = L2^T L1^T (upper)
+    for (int idx = threadIdx.x; idx < b * b; idx += NT) {
+      const int r = idx % b, cc = idx / b;
+      double s = 0.0;
+      for (int l = r; l <= cc; ++l) s += gram2[l + (int64_t)r * b] * gram[cc + (int64_t)l * b];
+      bn[r + (int64_t)cc * b] = (r <= cc) ? s : 0.0;
+    }
+    wg_copy(mb, b, Z, mb, Q + (int64_t)(k + 1) * b * mb, mb);
+  }
+}
+
+// K5: S-fraction blocks from (alpha_k, beta_k) (eq. GammaTrans, corrected).
+// Output at out_off: Ghat^1..Ghat^m then G^1..G^m.
+__global__ __launch_bounds__(NT) void k_sfraction(BuildBatch bb) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c)) return;
+  const int b = c.b, m = c.m;
+  const int64_t bb2 = (int64_t)b * b;
+  const double* alpha = bb.d_work + c.s_off;
+  const double* beta = alpha + m * bb2;
+  double* out = bb.d_work + c.out_off;
+  double* Ghat = out;
+  double* G = out + m * bb2;
+  // scratch in the av region: Gk, Ginv, T1, Mt, Minv, W, fac, chol
+  double* base = bb.d_work + c.av_off;
+  double* Gk = base;
+  double* Ginv = Gk + bb2;
+  double* T1 = Ginv + bb2;
+  double* Mt = T1 + bb2;
+  double* Minv = Mt + bb2;
+  double* Wk = Minv + bb2;
+  double* fac = Wk + bb2;
+  double* ch = fac + b;
+  // G_1 = beta_1^T
+  for (int idx = threadIdx.x; idx < b * b; idx += NT) {
+    const int r = idx % b, cc = idx / b;
+    Gk[r + (int64_t)cc * b] = beta[cc + (int64_t)r * b];
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    double* Gh = Ghat + k * bb2;
+    double* Gc = G + k * bb2;
+    wg_gemm<false, true>(b, b, b, 1.0, Gk, b, Gk, b, 0.0, Gh, b);
+    wg_symmetrize(b, Gh, b);
+    if (!wg_inverse(b, Gk, b, Ginv, b, Wk, fac)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
+    wg_gemm<false, false>(b, b, b, 1.0, alpha + k * bb2, b, Ginv, b, 0.0, T1, b);
+    if (k > 0) wg_copy(b, b, G + (k - 1) * bb2, b, Gc, b);
+    wg_gemm<true, false>(b, b, b, -1.0, Ginv, b, T1, b, (k > 0) ? -1.0 : 0.0, Gc, b);
+    wg_symmetrize(b, Gc, b);
+    // SPD checks of the pivots (eq. S-fraction); the deepest G^m of a
+    // floating cell is only semidefinite to rounding and is not checked.
+    wg_copy(b, b, Gh, b, ch, b);
+    double r1 = wg_potrf(b, ch, b);
+    double r2 = 1.0;
+    if (k < m - 1) {
+      wg_copy(b, b, Gc, b, ch, b);
+      r2 = wg_potrf(b, ch, b);
+    }
+    if (!(r1 > 0.0) || !(r2 > 0.0)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
+    if (k < m - 1) {
+      wg_gemm<true, false>(b, b, b, 1.0, Gk, b, Gc, b, 0.0, Mt, b);
+      if (!wg_inverse(b, Mt, b, Minv, b, Wk, fac)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
+      wg_gemm<false, true>(b, b, b, 1.0, Minv, b, beta + (k + 1) * bb2, b, 0.0, Gk, b);
+    }
+  }
+  // finite check
+  __shared__ int s_nf;
+  if (threadIdx.x == 0) s_nf = 0;
+  __syncthreads();
+  for (int64_t idx = threadIdx.x; idx < 2 * m * bb2; idx += NT)
+    if (!isfinite(out[idx])) s_nf = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && s_nf) c.status = ST_NONFINITE;
+}
+
+hipError_t launch_build(const BuildBatch& bb, hipStream_t st) {
+  const dim3 grid(bb.ncell), block(NT);
+  hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bb);
+  hipLaunchKernelGGL(k_krylov_start, grid, block, 0, st, bb);
+  for (int j = 0; j < bb.max_m; ++j) {
+    hipLaunchKernelGGL(k_cgs2, grid, block, 0, st, bb, j);
+    hipLaunchKernelGGL(k_normalize, grid, block, 0, st, bb, j);
+    if (j + 1 < bb.max_m) hipLaunchKernelGGL(k_shift_solve, grid, block, 0, st, bb, j);
+  }
+  hipLaunchKernelGGL(k_project, grid, block, 0, st, bb);
+  hipLaunchKernelGGL(k_lanczos, grid, block, 0, st, bb);
+  hipLaunchKernelGGL(k_sfraction, grid, block, 0, st, bb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// packing into the on-line layout and piece masses
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline T cvt(double v);
+template <>
+__device__ inline double cvt<double>(double v) { return v; }
+template <>
+__device__ inline float cvt<float>(double v) { return (float)v; }
+template <>
+__device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
+
+// Blocks per cell in the on-line layout: G^1..G^m, then Ghat^2..Ghat^m.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pack(const BuildCell* bc, const double* work,
+                                             const OnlineCell* oc, T* blocks, double* rom64,
+                                             const int64_t* rom64_off) {
+  const BuildCell& c = bc[blockIdx.x];
+  const OnlineCell& o = oc[blockIdx.x];
+  const int b = c.b, m = c.m;
+  const int64_t bb2 = (int64_t)b * b;
+  const double* src = work + c.out_off;
+  double* r64 = rom64 + rom64_off[blockIdx.x];
+  for (int64_t idx = threadIdx.x; idx < 2 * m * bb2; idx += NT) r64[idx] = src[idx];
+  T* dst = blocks + o.blk_off;
+  for (int64_t idx = threadIdx.x; idx < m * bb2; idx += NT) dst[idx] = cvt<T>(src[m * bb2 + idx]);
+  for (int64_t idx = threadIdx.x; idx < (m - 1) * bb2; idx += NT) dst[m * bb2 + idx] = cvt<T>(src[bb2 + idx]);
+}
+
+hipError_t launch_pack(int32_t ncell, const BuildCell* d_bcells, const double* d_work,
+                       const OnlineCell* d_ocells, int32_t prec, void* d_blocks, double* d_rom64,
+                       const int64_t* d_rom64_off, hipStream_t st) {
+  const dim3 grid(ncell), block(NT);
+  if (prec == SFROM_F64)
+    hipLaunchKernelGGL(k_pack<double>, grid, block, 0, st, d_bcells, d_work, d_ocells, (double*)d_blocks, d_rom64, d_rom64_off);
+  else if (prec == SFROM_F32)
+    hipLaunchKernelGGL(k_pack<float>, grid, block, 0, st, d_bcells, d_work, d_ocells, (float*)d_blocks, d_rom64, d_rom64_off);
+  else
+    hipLaunchKernelGGL(k_pack<__hip_bfloat16>, grid, block, 0, st, d_bcells, d_work, d_ocells, (__hip_bfloat16*)d_blocks, d_rom64, d_rom64_off);
+  return hipGetLastError();
+}
+
+// M_p = sum_{cells c owning p} ([Ghat_c^1]_pp)^{-1}; store M_p^{-1}. One
+// thread per piece (b_p is small: a face or edge basis); the three b_p x b_p
+// work matrices live in global scratch at 3 * minv_off.
+template <typename T>
+__global__ void k_piece_mass(MassArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.npiece) return;
+  const OnlinePiece pc = a.d_pieces[p];
+  const int bp = pc.b;
+  double* M = a.d_scratch + 3 * pc.minv_off;
+  double* Wm = M + bp * bp;
+  double* Inv = Wm + bp * bp;
+  for (int i = 0; i < bp * bp; ++i) M[i] = 0.0;
+  for (int e = 0; e < pc.ncell; ++e) {
+    const int cell = a.d_inc_cell[pc.inc_off + e];
+    const int col0 = a.d_inc_col[pc.inc_off + e];
+    const int b = a.d_cells[cell].b;
+    const double* G1 = a.d_rom64 + a.d_rom64_off[cell];   // Ghat^1 of the cell
+    for (int j = 0; j < bp; ++j)
+      for (int i = 0; i < bp; ++i) Wm[i + j * bp] = G1[(col0 + i) + (int64_t)(col0 + j) * b];
+    // invert the small SPD block by Gauss-Jordan
+    for (int i = 0; i < bp * bp; ++i) Inv[i] = 0.0;
+    for (int i = 0; i < bp; ++i) Inv[i + i * bp] = 1.0;
+    int ok = 1;
+    for (int j = 0; j < bp; ++j) {
+      int piv = j;
+      for (int i = j + 1; i < bp; ++i) if (fabs(Wm[i + j * bp]) > fabs(Wm[piv + j * bp])) piv = i;
+      if (!(fabs(Wm[piv + j * bp]) > 0.0)) { ok = 0; break; }
+      if (piv != j)
+        for (int cc = 0; cc < bp; ++cc) {
+          double t = Wm[j + cc * bp]; Wm[j + cc * bp] = Wm[piv + cc * bp]; Wm[piv + cc * bp] = t;
+          t = Inv[j + cc * bp]; Inv[j + cc * bp] = Inv[piv + cc * bp]; Inv[piv + cc * bp] = t;
+        }
+      const double ip = 1.0 / Wm[j + j * bp];
+      for (int cc = 0; cc < bp; ++cc) { Wm[j + cc * bp] *= ip; Inv[j + cc * bp] *= ip; }
+      for (int i = 0; i < bp; ++i) {
+        if (i == j) continue;
+        const double f = Wm[i + j * bp];
+        if (f == 0.0) continue;
+        for (int cc = 0; cc < bp; ++cc) { Wm[i + cc * bp] -= f * Wm[j + cc * bp]; Inv[i + cc * bp] -= f * Inv[j + cc * bp]; }
+      }
+    }
+    if (!ok) { a.d_status[p] = 1; return; }
+    for (int i = 0; i < bp * bp; ++i) M[i] += Inv[i];
+  }
+  // M_p^{-1}
+  for (int i = 0; i < bp * bp; ++i) { Wm[i] = 0.5 * (M[i] + M[(i % bp) * bp + i / bp]); Inv[i] = 0.0; }
+  for (int i = 0; i < bp; ++i) Inv[i + i * bp] = 1.0;
+  for (int j = 0; j < bp; ++j) {
+    int piv = j;
+    for (int i = j + 1; i < bp; ++i) if (fabs(Wm[i + j * bp]) > fabs(Wm[piv + j * bp])) piv = i;
+    if (!(fabs(Wm[piv + j * bp]) > 0.0)) { a.d_status[p] = 1; return; }
+    if (piv != j)
+      for (int cc = 0; cc < bp; ++cc) {
+        double t = Wm[j + cc * bp]; Wm[j + cc * bp] = Wm[piv + cc * bp]; Wm[piv + cc * bp] = t;
+        t = Inv[j + cc * bp]; Inv[j + cc * bp] = Inv[piv + cc * bp]; Inv[piv + cc * bp] = t;
+      }
+    const double ip = 1.0 / Wm[j + j * bp];
+    for (int cc = 0; cc < bp; ++cc) { Wm[j + cc * bp] *= ip; Inv[j + cc * bp] *= ip; }
+    for (int i = 0; i < bp; ++i) {
+      if (i == j) continue;
+      const double f = Wm[i + j * bp];
+      if (f == 0.0) continue;
+      for (int cc = 0; cc < bp; ++cc) { Wm[i + cc * bp] -= f * Wm[j + cc * bp]; Inv[i + cc * bp] -= f * Inv[j + cc * bp]; }
+    }
+  }
+  T* out = (T*)a.d_minv + pc.minv_off;
+  for (int i = 0; i < bp * bp; ++i) out[i] = cvt<T>(0.5 * (Inv[i] + Inv[(i % bp) * bp + i / bp]));
+  a.d_status[p] = 0;
+}
+
+hipError_t launch_piece_mass(const MassArgs& a, hipStream_t st) {
+  const int tpb = 64;
+  const dim3 grid((a.npiece + tpb - 1) / tpb), block(tpb);
+  // masses are kept in float for BF16 (only the blocks are bfloat16)
+  if (a.prec == SFROM_F64)
+    hipLaunchKernelGGL(k_piece_mass<double>, grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL(k_piece_mass<float>, grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace sfrom_impl

@@ -1,0 +1,274 @@
+// Internal definitions of libsfrom shared by the host C++ and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sfrom.h"
+
+namespace sfrom_impl {
+
+// ---------------------------------------------------------------------------
+// Problem description (host)
+// ---------------------------------------------------------------------------
+
+struct CellDef {
+  bool defined = false;
+  int32_t n = 0;
+  std::vector<int64_t> gnode;     // local -> global node
+  std::vector<int32_t> rowptr;    // local CSR of A_i
+  std::vector<int32_t> col;
+  std::vector<double> a;
+  std::vector<double> b;          // diag(B_i)
+};
+
+struct PieceDef {
+  bool defined = false;
+  std::vector<int64_t> gnode;     // global nodes, k_p
+  int32_t b = 0;                  // basis size b_p
+  std::vector<double> S;          // k_p x b_p column-major
+};
+
+// Columns (sources or receivers) after restriction to the skeleton.
+struct Columns {
+  int32_t count = 0;
+  std::vector<int64_t> colptr, row;   // fine-grid CSC (possibly projected)
+  std::vector<double> val;
+  // reduced coefficients: per column, list of (piece, coeff[b_p])
+  std::vector<int64_t> rptr;          // per column into rpiece
+  std::vector<int32_t> rpiece;
+  std::vector<int64_t> rcoff;         // offset into rcoef for each (column, piece)
+  std::vector<double> rcoef;
+};
+
+// Per-cell descriptor of the off-line workspace (device), all offsets in doubles.
+struct BuildCell {
+  int32_t n;        // local nodes
+  int32_t b;        // boundary dimension
+  int32_t m;        // layers
+  int32_t w;        // lower bandwidth
+  int32_t nnz;      // local CSR nonzeros
+  int32_t nw;       // number of skeleton rows (entries of the W map)
+  int64_t csr_off;  // into rowptr-free arrays (rowptr stored separately)
+  int64_t rp_off;   // into rowptr array (n+1 entries)
+  int64_t w_off;    // into the W map arrays
+  int64_t b_off;    // into diag(B_i) array
+  int64_t band_off; // band storage n*(w+1)
+  int64_t v_off;    // V: n x m b
+  int64_t x_off;    // X: n x b (work) and B q
+  int64_t av_off;   // A V: n x m b (reused as Lanczos work)
+  int64_t am_off;   // A^m: (m b)^2
+  int64_t q_off;    // Lanczos Q: (m b) x (m b)
+  int64_t s_off;    // small work: 8 b^2 + ...
+  int64_t r_off;    // R_j factors: m b^2 (R_1 = beta_1)
+  int64_t out_off;  // S-fraction output: 2 m b^2 (Ghat^1..m then G^1..m)
+  int32_t status;   // per-cell status (written by kernels)
+  int32_t pad;
+};
+
+// Per-cell on-line descriptor.
+struct OnlineCell {
+  int32_t m, b;
+  int64_t blk_off;   // elements into the block array: G^1..G^m, Ghat^2..Ghat^m
+  int64_t hid_off;   // rows into the hidden state ((m-1) b rows of n_s)
+  int64_t u1_off;    // rows into the gather map / phi scratch (b rows)
+};
+
+// Per-piece on-line descriptor.
+struct OnlinePiece {
+  int32_t b;         // b_p
+  int32_t ncell;     // incident cells
+  int64_t dof_off;   // rows into the piece state
+  int64_t inc_off;   // into the incidence array (phi base rows), ncell entries
+  int64_t minv_off;  // elements into M_p^{-1} (b_p x b_p)
+  int64_t src_off;   // rows into the dense reduced-source array, -1 if none
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+
+// Off-line build of a batch of cells. Returns hipError_t; per-cell status in
+// the device BuildCell array.
+struct BuildBatch {
+  int32_t ncell;
+  int32_t max_m, max_b, max_n;
+  double shift;
+  BuildCell* d_cells;
+  const int32_t* d_rowptr;
+  const int32_t* d_col;
+  const double* d_a;
+  const double* d_bdiag;
+  const int32_t* d_wrow;      // skeleton rows of the cell
+  const int32_t* d_wcol;      // first column of the row's piece block in W
+  const int64_t* d_wsoff;     // offset of S_p row for this node (S_p + pos) in d_S
+  const int32_t* d_wbp;       // b_p of that piece
+  const int32_t* d_wkp;       // k_p (leading dimension of S_p)
+  const double* d_S;
+  double* d_work;
+};
+hipError_t launch_build(const BuildBatch& bb, hipStream_t st);
+
+// Pack the double S-fraction of one batch into the on-line layout.
+hipError_t launch_pack(int32_t ncell, const BuildCell* d_bcells, const double* d_work,
+                       const OnlineCell* d_ocells, int32_t prec, void* d_blocks,
+                       double* d_rom64, const int64_t* d_rom64_off, hipStream_t st);
+
+// Piece masses M_p^{-1} from Ghat^1 of the incident cells.
+struct MassArgs {
+  int32_t npiece;
+  const OnlinePiece* d_pieces;
+  const int32_t* d_inc_cell;     // incident cell id per incidence entry
+  const int32_t* d_inc_col;      // column offset of the piece inside that cell
+  const OnlineCell* d_cells;
+  const double* d_rom64;         // per cell Ghat^1..m, G^1..m (double)
+  const int64_t* d_rom64_off;
+  int32_t prec;
+  void* d_minv;                  // output in on-line precision
+  int32_t* d_status;             // per piece status
+  double* d_scratch;             // 3 * sum_p b_p^2 doubles
+};
+hipError_t launch_piece_mass(const MassArgs& a, hipStream_t st);
+
+// One on-line leapfrog step.
+struct StepArgs {
+  int32_t ncell, npiece, ns, nrec;
+  int32_t prec;
+  int32_t max_b, max_m;
+  double dt2;
+  const OnlineCell* d_cells;
+  const OnlinePiece* d_pieces;
+  const int32_t* d_gather;       // per cell boundary row -> piece dof row
+  const int64_t* d_inc;          // phi base rows per piece incidence
+  const void* d_blocks;
+  const void* d_minv;
+  const void* d_src;             // dense reduced sources of source pieces
+  void* y_cur;                   // piece state level n   (read)
+  void* y_old;                   // piece state level n-1 (overwritten by n+1)
+  void* h_cur;                   // hidden level n
+  void* h_old;                   // hidden level n-1 (overwritten by n+1)
+  void* phi;                     // phi scratch, sum_i b_i rows
+  const double* w;               // device wavelet samples
+  int64_t step;                  // index into w
+  // receivers (CSR over piece dofs)
+  const int64_t* d_rptr;
+  const int64_t* d_rrow;
+  const double* d_rval;
+  void* traces;                  // n_steps x n_rec x ns
+  int64_t trace_step;            // which slice to write
+};
+hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
+
+// Fine-grid leapfrog step (CSR).
+struct FineArgs {
+  int64_t n;
+  int32_t ns, nrec, prec;
+  double dt2;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const void* a;                 // values in precision prec
+  const void* binv;              // 1/b in precision prec
+  void* u_cur;
+  void* u_old;                   // overwritten by level n+1
+  const double* w;
+  int64_t step;
+  int64_t nsrc_entries;
+  const int64_t* src_row;        // source entries (node, source, value)
+  const int32_t* src_col;
+  const double* src_val;
+  const int64_t* rec_ptr;        // receivers CSC over nodes
+  const int64_t* rec_row;
+  const double* rec_val;
+  void* traces;
+  int64_t trace_step;
+};
+hipError_t launch_fine_step(const FineArgs& a, hipStream_t st);
+
+}  // namespace sfrom_impl
+
+struct sfrom {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // pencil
+  int64_t n = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> a, b;
+
+  std::vector<sfrom_impl::CellDef> cells;
+  std::vector<sfrom_impl::PieceDef> pieces;
+
+  // derived partition
+  bool part_ready = false;
+  std::vector<int32_t> piece_of_node;       // n, -1 off skeleton
+  std::vector<int32_t> pos_in_piece;        // n
+  std::vector<std::vector<int32_t>> cell_pieces;   // ascending piece ids
+  std::vector<std::vector<int32_t>> cell_piece_col;// column offset of each piece in W_i
+  std::vector<int32_t> cell_b;
+  std::vector<std::vector<int32_t>> piece_cells;   // ascending cell ids
+  std::vector<int64_t> piece_dof_off;              // n_pieces + 1
+
+  // ROM
+  bool built = false;
+  int32_t prec = SFROM_F32;
+  std::vector<int32_t> cell_m;
+  double shift = 0.0;
+  double build_ms = 0.0;
+  int64_t n_hidden_dofs = 0;
+  int64_t block_elems = 0;
+  std::vector<sfrom_impl::OnlineCell> ocells;
+  std::vector<sfrom_impl::OnlinePiece> opieces;
+  std::vector<int64_t> rom64_off;                  // per cell into d_rom64
+
+  // device: on-line structures
+  void* d_blocks = nullptr;
+  void* d_minv = nullptr;
+  double* d_rom64 = nullptr;
+  int64_t* d_rom64_off = nullptr;
+  sfrom_impl::OnlineCell* d_ocells = nullptr;
+  sfrom_impl::OnlinePiece* d_opieces = nullptr;
+  int32_t* d_gather = nullptr;
+  int64_t* d_inc = nullptr;
+  int32_t* d_inc_cell = nullptr;
+  int32_t* d_inc_col = nullptr;
+  bool masses_dirty = true;
+
+  // sources / receivers
+  sfrom_impl::Columns src, rec;
+  bool src_dirty = true, rec_dirty = true;
+  // ROM-side device I/O
+  void* d_src = nullptr;          // dense reduced sources (rows of source pieces)
+  int64_t* d_rptr = nullptr;      // receivers over piece dofs
+  int64_t* d_rrow = nullptr;
+  double* d_rval = nullptr;
+  int32_t state_ns = -1;          // n_s the state buffers are sized for
+  void* d_y[2] = {nullptr, nullptr};
+  void* d_h[2] = {nullptr, nullptr};
+  void* d_phi = nullptr;
+  int cur = 0;                    // which buffer holds level n
+  double* d_w = nullptr;
+  int64_t d_w_cap = 0;
+
+  // fine comparator
+  int32_t fine_prec = -1;
+  int32_t fine_ns = -1;
+  int64_t* d_frowptr = nullptr;
+  int32_t* d_fcol = nullptr;
+  void* d_fa = nullptr;
+  void* d_fbinv = nullptr;
+  void* d_u[2] = {nullptr, nullptr};
+  int fcur = 0;
+  int64_t* d_fsrc_row = nullptr;
+  int32_t* d_fsrc_col = nullptr;
+  double* d_fsrc_val = nullptr;
+  int64_t fsrc_n = 0;
+  int64_t* d_frec_ptr = nullptr;
+  int64_t* d_frec_row = nullptr;
+  double* d_frec_val = nullptr;
+  bool fine_io_dirty = true;
+};

@@ -1,0 +1,298 @@
+"""ctypes binding of libsfrom (include/sfrom.h), function for function.
+
+Argument marshalling only: numpy arrays become host pointers, torch tensors
+on the GPU become device pointers; every computation happens in the
+library's HIP kernels. Importing this module raises if the library has not
+been built (``python -m paper_1604_06750_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfrom.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_1604_06750_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+SFROM_F64, SFROM_F32, SFROM_BF16 = 0, 1, 2
+
+STATUS = {
+    0: "OK", -1: "EINVAL", -2: "ENOTSYM", -3: "ENOTNSD", -4: "EBPOS", -5: "ESUPPORT",
+    -6: "EBREAKDOWN", -7: "ENOTSPD", -8: "ECFL", -9: "ENONFINITE", -10: "EDEVICE",
+    -11: "ESTATE", -12: "ENOMEM", -13: "ESPLIT",
+}
+
+
+class SfromError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class sfrom_build_opts(C.Structure):
+    _fields_ = [("m", C.c_int32), ("m_per_cell", C.POINTER(C.c_int32)), ("shift", C.c_double),
+                ("online_prec", C.c_int32), ("cells_per_batch", C.c_int32)]
+
+
+class sfrom_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_cells", C.c_int32), ("n_pieces", C.c_int32),
+                ("n_piece_dofs", C.c_int64), ("n_hidden_dofs", C.c_int64), ("max_b", C.c_int32),
+                ("max_m", C.c_int32), ("n_sources", C.c_int32), ("n_receivers", C.c_int32),
+                ("built", C.c_int32), ("online_prec", C.c_int32), ("block_bytes", C.c_int64),
+                ("build_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_P = C.c_void_p
+_SIGS = {
+    "sfrom_create": [C.POINTER(_P), C.c_int, _P],
+    "sfrom_destroy": [_P],
+    "sfrom_last_error": [_P],
+    "sfrom_set_pencil": [_P, C.c_int64, _P, _P, _P, _P],
+    "sfrom_add_cell": [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P],
+    "sfrom_add_piece": [_P, C.c_int32, C.c_int32, _P, C.c_int32, _P],
+    "sfrom_setup_voxel_acoustic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
+    "sfrom_build": [_P, C.POINTER(sfrom_build_opts)],
+    "sfrom_import_rom": [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P],
+    "sfrom_export_rom": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P],
+    "sfrom_set_sources": [_P, C.c_int32, _P, _P, _P, C.c_int32],
+    "sfrom_set_receivers": [_P, C.c_int32, _P, _P, _P, C.c_int32],
+    "sfrom_point_columns": [_P, C.c_int32, _P, _P, _P, _P],
+    "sfrom_reset": [_P],
+    "sfrom_run": [_P, C.c_int64, C.c_double, _P, C.c_int32, _P, C.c_int32],
+    "sfrom_fine_reset": [_P],
+    "sfrom_fine_run": [_P, C.c_int64, C.c_double, _P, C.c_int32, _P, C.c_int32, C.c_int32],
+    "sfrom_fine_lambda_max": [_P, C.POINTER(C.c_double)],
+    "sfrom_rom_lambda_max": [_P, C.POINTER(C.c_double)],
+    "sfrom_get_info": [_P, C.POINTER(sfrom_info)],
+    "sfrom_export_pencil": [_P, _P, _P, _P, _P],
+    "sfrom_export_cell": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                          _P, _P, _P, _P, _P],
+    "sfrom_export_piece": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.sfrom_destroy.restype = None
+_lib.sfrom_last_error.restype = C.c_char_p
+
+EXPORTED = tuple(_SIGS)
+
+
+def _ptr(a, dtype=None):
+    """Host pointer of a contiguous numpy array (kept alive by the caller)."""
+    if a is None:
+        return None
+    return a.ctypes.data_as(_P)
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _dev(t):
+    """Device pointer of a torch tensor."""
+    return _P(t.data_ptr())
+
+
+def _check(h, rc):
+    if rc != 0:
+        msg = _lib.sfrom_last_error(h).decode() if h else ""
+        raise SfromError(rc, msg)
+
+
+# ---------------------------------------------------------------------------
+# one wrapper per C function
+# ---------------------------------------------------------------------------
+
+def sfrom_create(device: int = 0, stream: int = 0):
+    h = _P()
+    rc = _lib.sfrom_create(C.byref(h), device, _P(stream) if stream else None)
+    if rc != 0:
+        raise SfromError(rc, "sfrom_create failed")
+    return h
+
+
+def sfrom_destroy(h):
+    _lib.sfrom_destroy(h)
+
+
+def sfrom_last_error(h) -> str:
+    return _lib.sfrom_last_error(h).decode()
+
+
+def sfrom_set_pencil(h, rowptr, col, a, b):
+    rowptr = _host(rowptr, np.int64); col = _host(col, np.int32)
+    a = _host(a, np.float64); b = _host(b, np.float64)
+    _check(h, _lib.sfrom_set_pencil(h, len(b), _ptr(rowptr), _ptr(col), _ptr(a), _ptr(b)))
+
+
+def sfrom_add_cell(h, cell, global_node, rowptr, col, a, b):
+    g = _host(global_node, np.int64); rp = _host(rowptr, np.int32); cl = _host(col, np.int32)
+    av = _host(a, np.float64); bv = _host(b, np.float64)
+    _check(h, _lib.sfrom_add_cell(h, cell, len(g), _ptr(g), _ptr(rp), _ptr(cl), _ptr(av), _ptr(bv)))
+
+
+def sfrom_add_piece(h, piece, global_node, S):
+    g = _host(global_node, np.int64)
+    S = np.asfortranarray(np.asarray(S, dtype=np.float64))
+    kp, bp = S.shape
+    Sf = S.ravel(order="F")
+    _check(h, _lib.sfrom_add_piece(h, piece, kp, _ptr(g), bp, _ptr(Sf)))
+
+
+def sfrom_setup_voxel_acoustic(h, sigma, rho, cuts, modes_face, modes_edge):
+    """sigma, rho: arrays indexed [x, y, z]; cuts: three sequences of plane
+    coordinates."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    nvox = np.array(sigma.shape, dtype=np.int32)
+    s = np.ascontiguousarray(sigma.transpose(2, 1, 0)).ravel()       # x fastest
+    r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64).transpose(2, 1, 0)).ravel()
+    ncut = np.array([len(c) for c in cuts], dtype=np.int32)
+    cc = np.concatenate([np.asarray(c, dtype=np.int32) for c in cuts]) if ncut.sum() else np.zeros(1, np.int32)
+    _check(h, _lib.sfrom_setup_voxel_acoustic(h, _ptr(nvox), _ptr(s), _ptr(r), _ptr(ncut), _ptr(cc),
+                                              modes_face, modes_edge))
+
+
+def sfrom_build(h, m, shift, online_prec=SFROM_F32, m_per_cell=None, cells_per_batch=0):
+    o = sfrom_build_opts()
+    o.m = m
+    keep = None
+    if m_per_cell is not None:
+        keep = _host(m_per_cell, np.int32)
+        o.m_per_cell = keep.ctypes.data_as(C.POINTER(C.c_int32))
+    o.shift = shift
+    o.online_prec = online_prec
+    o.cells_per_batch = cells_per_batch
+    _check(h, _lib.sfrom_build(h, C.byref(o)))
+    del keep
+
+
+def sfrom_import_rom(h, cell, Ghat, G):
+    Ghat = np.asarray(Ghat, dtype=np.float64); G = np.asarray(G, dtype=np.float64)
+    m, b, _ = Ghat.shape
+    gh = np.ascontiguousarray(Ghat.transpose(0, 2, 1)).ravel()   # column-major blocks
+    g = np.ascontiguousarray(G.transpose(0, 2, 1)).ravel()
+    _check(h, _lib.sfrom_import_rom(h, cell, m, b, _ptr(gh), _ptr(g)))
+
+
+def sfrom_export_rom(h, cell):
+    m = C.c_int32(); b = C.c_int32()
+    _check(h, _lib.sfrom_export_rom(h, cell, C.byref(m), C.byref(b), None, None))
+    gh = np.empty(m.value * b.value * b.value); g = np.empty_like(gh)
+    _check(h, _lib.sfrom_export_rom(h, cell, C.byref(m), C.byref(b), _ptr(gh), _ptr(g)))
+    shp = (m.value, b.value, b.value)
+    return gh.reshape(shp).transpose(0, 2, 1).copy(), g.reshape(shp).transpose(0, 2, 1).copy()
+
+
+def _csc(cols, n_cols):
+    colptr, row, val = cols
+    return _host(colptr, np.int64), _host(row, np.int64), _host(val, np.float64)
+
+
+def sfrom_set_sources(h, colptr, row, val, project=True):
+    cp, rw, vl = _csc((colptr, row, val), None)
+    _check(h, _lib.sfrom_set_sources(h, len(cp) - 1, _ptr(cp), _ptr(rw), _ptr(vl), int(project)))
+
+
+def sfrom_set_receivers(h, colptr, row, val, project=True):
+    cp, rw, vl = _csc((colptr, row, val), None)
+    _check(h, _lib.sfrom_set_receivers(h, len(cp) - 1, _ptr(cp), _ptr(rw), _ptr(vl), int(project)))
+
+
+def sfrom_point_columns(h, nodes, max_piece_nodes):
+    nodes = _host(nodes, np.int64)
+    cp = np.empty(len(nodes) + 1, np.int64)
+    rw = np.empty(max(1, len(nodes) * max_piece_nodes), np.int64)
+    vl = np.empty(max(1, len(nodes) * max_piece_nodes), np.float64)
+    _check(h, _lib.sfrom_point_columns(h, len(nodes), _ptr(nodes), _ptr(cp), _ptr(rw), _ptr(vl)))
+    return cp, rw[:cp[-1]].copy(), vl[:cp[-1]].copy()
+
+
+def sfrom_reset(h):
+    _check(h, _lib.sfrom_reset(h))
+
+
+def _wave_arg(w):
+    if hasattr(w, "data_ptr"):
+        return _dev(w), 1, None
+    w = _host(w, np.float64)
+    return _ptr(w), 0, w
+
+
+def _trace_arg(traces):
+    if hasattr(traces, "data_ptr"):
+        return _dev(traces), 1
+    return _ptr(traces), 0
+
+
+def sfrom_run(h, n_steps, dt, w, traces):
+    """w: numpy float64 (host) or torch float64 CUDA tensor; traces: numpy
+    or torch array of n_steps x n_r x n_s in the on-line precision (float64
+    for F64, float32 otherwise)."""
+    wp, wdev, keep = _wave_arg(w)
+    tp, tdev = _trace_arg(traces)
+    _check(h, _lib.sfrom_run(h, n_steps, dt, wp, wdev, tp, tdev))
+
+
+def sfrom_fine_reset(h):
+    _check(h, _lib.sfrom_fine_reset(h))
+
+
+def sfrom_fine_run(h, n_steps, dt, w, traces, prec=SFROM_F32):
+    wp, wdev, keep = _wave_arg(w)
+    tp, tdev = _trace_arg(traces)
+    _check(h, _lib.sfrom_fine_run(h, n_steps, dt, wp, wdev, tp, tdev, prec))
+
+
+def sfrom_fine_lambda_max(h) -> float:
+    v = C.c_double()
+    _check(h, _lib.sfrom_fine_lambda_max(h, C.byref(v)))
+    return v.value
+
+
+def sfrom_rom_lambda_max(h) -> float:
+    v = C.c_double()
+    _check(h, _lib.sfrom_rom_lambda_max(h, C.byref(v)))
+    return v.value
+
+
+def sfrom_get_info(h) -> dict:
+    i = sfrom_info()
+    _check(h, _lib.sfrom_get_info(h, C.byref(i)))
+    return i.as_dict()
+
+
+def sfrom_export_pencil(h):
+    info = sfrom_get_info(h)
+    rp = np.empty(info["n"] + 1, np.int64); cl = np.empty(info["nnz"], np.int32)
+    a = np.empty(info["nnz"]); b = np.empty(info["n"])
+    _check(h, _lib.sfrom_export_pencil(h, _ptr(rp), _ptr(cl), _ptr(a), _ptr(b)))
+    return rp, cl, a, b
+
+
+def sfrom_export_cell(h, cell):
+    n = C.c_int32(); nnz = C.c_int32(); bd = C.c_int32()
+    _check(h, _lib.sfrom_export_cell(h, cell, C.byref(n), C.byref(nnz), C.byref(bd), None, None, None, None, None))
+    g = np.empty(n.value, np.int64); rp = np.empty(n.value + 1, np.int32); cl = np.empty(nnz.value, np.int32)
+    a = np.empty(nnz.value); b = np.empty(n.value)
+    _check(h, _lib.sfrom_export_cell(h, cell, C.byref(n), C.byref(nnz), C.byref(bd), _ptr(g), _ptr(rp), _ptr(cl),
+                                     _ptr(a), _ptr(b)))
+    return {"global_node": g, "rowptr": rp, "col": cl, "a": a, "b": b, "b_dim": bd.value}
+
+
+def sfrom_export_piece(h, piece):
+    k = C.c_int32(); bp = C.c_int32()
+    _check(h, _lib.sfrom_export_piece(h, piece, C.byref(k), C.byref(bp), None, None))
+    g = np.empty(k.value, np.int64); S = np.empty(k.value * bp.value)
+    _check(h, _lib.sfrom_export_piece(h, piece, C.byref(k), C.byref(bp), _ptr(g), _ptr(S)))
+    return g, S.reshape(bp.value, k.value).T.copy()

@@ -252,4 +252,5 @@ def random_spd(n: int, rng: np.random.Generator, cond: float = 10.0, scale: floa
     log-spaced in [scale/cond, scale]."""
     q, _ = np.linalg.qr(rng.standard_normal((n, n)))
     ev = scale * np.logspace(-np.log10(cond), 0.0, n)
-    return (q * ev) @ q.T
+    m = (q * ev) @ q.T
+    return 0.5 * (m + m.T)

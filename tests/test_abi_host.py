@@ -1,0 +1,164 @@
+"""CPU tests of libsfrom's host side through the C ABI (no GPU calls):
+the library loads and exports every declared symbol; the host C++ voxel
+set-up (fine pencil, voxel-wise split, pieces, bases, projected point
+columns) equals the oracle's; validation rejects bad inputs with the
+documented status codes."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import fine
+from oracle.partition import CartesianPartition
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1604_06750_amd import sfrom
+    return sfrom
+
+
+def test_library_exports_every_declared_symbol():
+    S = _lib()
+    hdr = open(os.path.join(ROOT, "include", "sfrom.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(sfrom_\w+)\s*\(", hdr, re.M))
+    assert len(declared) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", S.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert declared <= exported, declared - exported
+    assert declared == set(S.EXPORTED)
+
+
+@pytest.fixture()
+def host():
+    S = _lib()
+    h = S.sfrom_create(-1)
+    yield S, h
+    S.sfrom_destroy(h)
+
+
+@pytest.mark.parametrize("name,mf,me", [("tiny", 4, 2), ("uneven", 9, 3)])
+def test_voxel_setup_matches_oracle(host, name, mf, me):
+    S, h = host
+    if name == "tiny":
+        wl = synth.workload("tiny", modes_face=mf, modes_edge=me)
+        sigma, rho, cuts, nvox = wl.sigma, wl.rho, wl.cuts, wl.nvox
+    else:
+        rng = np.random.default_rng(3)
+        nvox = (13, 10, 11)
+        sigma = rng.uniform(1, 4, nvox); rho = rng.uniform(1, 2, nvox)
+        cuts = (np.array([4, 9]), np.array([6]), np.array([3, 7]))
+    S.sfrom_setup_voxel_acoustic(h, sigma, rho, cuts, mf, me)
+    A, b = fine.assemble_acoustic(sigma, rho)
+    rp, cl, av, bv = S.sfrom_export_pencil(h)
+    Ah = sp.csr_matrix((av, cl, rp), shape=A.shape)
+    assert (Ah != 0).nnz == (A != 0).nnz
+    assert abs(Ah - A).max() <= 1e-15 * abs(A).max()
+    assert np.abs(bv - b).max() <= 1e-15 * b.max()
+    part = CartesianPartition(nvox, cuts, mf, me)
+    info = S.sfrom_get_info(h)
+    assert info["n_cells"] == len(part.cells) and info["n_pieces"] == len(part.pieces)
+    for i, c in enumerate(part.cells):
+        e = S.sfrom_export_cell(h, i)
+        assert np.array_equal(e["global_node"], c.nodes)
+        Ai, bi = part.cell_operator(i, sigma, rho)
+        Ae = sp.csr_matrix((e["a"], e["col"], e["rowptr"]), shape=Ai.shape).toarray()
+        assert np.abs(Ae - Ai).max() <= 1e-15 * np.abs(Ai).max()
+        assert np.abs(e["b"] - bi).max() <= 1e-15 * bi.max()
+        assert e["b_dim"] == part.cell_W(i).shape[1]
+    for p, pc in enumerate(part.pieces):
+        g, Sp = S.sfrom_export_piece(h, p)
+        assert np.array_equal(g, pc.nodes)
+        assert Sp.shape == pc.S.shape
+        assert np.abs(Sp - pc.S).max() <= 1e-14
+
+
+def test_point_columns_match_oracle(host):
+    S, h = host
+    from paper_1604_06750_amd.problem import node_ids, max_piece_nodes
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2)
+    S.sfrom_setup_voxel_acoustic(h, wl.sigma, wl.rho, wl.cuts, 4, 2)
+    part = CartesianPartition(wl.nvox, wl.cuts, 4, 2)
+    pts = np.vstack([wl.sources, wl.receivers])
+    G, _ = part.point_columns(pts)
+    cp, rw, vl = S.sfrom_point_columns(h, node_ids(wl.nvox, pts), max_piece_nodes(wl))
+    Gh = sp.csc_matrix((vl, rw, cp), shape=G.shape).toarray()
+    assert np.abs(Gh - G).max() <= 1e-15
+
+
+def _small_split(S, h):
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2)
+    S.sfrom_setup_voxel_acoustic(h, wl.sigma, wl.rho, wl.cuts, 4, 2)
+    return wl
+
+
+def test_source_off_skeleton_is_rejected(host):
+    S, h = host
+    wl = _small_split(S, h)
+    from paper_1604_06750_amd.problem import node_ids
+    k = node_ids(wl.nvox, [[3, 3, 3]])      # a cell-interior node
+    with pytest.raises(S.SfromError) as e:
+        S.sfrom_set_sources(h, np.array([0, 1]), k, np.array([1.0]))
+    assert e.value.name == "ESUPPORT"
+    with pytest.raises(S.SfromError) as e:
+        S.sfrom_point_columns(h, k, 64)
+    assert e.value.name == "ESUPPORT"
+
+
+def test_split_mismatch_is_rejected(host):
+    """A cell operator that does not add up to A (eq. splitN_c) is refused."""
+    S, h = host
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2)
+    A, b = fine.assemble_acoustic(wl.sigma, wl.rho)
+    S.sfrom_set_pencil(h, A.indptr, A.indices, A.data, b)
+    part = CartesianPartition(wl.nvox, wl.cuts, 4, 2)
+    for i, c in enumerate(part.cells):
+        Ai, bi = part.cell_operator(i, wl.sigma, wl.rho)
+        if i == 3:
+            bi = bi.copy(); bi[0] *= 1.01
+        M = sp.csr_matrix(Ai)
+        S.sfrom_add_cell(h, i, c.nodes, M.indptr, M.indices, M.data, bi)
+    for p, pc in enumerate(part.pieces):
+        S.sfrom_add_piece(h, p, pc.nodes, pc.S)
+    cp, rw, vl = np.array([0, 1]), np.array([part.pieces[0].nodes[0]]), np.array([1.0])
+    with pytest.raises(S.SfromError) as e:
+        S.sfrom_set_sources(h, cp, rw, vl)
+    assert e.value.name == "ESPLIT"
+
+
+def test_pencil_validation(host):
+    S, h = host
+    A = sp.csr_matrix(np.array([[-2.0, 1.0], [0.5, -2.0]]))
+    with pytest.raises(S.SfromError) as e:
+        S.sfrom_set_pencil(h, A.indptr, A.indices, A.data, np.ones(2))
+    assert e.value.name == "ENOTSYM"
+    A = sp.csr_matrix(np.array([[-2.0, 1.0], [1.0, -2.0]]))
+    with pytest.raises(S.SfromError) as e:
+        S.sfrom_set_pencil(h, A.indptr, A.indices, A.data, np.array([1.0, -1.0]))
+    assert e.value.name == "EBPOS"
+    with pytest.raises(S.SfromError) as e:
+        S.sfrom_set_pencil(h, A.indptr, A.indices, A.data, np.array([1.0, np.nan]))
+    assert e.value.name == "ENONFINITE"
+
+
+def test_piece_basis_must_be_orthonormal(host):
+    S, h = host
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2)
+    A, b = fine.assemble_acoustic(wl.sigma, wl.rho)
+    S.sfrom_set_pencil(h, A.indptr, A.indices, A.data, b)
+    with pytest.raises(S.SfromError) as e:
+        S.sfrom_add_piece(h, 0, np.array([5, 6]), np.array([[1.0], [1.0]]))
+    assert e.value.name == "EINVAL"
+
+
+def test_device_calls_refused_on_host_handle(host):
+    S, h = host
+    _small_split(S, h)
+    with pytest.raises(S.SfromError) as e:
+        S.sfrom_build(h, 3, -0.02)
+    assert e.value.name == "EDEVICE"

@@ -1,0 +1,206 @@
+"""GPU parity: libsfrom through the C ABI against the FP64 oracle on the same
+seeded inputs. FP64 paths must agree to 1e-10 relative, FP32 paths to 1e-4
+(relative L2 over all trace samples)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fine, pipeline
+from oracle.partition import CartesianPartition
+from oracle.rom_cell import build_cell
+from oracle.rom_global import GlobalROM
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lib():
+    from paper_1604_06750_amd import sfrom, problem
+    return sfrom, problem
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _handle(S):
+    return S.sfrom_create(0, torch.cuda.current_stream().cuda_stream)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
+
+
+def _gpu_rom(wl, prec, dt, w, m=None, m_per_cell=None):
+    S, P = _lib()
+    h = _handle(S)
+    try:
+        P.setup(h, wl)
+        S.sfrom_build(h, m or wl.m, wl.shift, prec, m_per_cell=m_per_cell)
+        info = S.sfrom_get_info(h)
+        tr = np.zeros((len(w), info["n_receivers"], info["n_sources"]),
+                      np.float64 if prec == S.SFROM_F64 else np.float32)
+        S.sfrom_run(h, len(w), dt, w, tr)
+        blocks = {i: S.sfrom_export_rom(h, i) for i in range(info["n_cells"])}
+        return tr, blocks, info
+    finally:
+        S.sfrom_destroy(h)
+
+
+def test_offline_blocks_match_oracle(dev):
+    """Each cell's S-fraction is unique (Sec. 5), so GPU and oracle blocks
+    must agree blockwise even though their Lanczos bases differ."""
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3)
+    run = pipeline.setup(wl, n_steps=10)
+    pipeline.build_all(run)
+    _, blocks, info = _gpu_rom(wl, S.SFROM_F64, run.dt, run.w)
+    worst = 0.0
+    for i, (Gh, G) in blocks.items():
+        oGh, oG = run.blocks[i]
+        for k in range(wl.m):
+            worst = max(worst, np.linalg.norm(Gh[k] - oGh[k]) / np.linalg.norm(oGh[k]))
+            worst = max(worst, np.linalg.norm(G[k] - oG[k]) / np.linalg.norm(oG[k]))
+    print("max relative block difference", worst)
+    assert worst <= 1e-9
+
+
+def test_online_step_fp64_with_generated_blocks(dev):
+    """The on-line step alone: random SPD S-fraction blocks from the seeded
+    generator (Ghat^1 block diagonal over pieces) are imported on the GPU and
+    stepped; the oracle assembles the same global ROM and steps it."""
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3)
+    part = CartesianPartition(wl.nvox, wl.cuts, 4, 2)
+    rng = np.random.default_rng(77)
+    blocks = {}
+    for i, c in enumerate(part.cells):
+        sizes = [part.pieces[p].S.shape[1] for p in c.pieces]
+        b = sum(sizes)
+        G1 = np.zeros((b, b)); o = 0
+        for s in sizes:
+            G1[o:o + s, o:o + s] = synth.random_spd(s, rng, cond=5.0)
+            o += s
+        Gh = [G1] + [synth.random_spd(b, rng, cond=20.0) for _ in range(wl.m - 1)]
+        G = [synth.random_spd(b, rng, cond=20.0) for _ in range(wl.m)]
+        blocks[i] = (Gh, G)
+    rom = GlobalROM(part, blocks)
+    dt = 0.9 * 2.0 / np.sqrt(rom.lambda_max())
+    w = synth.ricker(200, dt, 0.25 / (40 * dt))
+    _, rs = part.point_columns(wl.sources)
+    _, rr = part.point_columns(wl.receivers)
+    ref = rom.leapfrog(rom.reduced_columns(rs), rom.reduced_columns(rr), w, dt)
+    h = _handle(S)
+    try:
+        P.setup(h, wl)
+        S.sfrom_build(h, wl.m, wl.shift, S.SFROM_F64)
+        for i, (Gh, G) in blocks.items():
+            S.sfrom_import_rom(h, i, np.array(Gh), np.array(G))
+        tr = np.zeros(ref.shape)
+        S.sfrom_run(h, len(w), dt, w, tr)
+    finally:
+        S.sfrom_destroy(h)
+    e = rel(tr, ref)
+    print("on-line FP64 rel L2 vs oracle", e)
+    assert e <= 1e-12
+
+
+def test_end_to_end_fp64_small(dev):
+    """32^3 voxels, 4^3 cells, one source, 64 receivers, 1500 steps at half
+    the fine CFL limit: GPU build + run against oracle build + run (1e-10),
+    and GPU ROM against GPU fine grid within the method's error."""
+    S, P = _lib()
+    wl = synth.workload("small", modes_face=9, modes_edge=3, m=3)
+    run = pipeline.setup(wl)
+    pipeline.build_all(run)
+    ref = pipeline.rom_traces(run)
+    tr, _, _ = _gpu_rom(wl, S.SFROM_F64, run.dt, run.w)
+    e = rel(tr, ref)
+    print("end-to-end FP64 rel L2 vs oracle", e)
+    assert e <= 1e-10
+    fref = pipeline.fine_traces(run)
+    print("ROM vs fine (method error)", rel(tr, fref))
+    assert rel(tr, fref) <= 1e-3
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def test_fine_grid_matches_oracle(dev, prec, tol):
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, n_steps=300)
+    run = pipeline.setup(wl)
+    ref = pipeline.fine_traces(run)
+    h = _handle(S)
+    try:
+        P.setup(h, wl)
+        tr = np.zeros(ref.shape, np.float64 if prec == 0 else np.float32)
+        S.sfrom_fine_run(h, len(run.w), run.dt, run.w, tr, prec)
+        lam = S.sfrom_fine_lambda_max(h)
+    finally:
+        S.sfrom_destroy(h)
+    e = rel(tr, ref)
+    print("fine prec", prec, "rel L2", e)
+    assert e <= tol
+    assert abs(lam - fine.lambda_max(run.A, run.b)) <= 1e-9 * lam
+
+
+def test_fp32_rom_multi_source(dev):
+    """FP32 on-line stepping of the FP64-built ROM, 16 sources on the skeleton,
+    against the FP64 oracle ROM (1e-4)."""
+    S, P = _lib()
+    wl = synth.workload("small", modes_face=4, modes_edge=2, m=3, n_steps=800)
+    fi = synth.face_interior_nodes(wl.nvox, wl.cuts)
+    rng = np.random.default_rng(9)
+    wl.sources = fi[np.sort(rng.choice(len(fi), 16, replace=False))]
+    run = pipeline.setup(wl)
+    pipeline.build_all(run)
+    ref = pipeline.rom_traces(run)
+    tr, _, _ = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w)
+    e = rel(tr, ref)
+    print("FP32 rel L2 vs oracle", e)
+    assert e <= 1e-4
+
+
+def test_uneven_layers_per_cell(dev):
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3, n_steps=300)
+    run = pipeline.setup(wl)
+    mpc = np.array([2 + (i % 3) for i in range(8)], np.int32)
+    part, sigma, rho = run.part, wl.sigma, wl.rho
+    for i in range(len(part.cells)):
+        Ai, bi = part.cell_operator(i, sigma, rho)
+        run.blocks[i] = build_cell(Ai, bi, part.cell_W(i), wl.shift, int(mpc[i]))
+    ref = pipeline.rom_traces(run)
+    tr, _, _ = _gpu_rom(wl, S.SFROM_F64, run.dt, run.w, m_per_cell=mpc)
+    assert rel(tr, ref) <= 1e-10
+
+
+def test_breakdown_is_reported(dev):
+    """A partition whose Krylov blocks lose rank (a corner node with no
+    interior neighbour in a 2D slab, m = 2) must fail with EBREAKDOWN."""
+    S, P = _lib()
+    rng = np.random.default_rng(1)
+    nvox = (6, 8, 2)
+    wl = synth.Workload("slab4", nvox, 4.0 ** rng.uniform(0, 1, nvox), rng.uniform(1, 2, nvox),
+                        (np.array([3]), np.array([4]), np.array([], dtype=np.int64)), 2, 100, 100,
+                        np.array([[3, 2, 1]]), np.array([[3, 1, 1]]), 10, 0.05, 1.0, -0.02)
+    h = _handle(S)
+    try:
+        P.setup(h, wl)
+        with pytest.raises(S.SfromError) as e:
+            S.sfrom_build(h, 2, -0.02, S.SFROM_F64)
+        assert e.value.name == "EBREAKDOWN"
+    finally:
+        S.sfrom_destroy(h)
+
+
+def test_runs_are_bitwise_deterministic(dev):
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3, n_steps=200)
+    run = pipeline.setup(wl)
+    a, _, _ = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w)
+    b, _, _ = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w)
+    assert np.array_equal(a, b)
