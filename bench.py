@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-scale S-fraction ROM on one MI355X.
+
+One bench step is one whole job of the hot path on inputs resident in HBM:
+the off-line build of every cell's S-fraction (banded Cholesky, rational
+block Krylov, projection, block Lanczos, S-fraction recursion, piece masses)
+followed by the on-line leapfrog of all time steps for all sources with
+receiver traces written to device memory. ``value`` is the job's
+source-steps/s (sources x time steps / job time). The fine-grid leapfrog of
+the same pencil (same dt, same sources/receivers) is timed beside it, and
+the ROM traces of the timed job are compared with an FP64 fine-grid run.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "source-steps/s, ROM vs fine-grid leapfrog, at ≤1e-3 receiver rel-L2 error"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_cost(S, h, ns, prec):
+    """Algorithmic bytes and flops of one cell-phase launch: every block read
+    once, hidden layers read twice and written once, the cell's Phi^1 slice
+    written once, the piece dofs read once (unique), all for n_s sources."""
+    info = S.sfrom_get_info(h)
+    eb_state = 8 if prec == "f64" else 4
+    eb_blk = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    blocks = hidden = u1 = flops = 0
+    m = info["max_m"]
+    for i in range(info["n_cells"]):
+        b = _cell_b(S, h, i)
+        blocks += (2 * m - 1) * b * b
+        hidden += (m - 1) * b
+        u1 += b
+        flops += 2 * (2 * m - 1) * b * b * ns
+    bytes_ = blocks * eb_blk + (3 * hidden + u1) * ns * eb_state + info["n_piece_dofs"] * ns * eb_state
+    return bytes_, flops
+
+
+def _cell_b(S, h, i):
+    import ctypes as C
+    n = C.c_int32(); nnz = C.c_int32(); bd = C.c_int32()
+    rc = S._lib.sfrom_export_cell(h, i, C.byref(n), C.byref(nnz), C.byref(bd), None, None, None, None, None)
+    if rc != 0:
+        raise S.SfromError(rc, S.sfrom_last_error(h))
+    return bd.value
+
+
+def traffic_from_profiles(kernel_file, workload):
+    """HBM bytes per launch measured by rocprofv3 PMC counters (committed
+    summary), valid only while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", f"cell_phase_{workload}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(kernel_file, "rb").read()).hexdigest()
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("-"):
+            k, v = line.strip()[1:].split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(args, ns_target, nsteps_target, ncells_target, budget_s):
+    """The FP64 oracle timed on the host cores on a bounded sample of the same
+    workload: off-line build of the cells of a 32^3-voxel sub-block (4^3
+    cells of 8^3) of the same medium generator, and a few global-ROM leapfrog
+    steps there with n_s sources; both scaled linearly to the full cell count
+    and number of time steps."""
+    import synth
+    from oracle import pipeline
+    wl = synth.workload("small", modes_face=args.modes_face, modes_edge=args.modes_edge, m=args.m)
+    fi = synth.face_interior_nodes(wl.nvox, wl.cuts)
+    rng = np.random.default_rng(5)
+    wl.sources = fi[np.sort(rng.choice(len(fi), ns_target, replace=False))]
+    big = synth.workload(args.workload, modes_face=args.modes_face, modes_edge=args.modes_edge, m=args.m)
+    wl.sigma = big.sigma[:32, :32, :32].copy()
+    wl.rho = big.rho[:32, :32, :32].copy()
+    run = pipeline.setup(wl, n_steps=8)
+    t0 = time.perf_counter()
+    pipeline.build_all(run)
+    t_build = time.perf_counter() - t0
+    ncell = len(run.part.cells)
+    from oracle.rom_global import GlobalROM
+    rom = GlobalROM(run.part, run.blocks)
+    F = rom.reduced_columns(run.red_src)
+    Qr = rom.reduced_columns(run.red_rec)
+    nsteps = 4
+    while True:
+        t0 = time.perf_counter()
+        rom.leapfrog(F, Qr, run.w[:nsteps] if nsteps <= len(run.w) else np.resize(run.w, nsteps), run.dt)
+        t_step = (time.perf_counter() - t0) / nsteps
+        if t_build + t_step * nsteps * 2 > budget_s or nsteps >= 64:
+            break
+        nsteps *= 2
+    job = t_build / ncell * ncells_target + t_step / ncell * ncells_target * nsteps_target
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": ns_target * nsteps_target / job,
+        "unit": "source-steps/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"numpy/scipy FP64 oracle on a 32^3-voxel sub-block ({ncell} cells of 8^3) of the same "
+                   f"medium: off-line build of all {ncell} cells ({t_build:.1f} s) and {nsteps} global-ROM "
+                   f"leapfrog steps with {ns_target} sources ({t_step * 1e3:.0f} ms/step), scaled linearly "
+                   f"to {ncells_target} cells and {nsteps_target} steps; BLAS threads = {cores}, sparse "
+                   f"products single-threaded"),
+        "build_s_per_cell": t_build / ncell,
+        "online_s_per_cell_step": t_step / ncell,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--time-steps", type=int, default=None, help="leapfrog steps per job (default: workload)")
+    ap.add_argument("--m", type=int, default=3)
+    ap.add_argument("--modes-face", type=int, default=16)
+    ap.add_argument("--modes-edge", type=int, default=3)
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB float32 device copy (for PMC byte calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of "
+              "this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1604_06750_amd import problem, sfrom as S
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    prec = {"f64": S.SFROM_F64, "f32": S.SFROM_F32, "bf16": S.SFROM_BF16}[args.prec]
+    tdt = torch.float64 if args.prec == "f64" else torch.float32
+
+    wl = synth.workload(args.workload, modes_face=args.modes_face, modes_edge=args.modes_edge, m=args.m)
+    nt = args.time_steps or wl.n_steps
+    log(f"[bench] workload {args.workload}: {wl.nvox} voxels, m={args.m}, modes {args.modes_face}/{args.modes_edge}, "
+        f"{len(wl.sources)} sources, {len(wl.receivers)} receivers, {nt} steps, {args.prec}")
+    h = S.sfrom_create(0, stream.cuda_stream)
+    t0 = time.perf_counter()
+    problem.setup(h, wl)
+    lam = S.sfrom_fine_lambda_max(h)
+    dt = wl.cfl_fraction * 2.0 / np.sqrt(lam)
+    info = S.sfrom_get_info(h)
+    ns, nr = info["n_sources"], info["n_receivers"]
+    log(f"[bench] set-up {time.perf_counter() - t0:.1f} s; n={info['n']}, cells={info['n_cells']}, "
+        f"pieces={info['n_pieces']}, dt={dt:.5f}")
+    w = torch.tensor(synth.ricker(nt, dt, wl.f_p), dtype=torch.float64, device=dev)
+    tr = torch.zeros((nt, nr, ns), dtype=tdt, device=dev)
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def job():
+        S.sfrom_build(h, args.m, wl.shift, prec)
+        S.sfrom_reset(h)
+        S.sfrom_run(h, nt, dt, w, tr)
+
+    for i in range(args.warmup):
+        job()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    S.sfrom_profile(h, True)
+    for k in range(4):
+        S.sfrom_profile_read(h, k)
+    build_ms = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        job()
+        build_ms.append(S.sfrom_get_info(h)["build_ms"])
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    cell_ms, cell_n = S.sfrom_profile_read(h, S.KERNEL_CELL)
+    piece_ms, piece_n = S.sfrom_profile_read(h, S.KERNEL_PIECE)
+    rec_ms, rec_n = S.sfrom_profile_read(h, S.KERNEL_RECEIVERS)
+    S.sfrom_profile(h, False)
+    log(f"[bench] {args.steps} timed jobs done in {t_total:.2f} s")
+    ms_per_step = t_total / args.steps * 1e3
+    value = ns * nt / (ms_per_step / 1e3)
+
+    # on-line part alone (events around the on-line loop)
+    S.sfrom_reset(h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    S.sfrom_run(h, nt, dt, w, tr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    online_ms = e0.elapsed_time(e1)
+    rom_tr = tr.double().cpu().numpy()
+
+    # fine-grid comparator (same dt), timed in the on-line precision
+    S.sfrom_fine_reset(h)
+    tf = torch.zeros((nt, nr, ns), dtype=tdt if args.prec != "bf16" else torch.float32, device=dev)
+    fprec = S.SFROM_F64 if args.prec == "f64" else S.SFROM_F32
+    S.sfrom_fine_run(h, min(nt, 200), dt, w, tf, fprec)   # warm-up
+    S.sfrom_fine_reset(h)
+    S.sfrom_profile(h, True)
+    S.sfrom_profile_read(h, S.KERNEL_FINE)
+    e0.record(stream)
+    S.sfrom_fine_run(h, nt, dt, w, tf, fprec)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fine_ms = e0.elapsed_time(e1)
+    fine_kms, fine_kn = S.sfrom_profile_read(h, S.KERNEL_FINE)
+    S.sfrom_profile(h, False)
+    # accuracy reference: FP64 fine grid
+    S.sfrom_fine_reset(h)
+    t64 = torch.zeros((nt, nr, ns), dtype=torch.float64, device=dev)
+    S.sfrom_fine_run(h, nt, dt, w, t64, S.SFROM_F64)
+    torch.cuda.synchronize()
+    ref = t64.cpu().numpy()
+    rel_l2 = float(np.linalg.norm(rom_tr - ref) / np.linalg.norm(ref))
+
+    # roofline of the dominant kernel (on-line cell phase)
+    bytes_, flops = algorithmic_cost(S, h, ns, args.prec)
+    avg_ms = cell_ms / max(cell_n, 1)
+    bw = bytes_ / (avg_ms * 1e-3) / 1e9
+    tf_s = flops / (avg_ms * 1e-3) / 1e12
+    peak_tf = MFMA_PEAK_TFLOPS[args.prec]
+    intensity = flops / bytes_
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_1604_06750_amd", "csrc", "online.hip"), args.workload)
+    if intensity < ridge:
+        roofline = {"bound": "hbm", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(bw / HBM_PEAK_GBS, 4), "traffic": traffic}
+    else:
+        roofline = {"bound": "mfma", "achieved": round(tf_s, 2), "peak": peak_tf, "unit": "TFLOP/s",
+                    "frac": round(tf_s / peak_tf, 4), "traffic": traffic}
+    roofline.update({"kernel": "k_cell_phase", "avg_launch_ms": round(avg_ms, 4), "launches": cell_n,
+                     "algorithmic_bytes_per_launch": int(bytes_), "algorithmic_flops_per_launch": int(flops),
+                     "hbm_gbs_at_algorithmic_bytes": round(bw, 1)})
+
+    fine_ssps = ns * nt / (fine_ms / 1e3)
+    online_ssps = ns * nt / (online_ms / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "source-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"3D acoustic, {wl.nvox[0]}x{wl.nvox[1]}x{wl.nvox[2]} voxels, "
+                         f"{info['n_cells']} cells of 8^3, m={args.m}, {args.modes_face} face + "
+                         f"{args.modes_edge} edge + 1 corner modes per piece, {ns} sources, {nr} receivers, "
+                         f"{nt} leapfrog steps at 0.5 fine CFL; job = off-line build + on-line run"),
+            "n_fine": info["n"], "n_cells": info["n_cells"], "n_pieces": info["n_pieces"],
+            "rom_dofs": info["n_piece_dofs"] + info["n_hidden_dofs"], "max_b": info["max_b"],
+        },
+        "roofline": roofline,
+        "rel_l2_vs_fine_fp64": rel_l2,
+        "build_ms": round(float(np.mean(build_ms)), 2),
+        "online_ms": round(online_ms, 2),
+        "online_source_steps_per_s": round(online_ssps, 1),
+        "fine_ms": round(fine_ms, 2),
+        "fine_source_steps_per_s": round(fine_ssps, 1),
+        "speedup_job_vs_fine": round(value / fine_ssps, 3),
+        "speedup_online_vs_fine": round(online_ssps / fine_ssps, 3),
+        "kernel_avg_ms": {"cell_phase": round(avg_ms, 4), "piece_phase": round(piece_ms / max(piece_n, 1), 4),
+                          "receivers": round(rec_ms / max(rec_n, 1), 4),
+                          "fine_step": round(fine_kms / max(fine_kn, 1), 4)},
+    }
+    S.sfrom_destroy(h)
+    if not args.no_cpu:
+        log("[bench] timing the oracle on the host cores")
+        out["cpu_baseline"] = cpu_baseline(args, ns, nt, info["n_cells"], args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -202,6 +202,14 @@ int sfrom_fine_lambda_max(sfrom_t* h, double* lambda);
 /* Largest eigenvalue of the global ROM pencil (-L, D); needs a built ROM. */
 int sfrom_rom_lambda_max(sfrom_t* h, double* lambda);
 
+/* Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch while enabled. Kernel ids: 0 on-line cell phase, 1 on-line
+ * piece phase, 2 receivers, 3 fine-grid step. sfrom_profile_read
+ * synchronises the stream, returns the summed kernel time and the number of
+ * launches since the last read, and clears them. */
+int sfrom_profile(sfrom_t* h, int32_t enable);
+int sfrom_profile_read(sfrom_t* h, int32_t kernel, double* total_ms, int64_t* launches);
+
 /* ---------------------------------------------------------------------------
  * Introspection
  * ------------------------------------------------------------------------ */

@@ -97,10 +97,61 @@ void free_fine(sfrom_t* h) {
 
 void free_all(sfrom_t* h) {
   if (h->device < 0) return;
+  for (int k = 0; k < 4; ++k)
+    for (auto& pr : h->ev_pending[k]) { h->ev_pool.push_back(pr.first); h->ev_pool.push_back(pr.second); }
+  for (auto e : h->ev_pool) hipEventDestroy(e);
+  h->ev_pool.clear();
+  for (int k = 0; k < 4; ++k) h->ev_pending[k].clear();
   free_rom(h);
   free_fine(h);
   dfree(h->d_w);
   h->d_w_cap = 0;
+}
+
+// ---------------------------------------------------------------------------
+// optional per-kernel event timing
+// ---------------------------------------------------------------------------
+
+hipEvent_t take_event(sfrom_t* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+template <typename F>
+void timed(sfrom_t* h, int kid, F&& launch) {
+  if (!h->profiling) {
+    HIPCHK(launch());
+    return;
+  }
+  hipEvent_t a = take_event(h), b = take_event(h);
+  HIPCHK(hipEventRecord(a, h->stream));
+  HIPCHK(launch());
+  HIPCHK(hipEventRecord(b, h->stream));
+  h->ev_pending[kid].push_back({a, b});
+}
+
+void collect_events(sfrom_t* h) {
+  bool any = false;
+  for (int k = 0; k < 4; ++k) any |= !h->ev_pending[k].empty();
+  if (!any) return;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int k = 0; k < 4; ++k) {
+    for (auto& pr : h->ev_pending[k]) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+      h->prof_ms[k] += ms;
+      h->prof_n[k] += 1;
+      h->ev_pool.push_back(pr.first);
+      h->ev_pool.push_back(pr.second);
+    }
+    h->ev_pending[k].clear();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -606,8 +657,11 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
     a.y_cur = h->d_y[h->cur]; a.y_old = h->d_y[1 - h->cur];
     a.h_cur = h->d_h[h->cur]; a.h_old = h->d_h[1 - h->cur];
     a.step = s; a.trace_step = s;
-    HIPCHK(launch_online_step(a, h->stream));
+    timed(h, 0, [&] { return launch_cell_phase(a, h->stream); });
+    timed(h, 1, [&] { return launch_piece_phase(a, h->stream); });
+    timed(h, 2, [&] { return launch_receivers(a, h->stream); });
     h->cur = 1 - h->cur;
+    if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
   }
   if (own) {
     HIPCHK(hipMemcpyAsync(traces, d_tr, tbytes, hipMemcpyDeviceToHost, h->stream));
@@ -696,8 +750,9 @@ void fine_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_
   for (int64_t s = 0; s < n_steps; ++s) {
     a.u_cur = h->d_u[h->fcur]; a.u_old = h->d_u[1 - h->fcur];
     a.step = s; a.trace_step = s;
-    HIPCHK(launch_fine_step(a, h->stream));
+    timed(h, 3, [&] { return launch_fine_step(a, h->stream); });
     h->fcur = 1 - h->fcur;
+    if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
   }
   if (own) {
     HIPCHK(hipMemcpyAsync(traces, d_tr, tbytes, hipMemcpyDeviceToHost, h->stream));
@@ -1225,6 +1280,25 @@ int sfrom_rom_lambda_max(sfrom_t* h, double* lambda) {
     apply_msq(t2.data(), y);
   };
   *lambda = lanczos_max(ndof, mv);
+  API_END(h)
+}
+
+int sfrom_profile(sfrom_t* h, int32_t enable) {
+  API_BEGIN(h)
+  REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
+  collect_events(h);
+  h->profiling = enable != 0;
+  API_END(h)
+}
+
+int sfrom_profile_read(sfrom_t* h, int32_t kernel, double* total_ms, int64_t* launches) {
+  API_BEGIN(h)
+  REQUIRE(kernel >= 0 && kernel < 4 && total_ms && launches, SFROM_EINVAL, "bad kernel id");
+  if (h->device >= 0) collect_events(h);
+  *total_ms = h->prof_ms[kernel];
+  *launches = h->prof_n[kernel];
+  h->prof_ms[kernel] = 0.0;
+  h->prof_n[kernel] = 0;
   API_END(h)
 }
 

@@ -163,13 +163,23 @@ int cell_tile(const StepArgs& a, size_t acc_bytes) {
 }
 
 template <typename T, typename TB, typename TA>
-static hipError_t step_impl(const StepArgs& a, hipStream_t st) {
+static hipError_t cell_impl(const StepArgs& a, hipStream_t st) {
   const int nst = cell_tile(a, sizeof(TA));
   const size_t lds = 2 * (size_t)a.max_m * a.max_b * nst * sizeof(TA);
   const dim3 g1(a.ncell, (a.ns + nst - 1) / nst);
   hipLaunchKernelGGL((k_cell_phase<T, TB, TA>), g1, dim3(CELL_NT), lds, st, a, nst);
+  return hipGetLastError();
+}
+
+template <typename T, typename TA>
+static hipError_t piece_impl(const StepArgs& a, hipStream_t st) {
   const int64_t np = (int64_t)a.npiece * a.ns;
   hipLaunchKernelGGL((k_piece_phase<T, TA>), dim3((np + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, typename TA>
+static hipError_t rec_impl(const StepArgs& a, hipStream_t st) {
   if (a.nrec > 0) {
     const int64_t nr = (int64_t)a.nrec * a.ns;
     hipLaunchKernelGGL((k_receivers<T, TA>), dim3((nr + 255) / 256), dim3(256), 0, st, a);
@@ -177,10 +187,28 @@ static hipError_t step_impl(const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st) {
+  if (a.prec == SFROM_F64) return cell_impl<double, double, double>(a, st);
+  if (a.prec == SFROM_F32) return cell_impl<float, float, float>(a, st);
+  return cell_impl<float, __hip_bfloat16, float>(a, st);
+}
+
+hipError_t launch_piece_phase(const StepArgs& a, hipStream_t st) {
+  if (a.prec == SFROM_F64) return piece_impl<double, double>(a, st);
+  return piece_impl<float, float>(a, st);
+}
+
+hipError_t launch_receivers(const StepArgs& a, hipStream_t st) {
+  if (a.prec == SFROM_F64) return rec_impl<double, double>(a, st);
+  return rec_impl<float, float>(a, st);
+}
+
 hipError_t launch_online_step(const StepArgs& a, hipStream_t st) {
-  if (a.prec == SFROM_F64) return step_impl<double, double, double>(a, st);
-  if (a.prec == SFROM_F32) return step_impl<float, float, float>(a, st);
-  return step_impl<float, __hip_bfloat16, float>(a, st);
+  hipError_t e = launch_cell_phase(a, st);
+  if (e != hipSuccess) return e;
+  e = launch_piece_phase(a, st);
+  if (e != hipSuccess) return e;
+  return launch_receivers(a, st);
 }
 
 }  // namespace sfrom_impl

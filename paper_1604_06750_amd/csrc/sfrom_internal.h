@@ -161,6 +161,10 @@ struct StepArgs {
   int64_t trace_step;            // which slice to write
 };
 hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
+// the three parts of a step, for per-kernel timing
+hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st);
+hipError_t launch_piece_phase(const StepArgs& a, hipStream_t st);
+hipError_t launch_receivers(const StepArgs& a, hipStream_t st);
 
 // Fine-grid leapfrog step (CSR).
 struct FineArgs {
@@ -271,4 +275,12 @@ struct sfrom {
   int64_t* d_frec_row = nullptr;
   double* d_frec_val = nullptr;
   bool fine_io_dirty = true;
+
+  // optional per-kernel timing with HIP events (kernel ids: 0 cell phase,
+  // 1 piece phase, 2 receivers, 3 fine step)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[4];
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_n[4] = {0, 0, 0, 0};
 };

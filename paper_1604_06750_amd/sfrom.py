@@ -73,6 +73,8 @@ _SIGS = {
     "sfrom_fine_lambda_max": [_P, C.POINTER(C.c_double)],
     "sfrom_rom_lambda_max": [_P, C.POINTER(C.c_double)],
     "sfrom_get_info": [_P, C.POINTER(sfrom_info)],
+    "sfrom_profile": [_P, C.c_int32],
+    "sfrom_profile_read": [_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "sfrom_export_pencil": [_P, _P, _P, _P, _P],
     "sfrom_export_cell": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                           _P, _P, _P, _P, _P],
@@ -264,6 +266,20 @@ def sfrom_rom_lambda_max(h) -> float:
     v = C.c_double()
     _check(h, _lib.sfrom_rom_lambda_max(h, C.byref(v)))
     return v.value
+
+
+def sfrom_profile(h, enable=True):
+    _check(h, _lib.sfrom_profile(h, int(enable)))
+
+
+KERNEL_CELL, KERNEL_PIECE, KERNEL_RECEIVERS, KERNEL_FINE = 0, 1, 2, 3
+
+
+def sfrom_profile_read(h, kernel):
+    """(total_ms, launches) of kernel id since the last read."""
+    ms = C.c_double(); n = C.c_int64()
+    _check(h, _lib.sfrom_profile_read(h, kernel, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def sfrom_get_info(h) -> dict:
