@@ -229,6 +229,8 @@ typedef struct {
   int32_t online_prec;
   int64_t block_bytes;     /* on-line S-fraction storage           */
   double build_ms;         /* last sfrom_build wall time          */
+  int32_t cell_variant;    /* autotuned on-line cell-phase kernel variant of the last
+                              run (0-3 matrix-core tilings, 4 scalar; -1 before)    */
 } sfrom_info;
 
 int sfrom_get_info(const sfrom_t* h, sfrom_info* info);

@@ -88,6 +88,7 @@ void free_rom(sfrom_t* h) {
 }
 
 void free_fine(sfrom_t* h) {
+  dfree(h->d_stencil);
   dfree(h->d_frowptr); dfree(h->d_fcol); dfree(h->d_fa); dfree(h->d_fbinv);
   dfree(h->d_u[0]); dfree(h->d_u[1]);
   dfree(h->d_fsrc_row); dfree(h->d_fsrc_col); dfree(h->d_fsrc_val);
@@ -343,10 +344,12 @@ void build(sfrom_t* h, const sfrom_build_opts* o) {
     OnlineCell& oc = h->ocells[i];
     oc.m = h->cell_m[i];
     oc.b = h->cell_b[i];
+    oc.ld = (oc.b + 3) / 4 * 4;
+    oc.pad_ = 0;
     oc.blk_off = blk;
     oc.hid_off = hid;
     oc.u1_off = u1;
-    blk += (int64_t)(2 * oc.m - 1) * oc.b * oc.b;
+    blk += (int64_t)(2 * oc.m - 1) * oc.b * oc.ld;
     hid += (int64_t)(oc.m - 1) * oc.b;
     u1 += oc.b;
     h->rom64_off[i] = r64;
@@ -615,6 +618,57 @@ void prepare_online(sfrom_t* h) {
   }
 }
 
+// Autotuner of the cell phase: on the first run for a given (precision,
+// max b, max m, n_s), every kernel variant is timed over a few launches on
+// scratch copies of the state (the real state is not touched) and the
+// fastest is kept for the life of the handle.
+int autotune_cell(sfrom_t* h, StepArgs a) {
+  const auto key = std::make_tuple(a.prec, a.max_b, a.max_m, a.ns);
+  auto it = h->tuned.find(key);
+  if (it != h->tuned.end()) return it->second;
+  const int nv = cell_variants(a);
+  if (nv <= 1) { h->tuned[key] = 0; return 0; }
+  const size_t eb = prec_bytes(h->prec);
+  const int64_t npd = h->piece_dof_off.back();
+  int64_t nu1 = 0;
+  for (auto& oc : h->ocells) nu1 += oc.b;
+  const size_t ybytes = (size_t)npd * a.ns * eb;
+  const size_t hbytes = (size_t)std::max<int64_t>(h->n_hidden_dofs, 1) * a.ns * eb;
+  const size_t pbytes = (size_t)nu1 * a.ns * eb;
+  void* sy = dalloc<unsigned char>(h, ybytes);
+  void* sh0 = dalloc<unsigned char>(h, hbytes);
+  void* sh1 = dalloc<unsigned char>(h, hbytes);
+  void* sp = dalloc<unsigned char>(h, pbytes);
+  HIPCHK(hipMemcpyAsync(sy, h->d_y[h->cur], ybytes, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(sh0, h->d_h[h->cur], hbytes, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(sh1, h->d_h[1 - h->cur], hbytes, hipMemcpyDeviceToDevice, h->stream));
+  a.y_cur = sy; a.h_cur = sh0; a.h_old = sh1; a.phi = sp;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int v = 0; v < nv; ++v) {
+    a.cell_variant = v;
+    HIPCHK(launch_cell_phase(a, h->stream));      // warm-up (code object load)
+    HIPCHK(hipEventRecord(e0, h->stream));
+    const int reps = 4;
+    for (int r = 0; r < reps; ++r) HIPCHK(launch_cell_phase(a, h->stream));
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) { best_ms = ms; best = v; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  dfree(sy); dfree(sh0); dfree(sh1); dfree(sp);
+  h->tuned[key] = best;
+  h->tuned_variant = best;
+  h->tuned_ms = best_ms / 4;
+  return best;
+}
+
 const double* stage_w(sfrom_t* h, int64_t n_steps, const double* w, int w_on_device) {
   if (w_on_device) return w;
   if (h->d_w_cap < n_steps) {
@@ -647,12 +701,15 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   a.ns = ns; a.nrec = nr; a.prec = h->prec;
   a.max_b = 0; a.max_m = 0;
   for (auto& oc : h->ocells) { a.max_b = std::max(a.max_b, oc.b); a.max_m = std::max(a.max_m, oc.m); }
+  a.max_bp = 0;
+  for (auto& op : h->opieces) { a.max_bp = std::max(a.max_bp, op.b); REQUIRE(op.ncell <= 8, SFROM_EINVAL, "a piece is shared by more than 8 cells"); }
   a.dt2 = dt * dt;
   a.d_cells = h->d_ocells; a.d_pieces = h->d_opieces; a.d_gather = h->d_gather; a.d_inc = h->d_inc;
   a.d_blocks = h->d_blocks; a.d_minv = h->d_minv; a.d_src = h->d_src;
   a.phi = h->d_phi; a.w = d_w;
   a.d_rptr = h->d_rptr; a.d_rrow = h->d_rrow; a.d_rval = h->d_rval;
   a.traces = d_tr;
+  a.cell_variant = autotune_cell(h, a);
   for (int64_t s = 0; s < n_steps; ++s) {
     a.y_cur = h->d_y[h->cur]; a.y_old = h->d_y[1 - h->cur];
     a.h_cur = h->d_h[h->cur]; a.h_old = h->d_h[1 - h->cur];
@@ -694,6 +751,15 @@ void prepare_fine(sfrom_t* h, int prec) {
       std::vector<float> af(h->a.begin(), h->a.end()), bf(binv.begin(), binv.end());
       h->d_fa = dupload(h, af);
       h->d_fbinv = dupload(h, bf);
+    }
+    dfree(h->d_stencil);
+    if (!h->stencil.empty()) {
+      if (prec == SFROM_F64) {
+        h->d_stencil = dupload(h, h->stencil);
+      } else {
+        std::vector<float> sf(h->stencil.begin(), h->stencil.end());
+        h->d_stencil = dupload(h, sf);
+      }
     }
     h->fine_prec = prec;
     h->fine_ns = -1;
@@ -743,6 +809,8 @@ void fine_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_
   FineArgs a;
   a.n = h->n; a.ns = ns; a.nrec = nr; a.prec = prec; a.dt2 = dt * dt;
   a.rowptr = h->d_frowptr; a.col = h->d_fcol; a.a = h->d_fa; a.binv = h->d_fbinv;
+  a.stencil = h->d_stencil;
+  a.ux = h->grid_u[0]; a.uy = h->grid_u[1]; a.uz = h->grid_u[2];
   a.w = d_w;
   a.nsrc_entries = h->fsrc_n; a.src_row = h->d_fsrc_row; a.src_col = h->d_fsrc_col; a.src_val = h->d_fsrc_val;
   a.rec_ptr = h->d_frec_ptr; a.rec_row = h->d_frec_row; a.rec_val = h->d_frec_val;
@@ -912,6 +980,8 @@ int sfrom_set_pencil(sfrom_t* h, int64_t n, const int64_t* rowptr, const int32_t
   h->cells.clear();
   h->pieces.clear();
   h->part_ready = false;
+  h->stencil.clear();
+  h->grid_u[0] = h->grid_u[1] = h->grid_u[2] = 0;
   h->src = Columns();
   h->rec = Columns();
   API_END(h)
@@ -1013,10 +1083,15 @@ int sfrom_import_rom(sfrom_t* h, int32_t cell, int32_t m, int32_t b, const doubl
         REQUIRE(Ghat[u] == Ghat[v] && G[u] == G[v], SFROM_ENOTSPD, "blocks must be symmetric");
       }
   HIPCHK(hipMemcpy(h->d_rom64 + h->rom64_off[cell], r64.data(), r64.size() * sizeof(double), hipMemcpyHostToDevice));
-  // on-line layout: G^1..G^m, Ghat^2..Ghat^m
-  std::vector<double> blk((2 * m - 1) * bb2);
-  for (int64_t k = 0; k < m * bb2; ++k) blk[k] = G[k];
-  for (int64_t k = 0; k < (m - 1) * bb2; ++k) blk[m * bb2 + k] = Ghat[bb2 + k];
+  // on-line layout: G^1..G^m, Ghat^2..Ghat^m, each b x ld (row stride ld, zero padded)
+  const int ld = oc.ld;
+  const int64_t bsz = (int64_t)b * ld;
+  std::vector<double> blk((2 * m - 1) * bsz, 0.0);
+  for (int k = 0; k < 2 * m - 1; ++k) {
+    const double* src = (k < m) ? G + k * bb2 : Ghat + (k - m + 1) * bb2;
+    for (int r = 0; r < b; ++r)
+      for (int c = 0; c < b; ++c) blk[k * bsz + (int64_t)r * ld + c] = src[r + (int64_t)c * b];
+  }
   const size_t eb = block_bytes(h->prec);
   unsigned char* dst = reinterpret_cast<unsigned char*>(h->d_blocks) + (size_t)oc.blk_off * eb;
   if (h->prec == SFROM_F64) {
@@ -1320,6 +1395,7 @@ int sfrom_get_info(const sfrom_t* hc, sfrom_info* info) {
   info->online_prec = h->prec;
   info->block_bytes = h->built ? h->block_elems * (int64_t)block_bytes(h->prec) : 0;
   info->build_ms = h->build_ms;
+  info->cell_variant = h->tuned_variant;
   return SFROM_OK;
 }
 

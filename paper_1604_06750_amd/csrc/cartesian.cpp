@@ -169,6 +169,28 @@ extern "C" int sfrom_setup_voxel_acoustic(sfrom_t* h, const int32_t nvox[3], con
   const int64_t n = (int64_t)b.size();
   int rc = sfrom_set_pencil(h, n, rp.data(), col.data(), a.data(), b.data());
   if (rc != SFROM_OK) return rc;
+  // 7-point form of the same operator for the fine-grid comparator
+  {
+    const int ux = g.nx - 1, uy = g.ny - 1, uz = g.nz - 1;
+    std::vector<double> st((size_t)n * 8, 0.0);
+    for (int z = 1; z < g.nz; ++z)
+      for (int y = 1; y < g.ny; ++y)
+        for (int x = 1; x < g.nx; ++x) {
+          const int64_t k = g.gidx(x, y, z);
+          const int64_t nbr[6] = {x > 1 ? k - 1 : -1, x < g.nx - 1 ? k + 1 : -1,
+                                  y > 1 ? k - ux : -1, y < g.ny - 1 ? k + ux : -1,
+                                  z > 1 ? k - (int64_t)ux * uy : -1, z < g.nz - 1 ? k + (int64_t)ux * uy : -1};
+          for (int64_t e = rp[k]; e < rp[k + 1]; ++e) {
+            const int64_t c = col[e];
+            if (c == k) { st[k * 8 + 6] = a[e]; continue; }
+            for (int d = 0; d < 6; ++d)
+              if (nbr[d] == c) st[k * 8 + d] = a[e];
+          }
+          st[k * 8 + 7] = 1.0 / b[k];
+        }
+    h->stencil = std::move(st);
+    h->grid_u[0] = ux; h->grid_u[1] = uy; h->grid_u[2] = uz;
+  }
   // ---- cells ---------------------------------------------------------------------
   std::array<std::vector<int>, 3> edge;
   const int nvx[3] = {g.nx, g.ny, g.nz};

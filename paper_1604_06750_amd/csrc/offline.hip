@@ -575,7 +575,8 @@ __device__ inline float cvt<float>(double v) { return (float)v; }
 template <>
 __device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
 
-// Blocks per cell in the on-line layout: G^1..G^m, then Ghat^2..Ghat^m.
+// Blocks per cell in the on-line layout: G^1..G^m, then Ghat^2..Ghat^m, each
+// b rows of stride ld.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_pack(const BuildCell* bc, const double* work,
                                              const OnlineCell* oc, T* blocks, double* rom64,
@@ -587,9 +588,17 @@ __global__ __launch_bounds__(NT) void k_pack(const BuildCell* bc, const double* 
   const double* src = work + c.out_off;
   double* r64 = rom64 + rom64_off[blockIdx.x];
   for (int64_t idx = threadIdx.x; idx < 2 * m * bb2; idx += NT) r64[idx] = src[idx];
+  // b x ld blocks (row stride ld, zero padding); the blocks are symmetric, so
+  // rows and columns coincide
   T* dst = blocks + o.blk_off;
-  for (int64_t idx = threadIdx.x; idx < m * bb2; idx += NT) dst[idx] = cvt<T>(src[m * bb2 + idx]);
-  for (int64_t idx = threadIdx.x; idx < (m - 1) * bb2; idx += NT) dst[m * bb2 + idx] = cvt<T>(src[bb2 + idx]);
+  const int ld = o.ld;
+  const int64_t bsz = (int64_t)b * ld;
+  for (int64_t idx = threadIdx.x; idx < (2 * m - 1) * bsz; idx += NT) {
+    const int k = (int)(idx / bsz);
+    const int r = (int)((idx % bsz) / ld), cc = (int)(idx % ld);
+    const double* s = (k < m) ? src + (m + k) * bb2 : src + (k - m + 1) * bb2;
+    dst[idx] = cvt<T>(cc < b ? s[r + (int64_t)cc * b] : 0.0);
+  }
 }
 
 hipError_t launch_pack(int32_t ncell, const BuildCell* d_bcells, const double* d_work,

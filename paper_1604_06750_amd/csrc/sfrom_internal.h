@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/sfrom.h"
@@ -72,7 +74,9 @@ struct BuildCell {
 // Per-cell on-line descriptor.
 struct OnlineCell {
   int32_t m, b;
-  int64_t blk_off;   // elements into the block array: G^1..G^m, Ghat^2..Ghat^m
+  int32_t ld;        // row stride of every stored block (b rounded up to 4, zero padded)
+  int32_t pad_;
+  int64_t blk_off;   // elements into the block array: G^1..G^m, Ghat^2..Ghat^m (b x ld each)
   int64_t hid_off;   // rows into the hidden state ((m-1) b rows of n_s)
   int64_t u1_off;    // rows into the gather map / phi scratch (b rows)
 };
@@ -137,7 +141,7 @@ hipError_t launch_piece_mass(const MassArgs& a, hipStream_t st);
 struct StepArgs {
   int32_t ncell, npiece, ns, nrec;
   int32_t prec;
-  int32_t max_b, max_m;
+  int32_t max_b, max_m, max_bp;
   double dt2;
   const OnlineCell* d_cells;
   const OnlinePiece* d_pieces;
@@ -159,12 +163,14 @@ struct StepArgs {
   const double* d_rval;
   void* traces;                  // n_steps x n_rec x ns
   int64_t trace_step;            // which slice to write
+  int32_t cell_variant;          // kernel variant of the cell phase (autotuned)
 };
 hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
 // the three parts of a step, for per-kernel timing
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st);
 hipError_t launch_piece_phase(const StepArgs& a, hipStream_t st);
 hipError_t launch_receivers(const StepArgs& a, hipStream_t st);
+int cell_variants(const StepArgs& a);
 
 // Fine-grid leapfrog step (CSR).
 struct FineArgs {
@@ -188,6 +194,10 @@ struct FineArgs {
   const double* rec_val;
   void* traces;
   int64_t trace_step;
+  // Cartesian 7-point form (when stencil != nullptr): unknown grid ux x uy x uz,
+  // x fastest, 8 coefficients per node: A to x-, x+, y-, y+, z-, z+, diag, 1/b
+  const void* stencil;
+  int32_t ux, uy, uz;
 };
 hipError_t launch_fine_step(const FineArgs& a, hipStream_t st);
 
@@ -275,6 +285,10 @@ struct sfrom {
   int64_t* d_frec_row = nullptr;
   double* d_frec_val = nullptr;
   bool fine_io_dirty = true;
+  // Cartesian structure of the pencil (set by the voxel set-up)
+  int32_t grid_u[3] = {0, 0, 0};
+  std::vector<double> stencil;      // 8 per node, see FineArgs
+  void* d_stencil = nullptr;
 
   // optional per-kernel timing with HIP events (kernel ids: 0 cell phase,
   // 1 piece phase, 2 receivers, 3 fine step)
@@ -282,5 +296,9 @@ struct sfrom {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[4];
   double prof_ms[4] = {0, 0, 0, 0};
+  // autotuned cell-phase variant per (precision, max_b, max_m, n_s)
+  std::map<std::tuple<int, int, int, int>, int> tuned;
+  int tuned_variant = -1;
+  float tuned_ms = 0.f;
   int64_t prof_n[4] = {0, 0, 0, 0};
 };

@@ -45,7 +45,7 @@ class sfrom_info(C.Structure):
                 ("n_piece_dofs", C.c_int64), ("n_hidden_dofs", C.c_int64), ("max_b", C.c_int32),
                 ("max_m", C.c_int32), ("n_sources", C.c_int32), ("n_receivers", C.c_int32),
                 ("built", C.c_int32), ("online_prec", C.c_int32), ("block_bytes", C.c_int64),
-                ("build_ms", C.c_double)]
+                ("build_ms", C.c_double), ("cell_variant", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -204,3 +204,25 @@ def test_runs_are_bitwise_deterministic(dev):
     a, _, _ = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w)
     b, _, _ = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("mf,me,prec,tol", [(16, 3, 1, 1e-4), (9, 3, 1, 1e-4), (16, 3, 2, None)])
+def test_online_precisions_large_b(dev, mf, me, prec, tol):
+    """The matrix-core cell phase at the boundary dimensions the benchmark
+    uses (b = 140 and 98 for interior cells), FP32 and BF16 blocks, 16
+    sources, against the FP64 oracle ROM."""
+    S, P = _lib()
+    wl = synth.workload("small", modes_face=mf, modes_edge=me, m=3, n_steps=600)
+    fi = synth.face_interior_nodes(wl.nvox, wl.cuts)
+    rng = np.random.default_rng(13)
+    wl.sources = fi[np.sort(rng.choice(len(fi), 16, replace=False))]
+    run = pipeline.setup(wl)
+    pipeline.build_all(run)
+    ref = pipeline.rom_traces(run)
+    tr, _, info = _gpu_rom(wl, prec, run.dt, run.w)
+    e = rel(tr, ref)
+    print(f"modes {mf}/{me} prec {prec} max_b {info['max_b']}: rel L2 vs oracle {e:.3e}")
+    if tol is not None:
+        assert e <= tol
+    else:
+        assert e <= 5e-2
