@@ -184,7 +184,11 @@ int sfrom_reset(sfrom_t* h);
  * traces receives n_steps x n_r x n_s values (source fastest) of the
  * receiver output at levels n+1, as double for F64 and float otherwise,
  * host memory unless traces_on_device. dt must satisfy the stability limit
- * of the ROM when known (ECFL). Errors: ESTATE, EINVAL, ECFL, EDEVICE. */
+ * of the ROM when known (ECFL). After the steps the state is checked: a
+ * NaN or infinity (the scheme diverged, e.g. because rounding the blocks
+ * to F32/BF16 made a deep layer indefinite) returns ENONFINITE; the traces
+ * are written either way. Errors: ESTATE, EINVAL, ECFL, EDEVICE,
+ * ENONFINITE. */
 int sfrom_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int32_t w_on_device,
               void* traces, int32_t traces_on_device);
 
@@ -201,6 +205,19 @@ int sfrom_fine_run(sfrom_t* h, int64_t n_steps, double dt, const double* w,
 int sfrom_fine_lambda_max(sfrom_t* h, double* lambda);
 /* Largest eigenvalue of the global ROM pencil (-L, D); needs a built ROM. */
 int sfrom_rom_lambda_max(sfrom_t* h, double* lambda);
+
+/* hipGraph form of sfrom_run (default off): the launches of a whole run are
+ * captured into one graph, which is replayed by later runs with the same
+ * n_steps, dt, wavelet and trace pointers, state buffers and state parity
+ * (the typical case of repeated jobs with device-resident inputs and
+ * outputs). Runs with host pointers are captured afresh each time. */
+int sfrom_set_graph(sfrom_t* h, int32_t enable);
+
+/* Kernel variant of the on-line cell phase: -1 (default) lets the
+ * autotuner time the variants on the first run and keep the fastest; 0..7
+ * pin a matrix-core tiling, 8 the scalar kernel (F64 always uses the scalar
+ * kernel). Meant for tests and tuning studies. */
+int sfrom_set_cell_variant(sfrom_t* h, int32_t variant);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * every launch while enabled. Kernel ids: 0 on-line cell phase, 1 on-line

@@ -77,11 +77,13 @@ size_t block_bytes(int prec) { return prec == SFROM_F64 ? 8 : (prec == SFROM_F32
 
 void free_rom(sfrom_t* h) {
   if (h->device < 0) { h->built = false; return; }
+  if (h->graph_exec) { hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+  h->graph_key.clear();
   dfree(h->d_blocks); dfree(h->d_minv); dfree(h->d_rom64); dfree(h->d_rom64_off);
   dfree(h->d_ocells); dfree(h->d_opieces); dfree(h->d_gather); dfree(h->d_inc);
   dfree(h->d_inc_cell); dfree(h->d_inc_col);
   dfree(h->d_src); dfree(h->d_rptr); dfree(h->d_rrow); dfree(h->d_rval);
-  dfree(h->d_y[0]); dfree(h->d_y[1]); dfree(h->d_h[0]); dfree(h->d_h[1]); dfree(h->d_phi);
+  dfree(h->d_y[0]); dfree(h->d_y[1]); dfree(h->d_h[0]); dfree(h->d_h[1]); dfree(h->d_phi); dfree(h->d_flag);
   h->built = false;
   h->state_ns = -1;
   h->src_dirty = h->rec_dirty = true;
@@ -98,6 +100,7 @@ void free_fine(sfrom_t* h) {
 
 void free_all(sfrom_t* h) {
   if (h->device < 0) return;
+  if (h->capture_stream) { hipStreamDestroy(h->capture_stream); h->capture_stream = nullptr; }
   for (int k = 0; k < 4; ++k)
     for (auto& pr : h->ev_pending[k]) { h->ev_pool.push_back(pr.first); h->ev_pool.push_back(pr.second); }
   for (auto e : h->ev_pool) hipEventDestroy(e);
@@ -623,6 +626,10 @@ void prepare_online(sfrom_t* h) {
 // scratch copies of the state (the real state is not touched) and the
 // fastest is kept for the life of the handle.
 int autotune_cell(sfrom_t* h, StepArgs a) {
+  if (h->pinned_variant >= 0) {
+    h->tuned_variant = std::min(h->pinned_variant, cell_variants(a) - 1);
+    return h->tuned_variant;
+  }
   const auto key = std::make_tuple(a.prec, a.max_b, a.max_m, a.ns);
   auto it = h->tuned.find(key);
   if (it != h->tuned.end()) return it->second;
@@ -710,20 +717,78 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   a.d_rptr = h->d_rptr; a.d_rrow = h->d_rrow; a.d_rval = h->d_rval;
   a.traces = d_tr;
   a.cell_variant = autotune_cell(h, a);
-  for (int64_t s = 0; s < n_steps; ++s) {
-    a.y_cur = h->d_y[h->cur]; a.y_old = h->d_y[1 - h->cur];
-    a.h_cur = h->d_h[h->cur]; a.h_old = h->d_h[1 - h->cur];
-    a.step = s; a.trace_step = s;
-    timed(h, 0, [&] { return launch_cell_phase(a, h->stream); });
-    timed(h, 1, [&] { return launch_piece_phase(a, h->stream); });
-    timed(h, 2, [&] { return launch_receivers(a, h->stream); });
-    h->cur = 1 - h->cur;
-    if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
+  const bool graph = h->use_graph && !h->profiling && n_steps > 0;
+  std::vector<int64_t> key;
+  if (graph) {
+    double dtv = dt;
+    int64_t dbits;
+    std::memcpy(&dbits, &dtv, 8);
+    key = {n_steps, dbits, (int64_t)(intptr_t)d_w, (int64_t)(intptr_t)d_tr, (int64_t)h->cur,
+           (int64_t)(intptr_t)h->d_y[0], (int64_t)(intptr_t)h->d_h[0], (int64_t)(intptr_t)h->d_phi,
+           (int64_t)ns, (int64_t)nr, (int64_t)a.cell_variant, (int64_t)(intptr_t)h->d_blocks};
+    if (h->graph_exec && key == h->graph_key) {
+      HIPCHK(hipGraphLaunch(h->graph_exec, h->stream));
+      h->graph_launches++;
+      if (n_steps % 2) h->cur = 1 - h->cur;
+      goto done;
+    }
+    if (h->graph_exec) { hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+    // capture on a private stream (the null stream cannot be captured); the
+    // graph is launched on the handle's stream, which orders it after all
+    // work already enqueued there
+    if (!h->capture_stream) HIPCHK(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
   }
+  {
+  hipStream_t ls = graph ? h->capture_stream : h->stream;
+  {
+    const int cur0 = h->cur;
+    int cur = cur0;
+    for (int64_t s = 0; s < n_steps; ++s) {
+      a.y_cur = h->d_y[cur]; a.y_old = h->d_y[1 - cur];
+      a.h_cur = h->d_h[cur]; a.h_old = h->d_h[1 - cur];
+      a.step = s; a.trace_step = s;
+      timed(h, 0, [&] { return launch_cell_phase(a, ls); });
+      timed(h, 1, [&] { return launch_piece_phase(a, ls); });
+      timed(h, 2, [&] { return launch_receivers(a, ls); });
+      cur = 1 - cur;
+      if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
+    }
+    if (graph) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamEndCapture(h->capture_stream, &g));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIPCHK(e);
+      h->graph_exec = ex;
+      h->graph_key = key;
+      HIPCHK(hipGraphLaunch(h->graph_exec, h->stream));
+      h->graph_launches++;
+    }
+    h->cur = cur;
+  }
+  }
+done:
   if (own) {
     HIPCHK(hipMemcpyAsync(traces, d_tr, tbytes, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     dfree(d_tr);
+  }
+  if (n_steps > 0) {
+    // a reduced-precision ROM can lose the stability of the leap-frog scheme
+    // (rounded blocks of a deep layer need not stay definite); report it
+    // instead of returning garbage
+    if (!h->d_flag) h->d_flag = dalloc<int32_t>(h, 1);
+    HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), h->stream));
+    const int64_t npd = h->piece_dof_off.back();
+    HIPCHK(launch_nonfinite(h->d_y[h->cur], npd * ns, h->prec, h->d_flag, h->stream));
+    HIPCHK(launch_nonfinite(h->d_h[h->cur], h->n_hidden_dofs * ns, h->prec, h->d_flag, h->stream));
+    int32_t flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    REQUIRE(flag == 0, SFROM_ENONFINITE,
+            "the ROM state became non-finite: the scheme is unstable for this dt in this storage precision");
   }
 }
 
@@ -1355,6 +1420,21 @@ int sfrom_rom_lambda_max(sfrom_t* h, double* lambda) {
     apply_msq(t2.data(), y);
   };
   *lambda = lanczos_max(ndof, mv);
+  API_END(h)
+}
+
+int sfrom_set_graph(sfrom_t* h, int32_t enable) {
+  API_BEGIN(h)
+  REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
+  h->use_graph = enable != 0;
+  if (!h->use_graph && h->graph_exec) { hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; h->graph_key.clear(); }
+  API_END(h)
+}
+
+int sfrom_set_cell_variant(sfrom_t* h, int32_t variant) {
+  API_BEGIN(h)
+  REQUIRE(variant >= -1 && variant < 9, SFROM_EINVAL, "variant must be -1 (autotune) or 0..8");
+  h->pinned_variant = variant;
   API_END(h)
 }
 

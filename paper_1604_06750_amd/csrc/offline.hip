@@ -576,7 +576,8 @@ template <>
 __device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
 
 // Blocks per cell in the on-line layout: G^1..G^m, then Ghat^2..Ghat^m, each
-// b rows of stride ld.
+// b rows of stride ld (zero padded); the blocks are symmetric, so rows and
+// columns coincide.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_pack(const BuildCell* bc, const double* work,
                                              const OnlineCell* oc, T* blocks, double* rom64,
@@ -588,8 +589,6 @@ __global__ __launch_bounds__(NT) void k_pack(const BuildCell* bc, const double* 
   const double* src = work + c.out_off;
   double* r64 = rom64 + rom64_off[blockIdx.x];
   for (int64_t idx = threadIdx.x; idx < 2 * m * bb2; idx += NT) r64[idx] = src[idx];
-  // b x ld blocks (row stride ld, zero padding); the blocks are symmetric, so
-  // rows and columns coincide
   T* dst = blocks + o.blk_off;
   const int ld = o.ld;
   const int64_t bsz = (int64_t)b * ld;

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "sfrom_internal.h"
@@ -349,6 +350,180 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Streaming variant of the matrix-core cell phase: NW = ceil(nch / TPW)
+// waves per workgroup, each owning TPW 16-row tiles and streaming its A
+// fragments from HBM through a register ring of RING chunks. Registers and
+// LDS per workgroup are small, so several cells are in flight per CU and the
+// latency of one cell's loads is hidden behind another cell's products.
+// ---------------------------------------------------------------------------
+template <int TPW, int CT, bool BF16>
+__global__ __launch_bounds__(256) void k_cell_stream(StepArgs a, int kp, int ntile) {
+  using TB = typename std::conditional<BF16, __hip_bfloat16, float>::type;
+  constexpr int NS = 16 * CT;
+  constexpr int RING = 4;
+  extern __shared__ float lds[];
+  float* Dt = lds;
+  float* Et = lds + NS * kp;
+  int cell, tile;
+  {
+    const int bid = blockIdx.x;
+    const int grp = bid / (8 * ntile), r = bid % (8 * ntile);
+    tile = r / 8;
+    cell = grp * 8 + r % 8;
+    if (cell >= a.ncell) return;
+  }
+  const OnlineCell c = a.d_cells[cell];
+  const int m = c.m, b = c.b, ld = c.ld, ns = a.ns;
+  const int s0 = tile * NS;
+  const int nsl = min(NS, ns - s0);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nw = nthr >> 6;
+  const int w = tid >> 6, l = tid & 63, g = l >> 4, li = l & 15;
+  const int nch = (b + 15) >> 4;
+  const float* __restrict__ ycur = reinterpret_cast<const float*>(a.y_cur);
+  const float* __restrict__ hcur = reinterpret_cast<const float*>(a.h_cur);
+  float* __restrict__ hold = reinterpret_cast<float*>(a.h_old);
+  float* __restrict__ phi = reinterpret_cast<float*>(a.phi);
+  const int32_t* __restrict__ gat = a.d_gather + c.u1_off;
+  const TB* __restrict__ blk = reinterpret_cast<const TB*>(a.d_blocks) + c.blk_off;
+  const int64_t bsz = (int64_t)b * ld;
+  const float dt2 = (float)a.dt2;
+
+  // product of the wave's row tiles of block `base` with the transposed LDS
+  // tile Bt; results in acc[t][ct]
+  auto product = [&](floatx4 (&acc)[TPW][CT], const TB* base, const float* Bt) {
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[t][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const int rt = w + t * nw;
+      if (rt >= nch) continue;
+      const int row = rt * 16 + li;
+      const bool rok = row < b;
+      const TB* rp = base + (int64_t)(rok ? row : 0) * ld;
+      AFrag<BF16> ring[RING];
+#pragma unroll
+      for (int u = 0; u < RING; ++u) {
+        const int kk = u * 16 + g * 4;
+        if (u < nch && rok && kk < ld) ring[u].load(rp + kk); else ring[u].zero();
+      }
+      for (int ch0 = 0; ch0 < nch; ch0 += RING) {
+#pragma unroll
+        for (int u = 0; u < RING; ++u) {
+          const int ch = ch0 + u;
+          if (ch < nch) {
+            const AFrag<BF16> av = ring[u];
+            const int kn = (ch + RING) * 16 + g * 4;
+            if (ch + RING < nch && rok && kn < ld) ring[u].load(rp + kn); else ring[u].zero();
+            float4 bv[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              bv[ct] = *reinterpret_cast<const float4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
+            if constexpr (!BF16) {
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.v.x, bv[ct].x, acc[t][ct], 0, 0, 0);
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.v.y, bv[ct].y, acc[t][ct], 0, 0, 0);
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.v.z, bv[ct].z, acc[t][ct], 0, 0, 0);
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.v.w, bv[ct].w, acc[t][ct], 0, 0, 0);
+            } else {
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) {
+                const shortx4 bb = shortx4{f2bf(bv[ct].x), f2bf(bv[ct].y), f2bf(bv[ct].z), f2bf(bv[ct].w)};
+                acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av.v, bb, acc[t][ct], 0, 0, 0);
+              }
+            }
+          }
+        }
+      }
+    }
+  };
+
+  floatx4 prev[TPW][CT];
+  for (int k = 0; k < m; ++k) {
+    // Dt = (U^{k+1} - U^k)^T, zero padded to 16 nch rows and NS columns
+    for (int t = tid; t < NS * 4 * nch; t += nthr) {
+      const int col = t % NS, q = t / NS;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int kk = 4 * q + e;
+        float d = 0.f;
+        if (kk < b && col < nsl) {
+          const float un = (k + 1 < m) ? hcur[(c.hid_off + (int64_t)k * b + kk) * ns + s0 + col] : 0.f;
+          const float uc = (k == 0) ? ycur[(int64_t)gat[kk] * ns + s0 + col]
+                                    : hcur[(c.hid_off + (int64_t)(k - 1) * b + kk) * ns + s0 + col];
+          d = un - uc;
+        }
+        v[e] = d;
+      }
+      *reinterpret_cast<float4*>(Dt + col * kp + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    __syncthreads();
+    floatx4 acc[TPW][CT];
+    product(acc, blk + (int64_t)k * bsz, Dt);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int rt = w + t * nw;
+      if (rt >= nch) continue;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + li;
+        if (k == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rt * 16 + 4 * g + r;
+            if (row < b && col < nsl) phi[(c.u1_off + row) * ns + s0 + col] = acc[t][ct][r];
+          }
+        } else {
+          const floatx4 e = acc[t][ct] - prev[t][ct];
+          *reinterpret_cast<float4*>(Et + col * kp + rt * 16 + 4 * g) = make_float4(e[0], e[1], e[2], e[3]);
+        }
+        prev[t][ct] = acc[t][ct];
+      }
+    }
+    __syncthreads();
+    if (k >= 1) {
+      floatx4 acc2[TPW][CT];
+      product(acc2, blk + (int64_t)(m + k - 1) * bsz, Et);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int rt = w + t * nw;
+        if (rt >= nch) continue;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const int col = ct * 16 + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rt * 16 + 4 * g + r;
+            if (row < b && col < nsl) {
+              const int64_t hi = (c.hid_off + (int64_t)(k - 1) * b + row) * ns + s0 + col;
+              hold[hi] = 2.f * hcur[hi] - hold[hi] + dt2 * acc2[t][ct][r];
+            }
+          }
+        }
+      }
+    }
+    // Dt is rewritten at the next layer only after every wave has finished
+    // reading it (the barrier above), and Et only after the next barrier
+  }
+}
+
+template <int TPW, int CT, bool BF16>
+static void launch_stream(const StepArgs& a, hipStream_t st) {
+  constexpr int NS = 16 * CT;
+  const int nchmax = (a.max_b + 15) / 16;
+  const int kp = 16 * nchmax + 4;
+  const int nw = (nchmax + TPW - 1) / TPW;
+  const size_t lds = 2 * (size_t)NS * kp * sizeof(float);
+  const int ntile = (a.ns + NS - 1) / NS;
+  const int groups = (a.ncell + 7) / 8;
+  hipLaunchKernelGGL((k_cell_stream<TPW, CT, BF16>), dim3(groups * 8 * ntile), dim3(64 * nw), lds, st, a, kp, ntile);
+}
+
 template <int NCH, int CT, bool PF, bool BF16>
 static void launch_mfma(const StepArgs& a, hipStream_t st) {
   constexpr int NS = 16 * CT;
@@ -373,6 +548,16 @@ static void launch_variant(const StepArgs& a, int variant, hipStream_t st) {
 template <bool BF16>
 static hipError_t mfma_dispatch(const StepArgs& a, int variant, hipStream_t st) {
   const int need = (a.max_b + 15) / 16;
+  if (variant >= 4) {
+    if ((need + 1) / 2 > 4 && variant < 6) variant += 2;   // keep <= 4 waves per group
+    switch (variant) {
+      case 4: launch_stream<2, 1, BF16>(a, st); break;
+      case 5: launch_stream<2, 2, BF16>(a, st); break;
+      case 6: launch_stream<3, 1, BF16>(a, st); break;
+      default: launch_stream<3, 2, BF16>(a, st); break;
+    }
+    return hipGetLastError();
+  }
   if (need <= 4) launch_variant<4, BF16>(a, variant, st);
   else if (need <= 6) launch_variant<6, BF16>(a, variant, st);
   else if (need <= 7) launch_variant<7, BF16>(a, variant, st);
@@ -526,12 +711,14 @@ static hipError_t rec_impl(const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int cell_variants(const StepArgs& a) { return (a.prec == SFROM_F64 || a.max_b > 256) ? 1 : 5; }
+int cell_variants(const StepArgs& a) { return (a.prec == SFROM_F64 || a.max_b > 256) ? 1 : 9; }
 
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st) {
-  // variant 0..3: matrix-core kernel (source tile 64/32, with/without strip
-  // prefetch); variant 4 (and FP64): the scalar kernel
-  if (a.prec == SFROM_F64 || a.max_b > 256 || a.cell_variant >= 4) {
+  // variants 0..3: matrix-core kernel with one wave per row strip (source
+  // tile 64/32, with/without strip prefetch); 4..7: streaming matrix-core
+  // kernel (2 or 3 row tiles per wave, source tile 16/32); 8 (and FP64): the
+  // scalar kernel
+  if (a.prec == SFROM_F64 || a.max_b > 256 || a.cell_variant >= 8) {
     if (a.prec == SFROM_F64) return cell_impl<double, double, double>(a, st);
     if (a.prec == SFROM_F32) return cell_impl<float, float, float>(a, st);
     return cell_impl<float, __hip_bfloat16, float>(a, st);
@@ -548,6 +735,28 @@ hipError_t launch_piece_phase(const StepArgs& a, hipStream_t st) {
 hipError_t launch_receivers(const StepArgs& a, hipStream_t st) {
   if (a.prec == SFROM_F64) return rec_impl<double, double>(a, st);
   return rec_impl<float, float>(a, st);
+}
+
+// Sets *flag when any of the n state values is NaN or infinite (leap-frog
+// divergence). The flag is written with a vector atomic by one lane per wave.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nonfinite(const T* __restrict__ x, int64_t n, int32_t* flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = (double)x[i];
+    bad |= !(v - v == 0.0);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+hipError_t launch_nonfinite(const void* x, int64_t n, int prec, int32_t* flag, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(2048, (n + 255) / 256);
+  if (prec == SFROM_F64)
+    hipLaunchKernelGGL(k_nonfinite<double>, dim3(grid), dim3(256), 0, st, (const double*)x, n, flag);
+  else
+    hipLaunchKernelGGL(k_nonfinite<float>, dim3(grid), dim3(256), 0, st, (const float*)x, n, flag);
+  return hipGetLastError();
 }
 
 hipError_t launch_online_step(const StepArgs& a, hipStream_t st) {

@@ -170,6 +170,9 @@ hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st);
 hipError_t launch_piece_phase(const StepArgs& a, hipStream_t st);
 hipError_t launch_receivers(const StepArgs& a, hipStream_t st);
+// ORs 1 into *flag if any of n state values (double for F64, else float) is
+// not finite
+hipError_t launch_nonfinite(const void* x, int64_t n, int prec, int32_t* flag, hipStream_t st);
 int cell_variants(const StepArgs& a);
 
 // Fine-grid leapfrog step (CSR).
@@ -264,6 +267,7 @@ struct sfrom {
   void* d_y[2] = {nullptr, nullptr};
   void* d_h[2] = {nullptr, nullptr};
   void* d_phi = nullptr;
+  int32_t* d_flag = nullptr;  // non-finite state flag
   int cur = 0;                    // which buffer holds level n
   double* d_w = nullptr;
   int64_t d_w_cap = 0;
@@ -300,5 +304,14 @@ struct sfrom {
   std::map<std::tuple<int, int, int, int>, int> tuned;
   int tuned_variant = -1;
   float tuned_ms = 0.f;
+
+  // hipGraph form of sfrom_run: the whole run is captured once and replayed
+  // while its arguments (and the state buffers and their parity) are unchanged
+  bool use_graph = false;
+  hipStream_t capture_stream = nullptr;   // private stream used for capture
+  int pinned_variant = -1;                 // >= 0: cell-phase variant fixed by the caller
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<int64_t> graph_key;
+  int64_t graph_launches = 0;
   int64_t prof_n[4] = {0, 0, 0, 0};
 };

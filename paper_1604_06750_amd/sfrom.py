@@ -73,6 +73,8 @@ _SIGS = {
     "sfrom_fine_lambda_max": [_P, C.POINTER(C.c_double)],
     "sfrom_rom_lambda_max": [_P, C.POINTER(C.c_double)],
     "sfrom_get_info": [_P, C.POINTER(sfrom_info)],
+    "sfrom_set_graph": [_P, C.c_int32],
+    "sfrom_set_cell_variant": [_P, C.c_int32],
     "sfrom_profile": [_P, C.c_int32],
     "sfrom_profile_read": [_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "sfrom_export_pencil": [_P, _P, _P, _P, _P],
@@ -266,6 +268,14 @@ def sfrom_rom_lambda_max(h) -> float:
     v = C.c_double()
     _check(h, _lib.sfrom_rom_lambda_max(h, C.byref(v)))
     return v.value
+
+
+def sfrom_set_graph(h, enable=True):
+    _check(h, _lib.sfrom_set_graph(h, int(enable)))
+
+
+def sfrom_set_cell_variant(h, variant=-1):
+    _check(h, _lib.sfrom_set_cell_variant(h, int(variant)))
 
 
 def sfrom_profile(h, enable=True):

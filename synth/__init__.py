@@ -184,6 +184,11 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
                  many cells but stays within seconds for the oracle)
     ``large``  : 128^3 voxels, 16^3 cells of 8^3, 64 sources on an 8x8 grid,
                  1024 receivers, 4000 steps (the batched FP32 case)
+    ``layered``: 256x256x128 voxels, 6 layers of contrast 3:1 with a +-10%
+                 smooth perturbation, non-uniform cells of 8..16 voxels aligned
+                 to the layers, per-cell layer count 3..8 from the cell size
+                 (``extra['m_per_cell']``), 256 sources, 6000 steps
+    ``layered_small``: the same recipe on 64x64x32 voxels (parity case)
     """
     mf = 9 if modes_face is None else modes_face
     me = 2 if modes_edge is None else modes_edge
@@ -240,6 +245,67 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
         rec = np.array([[2 + 4 * i, 2 + 4 * j, 120] for j in b for i in b], dtype=np.int64)
         return Workload(name, nvox, sigma, rho, cuts, m or 4, mf, me, src, rec,
                         n_steps or 4000, f_p, omega_max, shift, seed=seed)
+    if name in ("layered", "layered_small"):
+        # layered medium, non-uniform cells of 8..16 voxels aligned to the
+        # layers, per-cell layer count from the cell size (uneven (m, b))
+        if name == "layered":
+            nvox = (256, 256, 128)
+            nsrc_side, nrec_side, steps = 16, 32, 6000
+        else:
+            nvox = (64, 64, 32)
+            nsrc_side, nrec_side, steps = 4, 8, 600
+        seed = 4001 + realisation
+        rng = np.random.Generator(np.random.PCG64(seed + 50))
+        nz = nvox[2]
+        nl = 6 if nz >= 96 else 3
+        zb = [int(round(nz * j / nl)) for j in range(1, nl)]
+        sigma, rho = layered_medium(nvox, seed, zb, contrast=3.0)
+
+        def segments(total):
+            cuts, pos = [], 0
+            while total - pos > 16:
+                step = int(rng.integers(8, 17))
+                if total - pos - step < 8:
+                    step = total - pos - 8
+                pos += step
+                cuts.append(pos)
+            return np.array(cuts, dtype=np.int64)
+
+        zcuts = []
+        for lo, hi in zip([0] + zb, zb + [nz]):
+            zcuts.append((lo + hi) // 2)
+            if hi < nz:
+                zcuts.append(hi)
+        cuts = (segments(nvox[0]), segments(nvox[1]), np.array(sorted(zcuts), dtype=np.int64))
+        plane = int(cuts[2][-1])                       # first interface below the top wall
+
+        def off_cut(v, c):
+            while v in set(int(x) for x in c) or v <= 0:
+                v += 1
+            return v
+
+        xs = [off_cut(int(v), cuts[0]) for v in np.linspace(4, nvox[0] - 5, nsrc_side).astype(int)]
+        ys = [off_cut(int(v), cuts[1]) for v in np.linspace(4, nvox[1] - 5, nsrc_side).astype(int)]
+        src = np.array([[x, y, plane] for y in ys for x in xs], dtype=np.int64)
+        if n_sources is not None:
+            src = src[:n_sources]
+        xr = [off_cut(int(v), cuts[0]) for v in np.linspace(2, nvox[0] - 3, nrec_side).astype(int)]
+        yr = [off_cut(int(v), cuts[1]) for v in np.linspace(2, nvox[1] - 3, nrec_side).astype(int)]
+        rec = np.array([[x, y, plane] for y in yr for x in xr], dtype=np.int64)
+        c_min = np.sqrt(0.9 / 2.2)                      # generator bounds of sigma and rho
+        f_p, omega_max = _band(c_min, ppw)
+        wl = Workload(name, nvox, sigma, rho, cuts, m or 3, mf, me, src, rec,
+                      n_steps or steps, f_p, omega_max, -omega_max ** 2 / 10.0, seed=seed)
+        # layers per cell grow with the cell size: 3 at 8 voxels, 8 at 16
+        edges = [np.diff(np.concatenate([[0], c, [n]])) for c, n in zip(cuts, nvox)]
+        mpc = []
+        for ez in edges[2]:
+            for ey in edges[1]:
+                for ex in edges[0]:
+                    v13 = (ex * ey * ez) ** (1.0 / 3.0)
+                    mpc.append(int(np.clip(round(3 + 5 * (v13 - 8) / 8), 3, 8)))
+        wl.extra["m_per_cell"] = np.array(mpc, dtype=np.int32)
+        return wl
     raise ValueError(f"unknown workload {name!r}")
 
 
