@@ -142,7 +142,10 @@ int sfrom_build(sfrom_t* h, const sfrom_build_opts* opts);
 /* Replace cell `cell`'s S-fraction by m blocks Ghat^k and G^k (each b x b
  * symmetric, column-major, stored consecutively: Ghat[k*b*b ...]); b must
  * equal the cell's boundary dimension. Requires a built ROM; piece masses
- * are recomputed from Ghat^1 at the next run. Errors: EINVAL, ESTATE, ENOTSPD. */
+ * are recomputed from Ghat^1 at the next run. The on-line blocks are formed
+ * on the host with Cholesky factors of Ghat^2..Ghat^m (the change of
+ * variables described at sfrom_run). Errors: EINVAL, ESTATE, ENOTSPD
+ * (non-symmetric blocks, or Ghat^k k >= 2 not positive definite). */
 int sfrom_import_rom(sfrom_t* h, int32_t cell, int32_t m, int32_t b, const double* Ghat,
                      const double* G);
 /* Copy cell `cell`'s S-fraction to host: *m, *b, and (if non-NULL) Ghat, G
@@ -178,16 +181,21 @@ int sfrom_point_columns(sfrom_t* h, int32_t count, const int64_t* node, int64_t*
 /* Zero the ROM state (eq. initial: U = 0 for t <= 0). */
 int sfrom_reset(sfrom_t* h);
 /* Advance the ROM n_steps leapfrog steps of size dt from its current state:
- * Y^{n+1} = 2Y^n - Y^{n-1} + dt^2 D^{-1} (L Y^n + w^n F), hidden layers by
- * eq. intrtstep_td, piece dofs by eq. bdrytstep. w[n_steps] (double) are the
+ * Y^{n+1} = 2Y^n - Y^{n-1} + dt^2 D^{-1} (L Y^n + w^n F), piece dofs by
+ * eq. bdrytstep. The hidden layers of eq. intrtstep_td are stepped in the
+ * unit-mass variables V^k = G_k^{-1} U^k (Ghat^k = G_k G_k^T, eq. GammaTrans),
+ * where each cell's operator is block tridiagonal with the cell's Lanczos
+ * blocks: an exactly equivalent form whose blocks stay well scaled when
+ * Ghat^k and G^k of deep layers are near singular, so that rounding them
+ * to F32/BF16 moves the spectrum by about a unit roundoff of its largest
+ * eigenvalue. The traces are unaffected by the change of variables. w[n_steps] (double) are the
  * wavelet samples for these steps, host memory unless w_on_device.
  * traces receives n_steps x n_r x n_s values (source fastest) of the
  * receiver output at levels n+1, as double for F64 and float otherwise,
  * host memory unless traces_on_device. dt must satisfy the stability limit
  * of the ROM when known (ECFL). After the steps the state is checked: a
- * NaN or infinity (the scheme diverged, e.g. because rounding the blocks
- * to F32/BF16 made a deep layer indefinite) returns ENONFINITE; the traces
- * are written either way. Errors: ESTATE, EINVAL, ECFL, EDEVICE,
+ * NaN or infinity (the scheme diverged) returns ENONFINITE; the traces are
+ * written either way. Errors: ESTATE, EINVAL, ECFL, EDEVICE,
  * ENONFINITE. */
 int sfrom_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int32_t w_on_device,
               void* traces, int32_t traces_on_device);
@@ -214,8 +222,8 @@ int sfrom_rom_lambda_max(sfrom_t* h, double* lambda);
 int sfrom_set_graph(sfrom_t* h, int32_t enable);
 
 /* Kernel variant of the on-line cell phase: -1 (default) lets the
- * autotuner time the variants on the first run and keep the fastest; 0..7
- * pin a matrix-core tiling, 8 the scalar kernel (F64 always uses the scalar
+ * autotuner time the variants on the first run and keep the fastest; 0..3
+ * pin a matrix-core tiling, 4 the scalar kernel (F64 always uses the scalar
  * kernel). Meant for tests and tuning studies. */
 int sfrom_set_cell_variant(sfrom_t* h, int32_t variant);
 

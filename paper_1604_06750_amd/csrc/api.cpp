@@ -25,6 +25,25 @@ struct Fail {
   int code;
 };
 
+// In-place lower Cholesky factor of a column-major n x n SPD matrix (upper
+// triangle zeroed); false if a pivot is not positive.
+bool host_cholesky(int n, double* A) {
+  for (int j = 0; j < n; ++j) {
+    double d = A[j + (int64_t)j * n];
+    for (int k = 0; k < j; ++k) d -= A[j + (int64_t)k * n] * A[j + (int64_t)k * n];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    d = std::sqrt(d);
+    A[j + (int64_t)j * n] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i + (int64_t)j * n];
+      for (int k = 0; k < j; ++k) v -= A[i + (int64_t)k * n] * A[j + (int64_t)k * n];
+      A[i + (int64_t)j * n] = v / d;
+    }
+    for (int i = 0; i < j; ++i) A[i + (int64_t)j * n] = 0.0;
+  }
+  return true;
+}
+
 int set_err(sfrom_t* h, int code, const std::string& msg) {
   if (h) h->err = msg;
   return code;
@@ -1148,14 +1167,53 @@ int sfrom_import_rom(sfrom_t* h, int32_t cell, int32_t m, int32_t b, const doubl
         REQUIRE(Ghat[u] == Ghat[v] && G[u] == G[v], SFROM_ENOTSPD, "blocks must be symmetric");
       }
   HIPCHK(hipMemcpy(h->d_rom64 + h->rom64_off[cell], r64.data(), r64.size() * sizeof(double), hipMemcpyHostToDevice));
-  // on-line layout: G^1..G^m, Ghat^2..Ghat^m, each b x ld (row stride ld, zero padded)
+  // on-line blocks D_0, C_0, D_1, ..., D_{m-1} (b x ld, row-major, zero
+  // padded) in the unit-mass variables V^k = R_k^{-1} U^k of the hidden
+  // layers, Ghat^k = R_k R_k^T (Cholesky; R_0 = I): D_0 = -G^1,
+  // D_l = -R_l^T (G^l + G^{l-1}) R_l, C_l = R_l^T G^l R_{l+1}
+  std::vector<std::vector<double>> R(m);
+  for (int k = 1; k < m; ++k) {
+    R[k].assign(Ghat + k * bb2, Ghat + (k + 1) * bb2);
+    REQUIRE(host_cholesky(b, R[k].data()), SFROM_ENOTSPD, "Ghat^k is not positive definite (eq. S-fraction)");
+  }
+  // X^T M Y for column-major b x b matrices; X or Y null means the identity
+  auto congruence = [&](const double* X, const double* M, const double* Y, std::vector<double>& out) {
+    std::vector<double> t(bb2);
+    for (int i = 0; i < b; ++i)
+      for (int j = 0; j < b; ++j) {
+        double acc = 0.0;
+        if (!Y) acc = M[i + (int64_t)j * b];
+        else
+          for (int q = 0; q < b; ++q) acc += M[i + (int64_t)q * b] * Y[q + (int64_t)j * b];
+        t[i + (int64_t)j * b] = acc;
+      }
+    out.assign(bb2, 0.0);
+    for (int i = 0; i < b; ++i)
+      for (int j = 0; j < b; ++j) {
+        double acc = 0.0;
+        if (!X) acc = t[i + (int64_t)j * b];
+        else
+          for (int q = 0; q < b; ++q) acc += X[q + (int64_t)i * b] * t[q + (int64_t)j * b];
+        out[i + (int64_t)j * b] = acc;
+      }
+  };
   const int ld = oc.ld;
   const int64_t bsz = (int64_t)b * ld;
   std::vector<double> blk((2 * m - 1) * bsz, 0.0);
-  for (int k = 0; k < 2 * m - 1; ++k) {
-    const double* src = (k < m) ? G + k * bb2 : Ghat + (k - m + 1) * bb2;
+  std::vector<double> M(bb2);
+  for (int l = 0; l < m; ++l) {
+    std::vector<double> Gs(G + l * bb2, G + (l + 1) * bb2);
+    if (l > 0)
+      for (int64_t q = 0; q < bb2; ++q) Gs[q] += G[(l - 1) * bb2 + q];
+    congruence(l ? R[l].data() : nullptr, Gs.data(), l ? R[l].data() : nullptr, M);
     for (int r = 0; r < b; ++r)
-      for (int c = 0; c < b; ++c) blk[k * bsz + (int64_t)r * ld + c] = src[r + (int64_t)c * b];
+      for (int c = 0; c < b; ++c)
+        blk[2 * l * bsz + (int64_t)r * ld + c] = -0.5 * (M[r + (int64_t)c * b] + M[c + (int64_t)r * b]);
+    if (l + 1 < m) {
+      congruence(l ? R[l].data() : nullptr, G + l * bb2, R[l + 1].data(), M);
+      for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) blk[(2 * l + 1) * bsz + (int64_t)r * ld + c] = M[r + (int64_t)c * b];
+    }
   }
   const size_t eb = block_bytes(h->prec);
   unsigned char* dst = reinterpret_cast<unsigned char*>(h->d_blocks) + (size_t)oc.blk_off * eb;
@@ -1433,7 +1491,7 @@ int sfrom_set_graph(sfrom_t* h, int32_t enable) {
 
 int sfrom_set_cell_variant(sfrom_t* h, int32_t variant) {
   API_BEGIN(h)
-  REQUIRE(variant >= -1 && variant < 9, SFROM_EINVAL, "variant must be -1 (autotune) or 0..8");
+  REQUIRE(variant >= -1 && variant < 5, SFROM_EINVAL, "variant must be -1 (autotune) or 0..4");
   h->pinned_variant = variant;
   API_END(h)
 }

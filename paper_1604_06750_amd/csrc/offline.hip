@@ -575,32 +575,61 @@ __device__ inline float cvt<float>(double v) { return (float)v; }
 template <>
 __device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
 
-// Blocks per cell in the on-line layout: G^1..G^m, then Ghat^2..Ghat^m, each
-// b rows of stride ld (zero padded); the blocks are symmetric, so rows and
-// columns coincide.
+// On-line blocks of a cell: the three-point scheme with its hidden layers
+// in the variables V^k = G_k^{-1} U^k (unit mass) is block tridiagonal with
+// D_0 = -G^1, C_0 = G^1 G_2 = G_1^{-T} beta_2^T = beta_1^{-1} beta_2^T, and
+// for l >= 1 D_l = -G_l^T (G^l + G^{l-1}) G_l = alpha_l and
+// C_l = G_l^T G^l G_{l+1} = beta_{l+1}^T (both by eq. GammaTrans; layers
+// counted from 0). They are stored as D_0, C_0, D_1, ..., D_{m-1}, each b
+// rows of stride ld (row-major, zero padded). The FP64 S-fraction blocks are
+// kept as well (export, piece masses, spectral bound).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_pack(const BuildCell* bc, const double* work,
-                                             const OnlineCell* oc, T* blocks, double* rom64,
-                                             const int64_t* rom64_off) {
-  const BuildCell& c = bc[blockIdx.x];
+__global__ __launch_bounds__(NT) void k_pack(BuildCell* bc, double* work, const OnlineCell* oc, T* blocks,
+                                             double* rom64, const int64_t* rom64_off) {
+  BuildCell& c = bc[blockIdx.x];
   const OnlineCell& o = oc[blockIdx.x];
   const int b = c.b, m = c.m;
   const int64_t bb2 = (int64_t)b * b;
   const double* src = work + c.out_off;
   double* r64 = rom64 + rom64_off[blockIdx.x];
   for (int64_t idx = threadIdx.x; idx < 2 * m * bb2; idx += NT) r64[idx] = src[idx];
+  if (cell_failed(c)) return;
+  const double* alpha = work + c.s_off;
+  const double* beta = alpha + m * bb2;
+  double* C0 = work + c.av_off;
+  if (m > 1) {
+    double* binv = C0 + bb2;
+    double* Wk = binv + bb2;
+    double* fac = Wk + bb2;
+    if (!wg_inverse(b, beta, b, binv, b, Wk, fac)) {
+      if (threadIdx.x == 0) c.status = ST_NOTSPD;
+      return;
+    }
+    wg_gemm<false, true>(b, b, b, 1.0, binv, b, beta + bb2, b, 0.0, C0, b);
+  }
+  const double* G1 = src + m * bb2;
   T* dst = blocks + o.blk_off;
   const int ld = o.ld;
   const int64_t bsz = (int64_t)b * ld;
   for (int64_t idx = threadIdx.x; idx < (2 * m - 1) * bsz; idx += NT) {
-    const int k = (int)(idx / bsz);
+    const int j = (int)(idx / bsz);
     const int r = (int)((idx % bsz) / ld), cc = (int)(idx % ld);
-    const double* s = (k < m) ? src + (m + k) * bb2 : src + (k - m + 1) * bb2;
-    dst[idx] = cvt<T>(cc < b ? s[r + (int64_t)cc * b] : 0.0);
+    const int l = j >> 1;
+    double v = 0.0;
+    if (cc < b) {
+      if ((j & 1) == 0) {
+        const double* M = (l == 0) ? G1 : alpha + l * bb2;
+        v = 0.5 * (M[r + (int64_t)cc * b] + M[cc + (int64_t)r * b]);
+        if (l == 0) v = -v;
+      } else {
+        v = (l == 0) ? C0[r + (int64_t)cc * b] : beta[(l + 1) * bb2 + cc + (int64_t)r * b];
+      }
+    }
+    dst[idx] = cvt<T>(v);
   }
 }
 
-hipError_t launch_pack(int32_t ncell, const BuildCell* d_bcells, const double* d_work,
+hipError_t launch_pack(int32_t ncell, BuildCell* d_bcells, double* d_work,
                        const OnlineCell* d_ocells, int32_t prec, void* d_blocks, double* d_rom64,
                        const int64_t* d_rom64_off, hipStream_t st) {
   const dim3 grid(ncell), block(NT);

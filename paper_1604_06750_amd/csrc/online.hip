@@ -2,23 +2,37 @@
 // coupled S-fraction ROM for a batch of sources.
 //
 // Unknowns: reduced piece dofs y_p (the conjugated boundary values of
-// eq. contred) and each cell's hidden layers U^2..U^m. With U^1 the cell's
-// piece dofs gathered in the column order of its boundary basis and
-// U^{m+1} = 0, the step is
+// eq. contred) and each cell's hidden layers. The S-fraction's three-point
+// scheme (eqs. GammaU1st, GammaUrem, intrtstep_td) is stepped after the
+// change of variables U^k = G_k V^k (k >= 2) of its hidden layers, where
+// Ghat^k = G_k G_k^T is the factor of the recursion of eq. GammaTrans. In
+// these variables the hidden layers have unit mass and the cell operator is
+// block tridiagonal with blocks
+//   D_0 = -G^1,   C_0 = G^1 G_2,
+//   D_l = -G_l^T (G^l + G^{l-1}) G_l,  C_l = G_l^T G^l G_{l+1}   (l >= 1,
+// layers counted from 0), i.e. the Lanczos blocks alpha, beta^T of the cell.
+// The form is exactly equivalent, and its blocks are bounded by the
+// largest frequency of the cell, while the blocks G^k and Ghat^k of deep
+// layers can be near singular; rounding D and C to FP32 or BF16 therefore
+// perturbs the spectrum by a unit roundoff of its largest eigenvalue only.
+// With X_0 = U^1 (the cell's piece dofs, gathered in the column order of its
+// boundary basis) and X_l = V^{l+1}:
 //
-//   cell phase   Phi^k = G^k (U^{k+1} - U^k),                k = 1..m
-//                U^k <- 2U^k - U^k_old + dt^2 Ghat^k (Phi^k - Phi^{k-1}),
-//                                                           k = 2..m
-//                (eq. intrtstep_td; Alg. alg1red step 2.2)
+//   cell phase   a_l = C_{l-1}^T X_{l-1} + D_l X_l + C_l X_{l+1}
+//                Phi^1 = a_0 (the flux G^1 (U^2 - U^1) into the pieces),
+//                X_l <- 2X_l - X_l,old + dt^2 a_l,  l >= 1
+//                (Alg. alg1red step 2.2)
 //   piece phase  r_p = sum over the cells owning p of their Phi^1 slice
 //                      + w^n g_p                            (step 2.1)
 //                y_p <- 2y_p - y_p,old + dt^2 M_p^{-1} r_p   (eq. bdrytstep,
 //                M_p = sum_i [(Ghat_i^1)^{-1}]_pp; step 2.3)
 //   receivers    trace = sum_p q_p^T y_p                     (eq. solatrec)
 //
-// State rows hold n_s sources contiguously ([row][source]). The exchange
-// between the two phases goes through the Phi^1 scratch in HBM, summed in a
-// fixed order (no atomics), so results are deterministic.
+// Blocks of a cell are stored in the order D_0, C_0, D_1, C_1, ..., D_{m-1},
+// each b rows of stride ld (row-major, zero padded). State rows hold n_s
+// sources contiguously ([row][source]). The exchange between the two
+// phases goes through the Phi^1 scratch in HBM, summed in a fixed order (no
+// atomics), so results are deterministic.
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
@@ -43,15 +57,15 @@ __device__ inline float ld_block<__hip_bfloat16, float>(const __hip_bfloat16* p)
 
 constexpr int CELL_NT = 256;
 
-// Cell phase. grid = (n_cells, ceil(n_s / nst)); dynamic LDS holds U and Phi
-// for the workgroup's source tile: 2 * max_m * max_b * nst accumulators.
+// Cell phase. grid = (n_cells, ceil(n_s / nst)); dynamic LDS holds the
+// cell's layers X_0..X_{m-1} for the workgroup's source tile (max_m * max_b
+// * nst values of the accumulation type).
 template <typename T, typename TB, typename TA>
 __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
   extern __shared__ unsigned char smem_raw[];
-  TA* U = reinterpret_cast<TA*>(smem_raw);
-  TA* P = U + (int64_t)a.max_m * a.max_b * nst;
+  TA* X = reinterpret_cast<TA*>(smem_raw);
   const OnlineCell c = a.d_cells[blockIdx.x];
-  const int m = c.m, b = c.b, ns = a.ns;
+  const int m = c.m, b = c.b, ld = c.ld, ns = a.ns;
   const int s0 = blockIdx.y * nst;
   const int nsl = min(nst, ns - s0);
   const int lay = b * nst;
@@ -62,51 +76,42 @@ __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
   const int32_t* gat = a.d_gather + c.u1_off;
   for (int idx = threadIdx.x; idx < lay; idx += CELL_NT) {
     const int r = idx / nst, s = idx % nst;
-    U[idx] = (s < nsl) ? (TA)ycur[(int64_t)gat[r] * ns + s0 + s] : (TA)0;
+    X[idx] = (s < nsl) ? (TA)ycur[(int64_t)gat[r] * ns + s0 + s] : (TA)0;
   }
   for (int k = 1; k < m; ++k) {
     const int64_t row0 = c.hid_off + (int64_t)(k - 1) * b;
     for (int idx = threadIdx.x; idx < lay; idx += CELL_NT) {
       const int r = idx / nst, s = idx % nst;
-      U[k * lay + idx] = (s < nsl) ? (TA)hcur[(row0 + r) * ns + s0 + s] : (TA)0;
+      X[k * lay + idx] = (s < nsl) ? (TA)hcur[(row0 + r) * ns + s0 + s] : (TA)0;
     }
   }
   __syncthreads();
   const TB* blk = reinterpret_cast<const TB*>(a.d_blocks) + c.blk_off;
-  // fluxes Phi^k = G^k (U^{k+1} - U^k)
-  for (int idx = threadIdx.x; idx < m * lay; idx += CELL_NT) {
-    const int k = idx / lay, rem = idx % lay;
-    const int r = rem / nst, s = rem % nst;
-    const TB* G = blk + (int64_t)k * b * c.ld + (int64_t)r * c.ld;
-    const TA* Uk = U + k * lay + s;
-    const TA* Un = U + (k + 1) * lay + s;
-    TA acc = 0;
-    if (k + 1 < m) {
-      for (int cc = 0; cc < b; ++cc) acc += ld_block<TB, TA>(G + cc) * (Un[cc * nst] - Uk[cc * nst]);
-    } else {
-      for (int cc = 0; cc < b; ++cc) acc -= ld_block<TB, TA>(G + cc) * Uk[cc * nst];
-    }
-    P[idx] = acc;
-  }
-  __syncthreads();
-  // hidden layers
+  const int64_t bsz = (int64_t)b * ld;
   const TA dt2 = (TA)a.dt2;
-  for (int idx = threadIdx.x; idx < (m - 1) * lay; idx += CELL_NT) {
-    const int k = 1 + idx / lay, rem = idx % lay;
+  for (int idx = threadIdx.x; idx < m * lay; idx += CELL_NT) {
+    const int l = idx / lay, rem = idx % lay;
     const int r = rem / nst, s = rem % nst;
-    const TB* Gh = blk + (int64_t)(m + k - 1) * b * c.ld + (int64_t)r * c.ld;
-    const TA* Pk = P + k * lay + s;
-    const TA* Pm = P + (k - 1) * lay + s;
+    const TA* xs = X + s;
     TA acc = 0;
-    for (int cc = 0; cc < b; ++cc) acc += ld_block<TB, TA>(Gh + cc) * (Pk[cc * nst] - Pm[cc * nst]);
-    if (s < nsl) {
-      const int64_t h = (c.hid_off + (int64_t)(k - 1) * b + r) * ns + s0 + s;
-      hold[h] = (T)((TA)2 * U[k * lay + rem] - (TA)hold[h] + dt2 * acc);
+    const TB* D = blk + 2 * l * bsz + (int64_t)r * ld;
+    for (int cc = 0; cc < b; ++cc) acc += ld_block<TB, TA>(D + cc) * xs[l * lay + cc * nst];
+    if (l > 0) {   // C_{l-1}^T X_{l-1}: column r of C_{l-1}
+      const TB* Cp = blk + (2 * l - 1) * bsz + r;
+      for (int cc = 0; cc < b; ++cc) acc += ld_block<TB, TA>(Cp + (int64_t)cc * ld) * xs[(l - 1) * lay + cc * nst];
     }
-  }
-  for (int idx = threadIdx.x; idx < lay; idx += CELL_NT) {
-    const int r = idx / nst, s = idx % nst;
-    if (s < nsl) phi[(c.u1_off + r) * ns + s0 + s] = (T)P[idx];
+    if (l + 1 < m) {   // C_l X_{l+1}
+      const TB* Cn = blk + (2 * l + 1) * bsz + (int64_t)r * ld;
+      for (int cc = 0; cc < b; ++cc) acc += ld_block<TB, TA>(Cn + cc) * xs[(l + 1) * lay + cc * nst];
+    }
+    if (s < nsl) {
+      if (l == 0) {
+        phi[(c.u1_off + r) * ns + s0 + s] = (T)acc;
+      } else {
+        const int64_t h = (c.hid_off + (int64_t)(l - 1) * b + r) * ns + s0 + s;
+        hold[h] = (T)((TA)2 * X[l * lay + rem] - (TA)hold[h] + dt2 * acc);
+      }
+    }
   }
 }
 
@@ -114,18 +119,20 @@ __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
 // Cell phase on the matrix cores (float state; float or bfloat16 blocks).
 //
 // One workgroup per (cell, tile of 16*CT sources); wave w owns rows
-// [16w, 16w+16) of every b x b block product, so a block is streamed from
-// HBM once per source tile and each wave holds its 16-row strip of the
-// block in registers (NCH float4 per lane). The K dimension is traversed in
-// chunks of 16 with a permuted order: inside a chunk, lane group g = lane/16
-// supplies k = 16 ch + 4 g + j to MFMA step j, so each lane fetches its A
-// values as one float4 from the row-major (symmetric) block and its B values
-// as one float4 from the transposed LDS tile. The strip of the next block is
-// prefetched while the current product runs.
+// [16w, 16w+16) of every layer, so each block is streamed from HBM once per
+// source tile and each wave holds its 16-row strip of the block in
+// registers (NCH fragments per lane). The K dimension is traversed in
+// chunks of 16 with a permuted order: inside a chunk, lane group g =
+// lane/16 supplies k = 16 ch + 4 g + j to MFMA step j, so each lane fetches
+// its A values as one vector from the row-major block (for the transposed
+// coupling block, four scalars from one column) and its B values as one
+// float4 from the transposed LDS tile. Layer l needs up to three strips,
+// C_{l-1}^T, D_l and C_l; the next strip is prefetched while the current
+// product runs.
 //
-// LDS: Dt = (U^{k+1} - U^k)^T and Et = (Phi^k - Phi^{k-1})^T, each
-// [16*CT columns][kp], kp = 16*NCH + 4. The fluxes of the previous layer
-// stay in registers.
+// LDS: three transposed layer tiles [16*CT columns][kp], kp = 16*NCH + 4,
+// used as a ring: X_{l-1}, X_l, X_{l+1} during layer l; X_{l+2} is loaded
+// into registers during layer l and stored over X_{l-1} after it.
 // ---------------------------------------------------------------------------
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -144,20 +151,34 @@ template <>
 struct AFrag<false> {
   float4 v;
   __device__ void load(const float* p) { v = *reinterpret_cast<const float4*>(p); }
+  // A[i][k..k+3] = C[k..k+3][i] of a row-major block with row stride ld,
+  // rows >= nrow read as zero
+  __device__ void load_t(const float* base, int ld, int k, int i, int nrow) {
+    v.x = (k < nrow) ? base[(int64_t)k * ld + i] : 0.f;
+    v.y = (k + 1 < nrow) ? base[(int64_t)(k + 1) * ld + i] : 0.f;
+    v.z = (k + 2 < nrow) ? base[(int64_t)(k + 2) * ld + i] : 0.f;
+    v.w = (k + 3 < nrow) ? base[(int64_t)(k + 3) * ld + i] : 0.f;
+  }
   __device__ void zero() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
 };
 template <>
 struct AFrag<true> {
   shortx4 v;
   __device__ void load(const __hip_bfloat16* p) { v = *reinterpret_cast<const shortx4*>(p); }
+  __device__ void load_t(const __hip_bfloat16* base_, int ld, int k, int i, int nrow) {
+    const short* base = reinterpret_cast<const short*>(base_);
+    v.x = (k < nrow) ? base[(int64_t)k * ld + i] : (short)0;
+    v.y = (k + 1 < nrow) ? base[(int64_t)(k + 1) * ld + i] : (short)0;
+    v.z = (k + 2 < nrow) ? base[(int64_t)(k + 2) * ld + i] : (short)0;
+    v.w = (k + 3 < nrow) ? base[(int64_t)(k + 3) * ld + i] : (short)0;
+  }
   __device__ void zero() { v = shortx4{0, 0, 0, 0}; }
 };
 
+// acc[ct] += A strip x Bt (column tile ct); Bt is a transposed LDS tile
 template <int NCH, int CT, bool BF16>
 __device__ inline void mfma_strip(floatx4 (&acc)[CT], const AFrag<BF16> (&A)[NCH], const float* Bt, int kp,
                                   int nch, int g, int li) {
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
     if (ch < nch) {
@@ -186,13 +207,23 @@ __device__ inline void mfma_strip(floatx4 (&acc)[CT], const AFrag<BF16> (&A)[NCH
   }
 }
 
+// Strip t of layer l: t = 0 is C_{l-1}^T (block 2l-1, transposed), t = 1 is
+// D_l (block 2l), t = 2 is C_l (block 2l+1); t = 0 is absent for l = 0 and
+// t = 2 for l = m-1. Advances (l, t) to the next present strip; returns
+// false past the last one.
+__device__ inline bool next_strip(int m, int& l, int& t) {
+  ++t;
+  if (t == 3 || (t == 2 && l == m - 1)) { ++l; t = 0; }
+  if (l >= m) return false;
+  if (t == 0 && l == 0) t = 1;
+  return true;
+}
+
 template <int NCH, int CT, bool PF, bool BF16>
 __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int ntile) {
   using TB = typename std::conditional<BF16, __hip_bfloat16, float>::type;
   constexpr int NS = 16 * CT;
   extern __shared__ float lds[];
-  float* Dt = lds;
-  float* Et = lds + NS * kp;
   // Workgroups are dealt to the 8 XCDs round-robin; the source tiles of one
   // cell are placed 8 workgroup ids apart so that they land on the same XCD
   // close in time and share its L2 copy of the cell's blocks.
@@ -221,24 +252,23 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
   const TB* __restrict__ blk = reinterpret_cast<const TB*>(a.d_blocks) + c.blk_off;
   const int64_t bsz = (int64_t)b * ld;
   const float dt2 = (float)a.dt2;
+  const int tsz = NS * kp;
 
   AFrag<BF16> Acur[NCH], Anxt[PF ? NCH : 1];
-  auto load_strip = [&](auto& A, const TB* base) {
+  auto load_strip = [&](auto& A, int sl, int st) {
+    const int j = 2 * sl + st - 1;
+    const TB* base = blk + (int64_t)j * bsz;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int kk = ch * 16 + g * 4;
-      if (active && ch < nch && arow < b && kk < ld) A[ch].load(base + (int64_t)arow * ld + kk);
+      if (!active || ch >= nch || arow >= b) A[ch].zero();
+      else if (st == 0) A[ch].load_t(base, ld, kk, arow, b);
+      else if (kk < ld) A[ch].load(base + (int64_t)arow * ld + kk);
       else A[ch].zero();
     }
   };
-  auto copy_strip = [&]() {
-    if constexpr (PF) {
-#pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) Acur[ch] = Anxt[ch];
-    }
-  };
-  // Delta items of this thread: item i covers column col_i and rows
-  // 4 q_i .. 4 q_i + 3 of the transposed tile; NS * 4 * NCH items over
+  // layer items of this thread: item i covers column icol_i and rows
+  // 4 q_i .. 4 q_i + 3 of a transposed tile; NS * 4 * NCH items over
   // 64 * NCH threads is CT items per thread.
   int icol[CT], iq[CT];
   bool iok[CT];
@@ -249,7 +279,7 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
     iq[i] = item / NS;
     iok[i] = iq[i] < 4 * nch;
   }
-  // U^j values of the thread's items (zero outside the cell or the tile)
+  // X_j values of the thread's items (zero outside the cell or the tile)
   auto load_layer = [&](float4 (&v)[CT], int j) {
 #pragma unroll
     for (int i = 0; i < CT; ++i) {
@@ -258,7 +288,7 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
       for (int e = 0; e < 4; ++e) {
         const int kk = 4 * iq[i] + e;
         float t = 0.f;
-        if (j < m && iok[i] && kk < b && icol[i] < nsl) {
+        if (iok[i] && kk < b && icol[i] < nsl) {
           if (j == 0) t = ycur[(int64_t)gat[kk] * ns + s0 + icol[i]];
           else t = hcur[(c.hid_off + (int64_t)(j - 1) * b + kk) * ns + s0 + icol[i]];
         }
@@ -267,268 +297,91 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
       v[i] = make_float4(x[0], x[1], x[2], x[3]);
     }
   };
-
-  float4 UA[CT], UB[CT];
-  load_layer(UA, 0);
-  load_layer(UB, 1);
-  load_strip(Acur, blk);                       // G^1
-  floatx4 prev[CT];
-  for (int k = 0; k < m; ++k) {
-    // Dt = (U^{k+1} - U^k)^T; U^{m+1} = 0 (load_layer returns zeros for j >= m)
+  auto store_layer = [&](const float4 (&v)[CT], int j) {
+    float* T = lds + (j % 3) * tsz;
 #pragma unroll
-    for (int i = 0; i < CT; ++i) {
-      if (iok[i]) {
-        const float4 d = make_float4(UB[i].x - UA[i].x, UB[i].y - UA[i].y, UB[i].z - UA[i].z, UB[i].w - UA[i].w);
-        *reinterpret_cast<float4*>(Dt + icol[i] * kp + 4 * iq[i]) = d;
-      }
-      UA[i] = UB[i];
+    for (int i = 0; i < CT; ++i)
+      if (iok[i]) *reinterpret_cast<float4*>(T + icol[i] * kp + 4 * iq[i]) = v[i];
+  };
+
+  {
+    float4 v[CT];
+    load_layer(v, 0);
+    store_layer(v, 0);
+    if (m > 1) {
+      load_layer(v, 1);
+      store_layer(v, 1);
     }
-    if (k + 2 <= m) load_layer(UB, k + 2);     // in flight during this layer's products
-    __syncthreads();
-    if (PF) {
-      if (k >= 1) load_strip(Anxt, blk + (int64_t)(m + k - 1) * bsz);
-      else if (m > 1) load_strip(Anxt, blk + bsz);
-    }
-    floatx4 acc[CT];
-    if (active) mfma_strip<NCH, CT, BF16>(acc, Acur, Dt, kp, nch, g, li);
-    // operands of the hidden-layer update, loaded before the second product
-    float hc[CT][4], ho[CT][4];
-    if (k >= 1 && active) {
+  }
+  load_strip(Acur, 0, 1);                      // D_0
+  __syncthreads();
+  int pl = 0, pt = 1;                          // strip held in Acur
+  for (int ly = 0; ly < m; ++ly) {
+    float4 xn[CT];
+    if (ly + 2 < m) load_layer(xn, ly + 2);    // in flight during this layer's products
+    float ho[CT][4];
+    if (ly >= 1 && active) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = w * 16 + 4 * g + r, col = ct * 16 + li;
-          const bool ok = row < b && col < nsl;
-          const int64_t hi = (c.hid_off + (int64_t)(k - 1) * b + row) * ns + s0 + col;
-          hc[ct][r] = ok ? hcur[hi] : 0.f;
-          ho[ct][r] = ok ? hold[hi] : 0.f;
+          ho[ct][r] = (row < b && col < nsl)
+                          ? hold[(c.hid_off + (int64_t)(ly - 1) * b + row) * ns + s0 + col] : 0.f;
         }
+    }
+    floatx4 acc[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // the strips of this layer, in order
+    while (pl == ly) {
+      int nl = pl, nt = pt;
+      const bool more = next_strip(m, nl, nt);
+      if (PF && more) load_strip(Anxt, nl, nt);
+      if (active) mfma_strip<NCH, CT, BF16>(acc, Acur, lds + ((ly + pt + 2) % 3) * tsz, kp, nch, g, li);
+      if (more) {
+        if constexpr (PF) {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) Acur[ch] = Anxt[ch];
+        } else {
+          load_strip(Acur, nl, nt);
+        }
+      }
+      pl = more ? nl : m;
+      pt = nt;
     }
     if (active) {
+      const float* Tl = lds + (ly % 3) * tsz;
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + li;
-        if (k == 0) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = w * 16 + 4 * g + r;
-            if (row < b && col < nsl) phi[(c.u1_off + row) * ns + s0 + col] = acc[ct][r];
-          }
-        } else {
-          const floatx4 e = acc[ct] - prev[ct];
-          *reinterpret_cast<float4*>(Et + col * kp + w * 16 + 4 * g) = make_float4(e[0], e[1], e[2], e[3]);
-        }
-        prev[ct] = acc[ct];
-      }
-    }
-    __syncthreads();
-    if (PF) copy_strip();
-    else if (k >= 1) load_strip(Acur, blk + (int64_t)(m + k - 1) * bsz);
-    else if (m > 1) load_strip(Acur, blk + bsz);
-    if (k >= 1) {
-      if (PF && k + 1 < m) load_strip(Anxt, blk + (int64_t)(k + 1) * bsz);
-      floatx4 acc2[CT];
-      if (active) {
-        mfma_strip<NCH, CT, BF16>(acc2, Acur, Et, kp, nch, g, li);
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-          const int col = ct * 16 + li;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = w * 16 + 4 * g + r;
-            if (row < b && col < nsl) {
-              const int64_t hi = (c.hid_off + (int64_t)(k - 1) * b + row) * ns + s0 + col;
-              hold[hi] = 2.f * hc[ct][r] - ho[ct][r] + dt2 * acc2[ct][r];
-            }
-          }
-        }
-      }
-      if (PF) copy_strip();
-      else if (k + 1 < m) load_strip(Acur, blk + (int64_t)(k + 1) * bsz);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Streaming variant of the matrix-core cell phase: NW = ceil(nch / TPW)
-// waves per workgroup, each owning TPW 16-row tiles and streaming its A
-// fragments from HBM through a register ring of RING chunks. Registers and
-// LDS per workgroup are small, so several cells are in flight per CU and the
-// latency of one cell's loads is hidden behind another cell's products.
-// ---------------------------------------------------------------------------
-template <int TPW, int CT, bool BF16>
-__global__ __launch_bounds__(256) void k_cell_stream(StepArgs a, int kp, int ntile) {
-  using TB = typename std::conditional<BF16, __hip_bfloat16, float>::type;
-  constexpr int NS = 16 * CT;
-  constexpr int RING = 4;
-  extern __shared__ float lds[];
-  float* Dt = lds;
-  float* Et = lds + NS * kp;
-  int cell, tile;
-  {
-    const int bid = blockIdx.x;
-    const int grp = bid / (8 * ntile), r = bid % (8 * ntile);
-    tile = r / 8;
-    cell = grp * 8 + r % 8;
-    if (cell >= a.ncell) return;
-  }
-  const OnlineCell c = a.d_cells[cell];
-  const int m = c.m, b = c.b, ld = c.ld, ns = a.ns;
-  const int s0 = tile * NS;
-  const int nsl = min(NS, ns - s0);
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int nw = nthr >> 6;
-  const int w = tid >> 6, l = tid & 63, g = l >> 4, li = l & 15;
-  const int nch = (b + 15) >> 4;
-  const float* __restrict__ ycur = reinterpret_cast<const float*>(a.y_cur);
-  const float* __restrict__ hcur = reinterpret_cast<const float*>(a.h_cur);
-  float* __restrict__ hold = reinterpret_cast<float*>(a.h_old);
-  float* __restrict__ phi = reinterpret_cast<float*>(a.phi);
-  const int32_t* __restrict__ gat = a.d_gather + c.u1_off;
-  const TB* __restrict__ blk = reinterpret_cast<const TB*>(a.d_blocks) + c.blk_off;
-  const int64_t bsz = (int64_t)b * ld;
-  const float dt2 = (float)a.dt2;
-
-  // product of the wave's row tiles of block `base` with the transposed LDS
-  // tile Bt; results in acc[t][ct]
-  auto product = [&](floatx4 (&acc)[TPW][CT], const TB* base, const float* Bt) {
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) acc[t][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-      const int rt = w + t * nw;
-      if (rt >= nch) continue;
-      const int row = rt * 16 + li;
-      const bool rok = row < b;
-      const TB* rp = base + (int64_t)(rok ? row : 0) * ld;
-      AFrag<BF16> ring[RING];
-#pragma unroll
-      for (int u = 0; u < RING; ++u) {
-        const int kk = u * 16 + g * 4;
-        if (u < nch && rok && kk < ld) ring[u].load(rp + kk); else ring[u].zero();
-      }
-      for (int ch0 = 0; ch0 < nch; ch0 += RING) {
-#pragma unroll
-        for (int u = 0; u < RING; ++u) {
-          const int ch = ch0 + u;
-          if (ch < nch) {
-            const AFrag<BF16> av = ring[u];
-            const int kn = (ch + RING) * 16 + g * 4;
-            if (ch + RING < nch && rok && kn < ld) ring[u].load(rp + kn); else ring[u].zero();
-            float4 bv[CT];
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-              bv[ct] = *reinterpret_cast<const float4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
-            if constexpr (!BF16) {
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct) acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.v.x, bv[ct].x, acc[t][ct], 0, 0, 0);
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct) acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.v.y, bv[ct].y, acc[t][ct], 0, 0, 0);
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct) acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.v.z, bv[ct].z, acc[t][ct], 0, 0, 0);
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct) acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.v.w, bv[ct].w, acc[t][ct], 0, 0, 0);
+        for (int r = 0; r < 4; ++r) {
+          const int row = w * 16 + 4 * g + r;
+          if (row < b && col < nsl) {
+            if (ly == 0) {
+              phi[(c.u1_off + row) * ns + s0 + col] = acc[ct][r];
             } else {
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct) {
-                const shortx4 bb = shortx4{f2bf(bv[ct].x), f2bf(bv[ct].y), f2bf(bv[ct].z), f2bf(bv[ct].w)};
-                acc[t][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av.v, bb, acc[t][ct], 0, 0, 0);
-              }
+              const int64_t hi = (c.hid_off + (int64_t)(ly - 1) * b + row) * ns + s0 + col;
+              hold[hi] = 2.f * Tl[col * kp + row] - ho[ct][r] + dt2 * acc[ct][r];
             }
           }
         }
       }
     }
-  };
-
-  floatx4 prev[TPW][CT];
-  for (int k = 0; k < m; ++k) {
-    // Dt = (U^{k+1} - U^k)^T, zero padded to 16 nch rows and NS columns
-    for (int t = tid; t < NS * 4 * nch; t += nthr) {
-      const int col = t % NS, q = t / NS;
-      float v[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int kk = 4 * q + e;
-        float d = 0.f;
-        if (kk < b && col < nsl) {
-          const float un = (k + 1 < m) ? hcur[(c.hid_off + (int64_t)k * b + kk) * ns + s0 + col] : 0.f;
-          const float uc = (k == 0) ? ycur[(int64_t)gat[kk] * ns + s0 + col]
-                                    : hcur[(c.hid_off + (int64_t)(k - 1) * b + kk) * ns + s0 + col];
-          d = un - uc;
-        }
-        v[e] = d;
-      }
-      *reinterpret_cast<float4*>(Dt + col * kp + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
+    if (ly + 2 < m) {
+      __syncthreads();                         // every wave is done with X_{ly-1}
+      store_layer(xn, ly + 2);
+      __syncthreads();
     }
-    __syncthreads();
-    floatx4 acc[TPW][CT];
-    product(acc, blk + (int64_t)k * bsz, Dt);
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int rt = w + t * nw;
-      if (rt >= nch) continue;
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int col = ct * 16 + li;
-        if (k == 0) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = rt * 16 + 4 * g + r;
-            if (row < b && col < nsl) phi[(c.u1_off + row) * ns + s0 + col] = acc[t][ct][r];
-          }
-        } else {
-          const floatx4 e = acc[t][ct] - prev[t][ct];
-          *reinterpret_cast<float4*>(Et + col * kp + rt * 16 + 4 * g) = make_float4(e[0], e[1], e[2], e[3]);
-        }
-        prev[t][ct] = acc[t][ct];
-      }
-    }
-    __syncthreads();
-    if (k >= 1) {
-      floatx4 acc2[TPW][CT];
-      product(acc2, blk + (int64_t)(m + k - 1) * bsz, Et);
-#pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        const int rt = w + t * nw;
-        if (rt >= nch) continue;
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-          const int col = ct * 16 + li;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = rt * 16 + 4 * g + r;
-            if (row < b && col < nsl) {
-              const int64_t hi = (c.hid_off + (int64_t)(k - 1) * b + row) * ns + s0 + col;
-              hold[hi] = 2.f * hcur[hi] - hold[hi] + dt2 * acc2[t][ct][r];
-            }
-          }
-        }
-      }
-    }
-    // Dt is rewritten at the next layer only after every wave has finished
-    // reading it (the barrier above), and Et only after the next barrier
   }
-}
-
-template <int TPW, int CT, bool BF16>
-static void launch_stream(const StepArgs& a, hipStream_t st) {
-  constexpr int NS = 16 * CT;
-  const int nchmax = (a.max_b + 15) / 16;
-  const int kp = 16 * nchmax + 4;
-  const int nw = (nchmax + TPW - 1) / TPW;
-  const size_t lds = 2 * (size_t)NS * kp * sizeof(float);
-  const int ntile = (a.ns + NS - 1) / NS;
-  const int groups = (a.ncell + 7) / 8;
-  hipLaunchKernelGGL((k_cell_stream<TPW, CT, BF16>), dim3(groups * 8 * ntile), dim3(64 * nw), lds, st, a, kp, ntile);
 }
 
 template <int NCH, int CT, bool PF, bool BF16>
 static void launch_mfma(const StepArgs& a, hipStream_t st) {
   constexpr int NS = 16 * CT;
   const int kp = 16 * NCH + 4;
-  const size_t lds = 2 * (size_t)NS * kp * sizeof(float);
+  const size_t lds = 3 * (size_t)NS * kp * sizeof(float);
   const int ntile = (a.ns + NS - 1) / NS;
   const int groups = (a.ncell + 7) / 8;
   hipLaunchKernelGGL((k_cell_mfma<NCH, CT, PF, BF16>), dim3(groups * 8 * ntile), dim3(64 * NCH), lds, st, a, kp,
@@ -537,6 +390,9 @@ static void launch_mfma(const StepArgs& a, hipStream_t st) {
 
 template <int NCH, bool BF16>
 static void launch_variant(const StepArgs& a, int variant, hipStream_t st) {
+  // three layer tiles of 64 sources exceed the 160 KiB of LDS beyond 12
+  // chunks: use the 32-source tile there
+  if (3 * 64 * (16 * NCH + 4) * 4 > 160 * 1024) variant |= 2;
   switch (variant) {
     case 0: launch_mfma<NCH, 4, true, BF16>(a, st); break;
     case 1: launch_mfma<NCH, 4, false, BF16>(a, st); break;
@@ -548,16 +404,6 @@ static void launch_variant(const StepArgs& a, int variant, hipStream_t st) {
 template <bool BF16>
 static hipError_t mfma_dispatch(const StepArgs& a, int variant, hipStream_t st) {
   const int need = (a.max_b + 15) / 16;
-  if (variant >= 4) {
-    if ((need + 1) / 2 > 4 && variant < 6) variant += 2;   // keep <= 4 waves per group
-    switch (variant) {
-      case 4: launch_stream<2, 1, BF16>(a, st); break;
-      case 5: launch_stream<2, 2, BF16>(a, st); break;
-      case 6: launch_stream<3, 1, BF16>(a, st); break;
-      default: launch_stream<3, 2, BF16>(a, st); break;
-    }
-    return hipGetLastError();
-  }
   if (need <= 4) launch_variant<4, BF16>(a, variant, st);
   else if (need <= 6) launch_variant<6, BF16>(a, variant, st);
   else if (need <= 7) launch_variant<7, BF16>(a, variant, st);
@@ -673,7 +519,7 @@ __global__ __launch_bounds__(256) void k_receivers(StepArgs a) {
 int cell_tile(const StepArgs& a, size_t acc_bytes) {
   // largest power-of-two source tile (<= 64) whose LDS fits in 64 KiB
   int nst = 64;
-  while (nst > 1 && 2 * (size_t)a.max_m * a.max_b * nst * acc_bytes > 65536) nst /= 2;
+  while (nst > 1 && (size_t)a.max_m * a.max_b * nst * acc_bytes > 65536) nst /= 2;
   if (nst > a.ns) {
     int t = 1;
     while (t < a.ns) t *= 2;
@@ -685,7 +531,7 @@ int cell_tile(const StepArgs& a, size_t acc_bytes) {
 template <typename T, typename TB, typename TA>
 static hipError_t cell_impl(const StepArgs& a, hipStream_t st) {
   const int nst = cell_tile(a, sizeof(TA));
-  const size_t lds = 2 * (size_t)a.max_m * a.max_b * nst * sizeof(TA);
+  const size_t lds = (size_t)a.max_m * a.max_b * nst * sizeof(TA);
   const dim3 g1(a.ncell, (a.ns + nst - 1) / nst);
   hipLaunchKernelGGL((k_cell_phase<T, TB, TA>), g1, dim3(CELL_NT), lds, st, a, nst);
   return hipGetLastError();
@@ -711,14 +557,12 @@ static hipError_t rec_impl(const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int cell_variants(const StepArgs& a) { return (a.prec == SFROM_F64 || a.max_b > 256) ? 1 : 9; }
+int cell_variants(const StepArgs& a) { return (a.prec == SFROM_F64 || a.max_b > 256) ? 1 : 5; }
 
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st) {
-  // variants 0..3: matrix-core kernel with one wave per row strip (source
-  // tile 64/32, with/without strip prefetch); 4..7: streaming matrix-core
-  // kernel (2 or 3 row tiles per wave, source tile 16/32); 8 (and FP64): the
-  // scalar kernel
-  if (a.prec == SFROM_F64 || a.max_b > 256 || a.cell_variant >= 8) {
+  // variants 0..3: matrix-core kernel (source tile 64/32, with/without strip
+  // prefetch); 4 (and FP64): the scalar kernel
+  if (a.prec == SFROM_F64 || a.max_b > 256 || a.cell_variant >= 4) {
     if (a.prec == SFROM_F64) return cell_impl<double, double, double>(a, st);
     if (a.prec == SFROM_F32) return cell_impl<float, float, float>(a, st);
     return cell_impl<float, __hip_bfloat16, float>(a, st);

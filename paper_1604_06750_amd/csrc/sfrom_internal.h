@@ -76,7 +76,7 @@ struct OnlineCell {
   int32_t m, b;
   int32_t ld;        // row stride of every stored block (b rounded up to 4, zero padded)
   int32_t pad_;
-  int64_t blk_off;   // elements into the block array: G^1..G^m, Ghat^2..Ghat^m (b x ld each)
+  int64_t blk_off;   // elements into the block array: D_0, C_0, ..., D_{m-1} (b x ld each)
   int64_t hid_off;   // rows into the hidden state ((m-1) b rows of n_s)
   int64_t u1_off;    // rows into the gather map / phi scratch (b rows)
 };
@@ -117,7 +117,7 @@ struct BuildBatch {
 hipError_t launch_build(const BuildBatch& bb, hipStream_t st);
 
 // Pack the double S-fraction of one batch into the on-line layout.
-hipError_t launch_pack(int32_t ncell, const BuildCell* d_bcells, const double* d_work,
+hipError_t launch_pack(int32_t ncell, BuildCell* d_bcells, double* d_work,
                        const OnlineCell* d_ocells, int32_t prec, void* d_blocks,
                        double* d_rom64, const int64_t* d_rom64_off, hipStream_t st);
 

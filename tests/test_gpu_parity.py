@@ -35,16 +35,19 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
 
 
-def _gpu_rom(wl, prec, dt, w, m=None, m_per_cell=None):
+def _gpu_rom(wl, prec, dt, w, m=None, m_per_cell=None, variant=None):
     S, P = _lib()
     h = _handle(S)
     try:
         P.setup(h, wl)
+        if variant is not None:
+            S.sfrom_set_cell_variant(h, variant)
         S.sfrom_build(h, m or wl.m, wl.shift, prec, m_per_cell=m_per_cell)
         info = S.sfrom_get_info(h)
         tr = np.zeros((len(w), info["n_receivers"], info["n_sources"]),
                       np.float64 if prec == S.SFROM_F64 else np.float32)
         S.sfrom_run(h, len(w), dt, w, tr)
+        info = S.sfrom_get_info(h)      # now with the cell-phase variant used
         blocks = {i: S.sfrom_export_rom(h, i) for i in range(info["n_cells"])}
         return tr, blocks, info
     finally:
@@ -178,6 +181,46 @@ def test_uneven_layers_per_cell(dev):
     assert rel(tr, ref) <= 1e-10
 
 
+def test_uneven_layers_matrix_cores(dev):
+    """Per-cell layer counts 1..4 in one launch of the FP32 matrix-core cell
+    phase (every variant) and the scalar kernel: m = 1 has only D_0, m = 2
+    no interior layer, so each branch of the strip sequence is exercised."""
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3, n_steps=300)
+    run = pipeline.setup(wl)
+    mpc = np.array([1, 2, 3, 4, 4, 3, 2, 1], np.int32)
+    part, sigma, rho = run.part, wl.sigma, wl.rho
+    for i in range(len(part.cells)):
+        Ai, bi = part.cell_operator(i, sigma, rho)
+        run.blocks[i] = build_cell(Ai, bi, part.cell_W(i), wl.shift, int(mpc[i]))
+    ref = pipeline.rom_traces(run)
+    for v in range(5):
+        tr, _, info = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w, m_per_cell=mpc, variant=v)
+        e = rel(tr, ref)
+        print(f"variant {v} (used {info['cell_variant']}): rel L2 vs oracle {e:.2e}")
+        assert info["cell_variant"] == v
+        assert e <= 1e-4
+
+
+def test_cell_variants_match_oracle(dev):
+    """Each cell-phase variant (matrix cores with 64/32-source tiles, with
+    and without strip prefetch, and the scalar kernel) in FP32 at b = 98
+    with 16 sources: a ragged last source tile for the 64-source variants."""
+    S, P = _lib()
+    wl = synth.workload("small", modes_face=9, modes_edge=3, m=3, n_steps=300)
+    fi = synth.face_interior_nodes(wl.nvox, wl.cuts)
+    rng = np.random.default_rng(21)
+    wl.sources = fi[np.sort(rng.choice(len(fi), 40, replace=False))]
+    run = pipeline.setup(wl)
+    pipeline.build_all(run)
+    ref = pipeline.rom_traces(run)
+    for v in range(5):
+        tr, _, info = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w, variant=v)
+        e = rel(tr, ref)
+        print(f"variant {v}: rel L2 vs oracle {e:.2e}")
+        assert e <= 1e-4
+
+
 def test_breakdown_is_reported(dev):
     """A partition whose Krylov blocks lose rank (a corner node with no
     interior neighbour in a 2D slab, m = 2) must fail with EBREAKDOWN."""
@@ -246,25 +289,34 @@ def test_online_bf16_small_b(dev):
     assert e <= 5e-2
 
 
-def test_online_bf16_divergence_reported(dev):
-    """At b = 140 BF16-rounded blocks are no longer semidefinite enough for
-    the leap-frog scheme; the run must end with ENONFINITE instead of
-    returning non-finite traces silently."""
+def test_online_bf16_large_b_is_finite_or_reported(dev):
+    """BF16 blocks at b = 140, 600 steps: the error against the FP64 oracle
+    is printed (8-bit blocks perturb the low frequencies of the band by a
+    unit roundoff of the cell's largest eigenvalue, so this is a reported
+    figure, not a parity bound); the run either returns finite traces or
+    ends with ENONFINITE, never silent NaN."""
     S, P = _lib()
     wl = synth.workload("small", modes_face=16, modes_edge=3, m=3, n_steps=600)
     run = pipeline.setup(wl)
-    with pytest.raises(S.SfromError) as e:
-        _gpu_rom(wl, S.SFROM_BF16, run.dt, run.w)
-    assert e.value.name == "ENONFINITE"
+    pipeline.build_all(run)
+    ref = pipeline.rom_traces(run)
+    try:
+        tr, _, info = _gpu_rom(wl, S.SFROM_BF16, run.dt, run.w)
+    except S.SfromError as e:
+        assert e.name == "ENONFINITE"
+        print("BF16 b=140: ENONFINITE")
+        return
+    assert np.isfinite(tr).all()
+    print(f"BF16 max_b {info['max_b']}: rel L2 vs oracle {rel(tr, ref):.3e}")
 
 
 def test_uneven_cells_layered_medium(dev):
     """Non-uniform cells (8..16 voxels along x, y; layer-aligned in z) with a
     per-cell layer count from the cell size: uneven (m_i, b_i) in one
-    launch, FP64 against the oracle (1e-10). In FP32 the deepest layers of
-    the largest cells hold near-singular blocks (condition numbers up to
-    1e16) whose rounding makes the scheme unstable; the run must report
-    ENONFINITE."""
+    launch. FP64 against the oracle (1e-10) and FP32 (1e-4). The deepest
+    layers of the largest cells hold near-singular S-fraction blocks
+    (condition numbers up to 1e16); the unit-mass on-line form keeps FP32
+    stable there."""
     S, P = _lib()
     wl = synth.workload("layered_small", modes_face=4, modes_edge=2, n_steps=400)
     mpc = wl.extra["m_per_cell"]
@@ -275,12 +327,12 @@ def test_uneven_cells_layered_medium(dev):
         run.blocks[i] = build_cell(Ai, bi, part.cell_W(i), wl.shift, int(mpc[i]))
     ref = pipeline.rom_traces(run)
     tr64, _, info = _gpu_rom(wl, S.SFROM_F64, run.dt, run.w, m_per_cell=mpc)
-    e64 = rel(tr64, ref)
-    print(f"layered: {info['n_cells']} cells, max m {info['max_m']}, max b {info['max_b']}: FP64 {e64:.2e}")
+    tr32, _, _ = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w, m_per_cell=mpc)
+    e64, e32 = rel(tr64, ref), rel(tr32, ref)
+    print(f"layered: {info['n_cells']} cells, max m {info['max_m']}, max b {info['max_b']}: "
+          f"FP64 {e64:.2e}, FP32 {e32:.2e}")
     assert e64 <= 1e-10
-    with pytest.raises(S.SfromError) as e:
-        _gpu_rom(wl, S.SFROM_F32, run.dt, run.w, m_per_cell=mpc)
-    assert e.value.name == "ENONFINITE"
+    assert e32 <= 1e-4
 
 
 def test_graph_replay_matches_eager(dev):
