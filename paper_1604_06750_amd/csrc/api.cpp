@@ -360,7 +360,7 @@ void build(sfrom_t* h, const sfrom_build_opts* o) {
   // ---- on-line layout -------------------------------------------------------
   h->ocells.resize(nc);
   std::vector<int32_t> gather;
-  int64_t blk = 0, hid = 0, u1 = 0, r64 = 0;
+  int64_t blk = 0, hid = 0, hdofs = 0, u1 = 0, r64 = 0;
   h->rom64_off.resize(nc);
   for (int i = 0; i < nc; ++i) {
     OnlineCell& oc = h->ocells[i];
@@ -372,7 +372,8 @@ void build(sfrom_t* h, const sfrom_build_opts* o) {
     oc.hid_off = hid;
     oc.u1_off = u1;
     blk += (int64_t)(2 * oc.m - 1) * oc.b * oc.ld;
-    hid += (int64_t)(oc.m - 1) * oc.b;
+    hid += (int64_t)(oc.m - 1) * oc.ld;
+    hdofs += (int64_t)(oc.m - 1) * oc.b;
     u1 += oc.b;
     h->rom64_off[i] = r64;
     r64 += (int64_t)2 * oc.m * oc.b * oc.b;
@@ -381,7 +382,8 @@ void build(sfrom_t* h, const sfrom_build_opts* o) {
       for (int l = 0; l < h->pieces[p].b; ++l) gather.push_back((int32_t)(h->piece_dof_off[p] + l));
     }
   }
-  h->n_hidden_dofs = hid;
+  h->n_hidden_dofs = hdofs;
+  h->n_hidden_rows = hid;
   h->block_elems = blk;
   h->opieces.resize(np);
   std::vector<int64_t> inc;
@@ -627,14 +629,14 @@ void prepare_online(sfrom_t* h) {
     for (int k = 0; k < 2; ++k) {
       dfree(h->d_y[k]); dfree(h->d_h[k]);
       h->d_y[k] = dalloc<unsigned char>(h, (size_t)npd * ns * eb);
-      h->d_h[k] = dalloc<unsigned char>(h, (size_t)std::max<int64_t>(h->n_hidden_dofs, 1) * ns * eb);
+      h->d_h[k] = dalloc<unsigned char>(h, (size_t)std::max<int64_t>(h->n_hidden_rows, 1) * ns * eb);
     }
     dfree(h->d_phi);
     h->d_phi = dalloc<unsigned char>(h, (size_t)nu1 * ns * eb);
     h->state_ns = ns;
     for (int k = 0; k < 2; ++k) {
       HIPCHK(hipMemsetAsync(h->d_y[k], 0, (size_t)npd * ns * eb, h->stream));
-      HIPCHK(hipMemsetAsync(h->d_h[k], 0, (size_t)std::max<int64_t>(h->n_hidden_dofs, 1) * ns * eb, h->stream));
+      HIPCHK(hipMemsetAsync(h->d_h[k], 0, (size_t)std::max<int64_t>(h->n_hidden_rows, 1) * ns * eb, h->stream));
     }
     h->cur = 0;
   }
@@ -659,7 +661,7 @@ int autotune_cell(sfrom_t* h, StepArgs a) {
   int64_t nu1 = 0;
   for (auto& oc : h->ocells) nu1 += oc.b;
   const size_t ybytes = (size_t)npd * a.ns * eb;
-  const size_t hbytes = (size_t)std::max<int64_t>(h->n_hidden_dofs, 1) * a.ns * eb;
+  const size_t hbytes = (size_t)std::max<int64_t>(h->n_hidden_rows, 1) * a.ns * eb;
   const size_t pbytes = (size_t)nu1 * a.ns * eb;
   void* sy = dalloc<unsigned char>(h, ybytes);
   void* sh0 = dalloc<unsigned char>(h, hbytes);
@@ -802,7 +804,7 @@ done:
     HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), h->stream));
     const int64_t npd = h->piece_dof_off.back();
     HIPCHK(launch_nonfinite(h->d_y[h->cur], npd * ns, h->prec, h->d_flag, h->stream));
-    HIPCHK(launch_nonfinite(h->d_h[h->cur], h->n_hidden_dofs * ns, h->prec, h->d_flag, h->stream));
+    HIPCHK(launch_nonfinite(h->d_h[h->cur], h->n_hidden_rows * ns, h->prec, h->d_flag, h->stream));
     int32_t flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1364,6 +1366,8 @@ int sfrom_rom_lambda_max(sfrom_t* h, double* lambda) {
   HIPCHK(hipMemcpy(r64.data(), h->d_rom64, tot * 8, hipMemcpyDeviceToHost));
   const int64_t npd = h->piece_dof_off.back();
   const int64_t ndof = npd + h->n_hidden_dofs;
+  std::vector<int64_t> hoff(nc + 1, 0);   // hidden dofs of the cells, unpadded
+  for (int i = 0; i < nc; ++i) hoff[i + 1] = hoff[i] + (int64_t)(h->ocells[i].m - 1) * h->ocells[i].b;
   // symmetric square roots of the mass blocks: piece masses M_p and hidden (Ghat^k)^{-1}
   auto symsqrt = [](int n, const double* A, double* out, bool inverse) {
     // Jacobi eigen-decomposition (small n)
@@ -1441,7 +1445,7 @@ int sfrom_rom_lambda_max(sfrom_t* h, double* lambda) {
     for (int i = 0; i < nc; ++i) {
       const int m = h->ocells[i].m, b = h->ocells[i].b;
       for (int k = 1; k < m; ++k) {
-        const int64_t o = npd + h->ocells[i].hid_off + (int64_t)(k - 1) * b;
+        const int64_t o = npd + hoff[i] + (int64_t)(k - 1) * b;
         const double* S = hsq[i].data() + (int64_t)(k - 1) * b * b;
         for (int r = 0; r < b; ++r) { double s = 0.0; for (int c = 0; c < b; ++c) s += S[r + c * b] * x[o + c]; y[o + r] = s; }
       }
@@ -1460,7 +1464,7 @@ int sfrom_rom_lambda_max(sfrom_t* h, double* lambda) {
         const int32_t p = h->cell_pieces[i][q];
         for (int l = 0; l < h->pieces[p].b; ++l) rows[r0++] = h->piece_dof_off[p] + l;
       }
-      for (int k = 1; k < m; ++k) for (int r = 0; r < b; ++r) rows[(size_t)k * b + r] = npd + h->ocells[i].hid_off + (int64_t)(k - 1) * b + r;
+      for (int k = 1; k < m; ++k) for (int r = 0; r < b; ++r) rows[(size_t)k * b + r] = npd + hoff[i] + (int64_t)(k - 1) * b + r;
       // (-L U)^k = -(Phi^k - Phi^{k-1}), Phi^k = G^k (U^{k+1} - U^k)
       std::vector<double> phi((size_t)m * b);
       for (int k = 0; k < m; ++k)

@@ -79,10 +79,10 @@ __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
     X[idx] = (s < nsl) ? (TA)ycur[(int64_t)gat[r] * ns + s0 + s] : (TA)0;
   }
   for (int k = 1; k < m; ++k) {
-    const int64_t row0 = c.hid_off + (int64_t)(k - 1) * b;
+    const T* hl = hcur + (c.hid_off + (int64_t)(k - 1) * ld) * ns;
     for (int idx = threadIdx.x; idx < lay; idx += CELL_NT) {
-      const int r = idx / nst, s = idx % nst;
-      X[k * lay + idx] = (s < nsl) ? (TA)hcur[(row0 + r) * ns + s0 + s] : (TA)0;
+      const int r = idx % b, s = idx / b;
+      X[k * lay + r * nst + s] = (s < nsl) ? (TA)hl[(int64_t)(s0 + s) * ld + r] : (TA)0;
     }
   }
   __syncthreads();
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
   const TA dt2 = (TA)a.dt2;
   for (int idx = threadIdx.x; idx < m * lay; idx += CELL_NT) {
     const int l = idx / lay, rem = idx % lay;
-    const int r = rem / nst, s = rem % nst;
+    const int r = rem % b, s = rem / b;     // consecutive threads: consecutive rows
     const TA* xs = X + s;
     TA acc = 0;
     const TB* D = blk + 2 * l * bsz + (int64_t)r * ld;
@@ -108,8 +108,8 @@ __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
       if (l == 0) {
         phi[(c.u1_off + r) * ns + s0 + s] = (T)acc;
       } else {
-        const int64_t h = (c.hid_off + (int64_t)(l - 1) * b + r) * ns + s0 + s;
-        hold[h] = (T)((TA)2 * X[l * lay + rem] - (TA)hold[h] + dt2 * acc);
+        const int64_t h = (c.hid_off + (int64_t)(l - 1) * ld) * ns + (int64_t)(s0 + s) * ld + r;
+        hold[h] = (T)((TA)2 * X[l * lay + r * nst + s] - (TA)hold[h] + dt2 * acc);
       }
     }
   }
@@ -119,20 +119,23 @@ __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
 // Cell phase on the matrix cores (float state; float or bfloat16 blocks).
 //
 // One workgroup per (cell, tile of 16*CT sources); wave w owns rows
-// [16w, 16w+16) of every layer, so each block is streamed from HBM once per
-// source tile and each wave holds its 16-row strip of the block in
-// registers (NCH fragments per lane). The K dimension is traversed in
-// chunks of 16 with a permuted order: inside a chunk, lane group g =
-// lane/16 supplies k = 16 ch + 4 g + j to MFMA step j, so each lane fetches
-// its A values as one vector from the row-major block (for the transposed
-// coupling block, four scalars from one column) and its B values as one
-// float4 from the transposed LDS tile. Layer l needs up to three strips,
-// C_{l-1}^T, D_l and C_l; the next strip is prefetched while the current
-// product runs.
+// [16w, 16w+16) of every layer. The cell's blocks are consumed as one
+// stream of 16-column chunks: for layer l the strips C_{l-1}^T, D_l, C_l
+// (block 2l+t-1 for t = 0, 1, 2; t = 0 absent for l = 0, t = 2 for
+// l = m-1), each nch = ceil(b/16) chunks. Every wave keeps the next R
+// chunks of its strip in flight in a register ring, across strip and layer
+// boundaries, so the A operand is read from HBM once per source tile
+// without holding whole strips in registers. Inside a chunk, lane group
+// g = lane/16 supplies k = 16 ch + 4 g + j to MFMA step j: each lane reads
+// its A values as one vector from the row-major block (four scalars from
+// one column for the transposed C_{l-1}) and its B values as one float4
+// from the transposed LDS tile.
 //
 // LDS: three transposed layer tiles [16*CT columns][kp], kp = 16*NCH + 4,
 // used as a ring: X_{l-1}, X_l, X_{l+1} during layer l; X_{l+2} is loaded
-// into registers during layer l and stored over X_{l-1} after it.
+// into registers during layer l and stored over X_{l-1} after it. The
+// hidden layers are stored source-major (ld floats per source, zero
+// padded), so a thread moves four rows of one source with one float4.
 // ---------------------------------------------------------------------------
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -175,51 +178,51 @@ struct AFrag<true> {
   __device__ void zero() { v = shortx4{0, 0, 0, 0}; }
 };
 
-// acc[ct] += A strip x Bt (column tile ct); Bt is a transposed LDS tile
-template <int NCH, int CT, bool BF16>
-__device__ inline void mfma_strip(floatx4 (&acc)[CT], const AFrag<BF16> (&A)[NCH], const float* Bt, int kp,
-                                  int nch, int g, int li) {
+// acc[ct] += A chunk x Bt chunk (column tile ct); Bt is a transposed LDS tile
+template <int CT, bool BF16>
+__device__ inline void mfma_chunk(floatx4 (&acc)[CT], const AFrag<BF16>& A, const float* Bt, int kp, int ch,
+                                  int g, int li) {
+  float4 bv[CT];
 #pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) {
-    if (ch < nch) {
-      float4 bv[CT];
+  for (int ct = 0; ct < CT; ++ct) bv[ct] = *reinterpret_cast<const float4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
+  // consecutive MFMAs go to independent accumulators (column tiles)
+  if constexpr (!BF16) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        bv[ct] = *reinterpret_cast<const float4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
-      // consecutive MFMAs go to independent accumulators (column tiles)
-      if constexpr (!BF16) {
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.x, bv[ct].x, acc[ct], 0, 0, 0);
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ch].v.x, bv[ct].x, acc[ct], 0, 0, 0);
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.y, bv[ct].y, acc[ct], 0, 0, 0);
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ch].v.y, bv[ct].y, acc[ct], 0, 0, 0);
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.z, bv[ct].z, acc[ct], 0, 0, 0);
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ch].v.z, bv[ct].z, acc[ct], 0, 0, 0);
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.w, bv[ct].w, acc[ct], 0, 0, 0);
+  } else {
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ch].v.w, bv[ct].w, acc[ct], 0, 0, 0);
-      } else {
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-          const shortx4 bb = shortx4{f2bf(bv[ct].x), f2bf(bv[ct].y), f2bf(bv[ct].z), f2bf(bv[ct].w)};
-          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[ch].v, bb, acc[ct], 0, 0, 0);
-        }
-      }
+    for (int ct = 0; ct < CT; ++ct) {
+      const shortx4 bb = shortx4{f2bf(bv[ct].x), f2bf(bv[ct].y), f2bf(bv[ct].z), f2bf(bv[ct].w)};
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.v, bb, acc[ct], 0, 0, 0);
     }
   }
 }
 
-// Strip t of layer l: t = 0 is C_{l-1}^T (block 2l-1, transposed), t = 1 is
-// D_l (block 2l), t = 2 is C_l (block 2l+1); t = 0 is absent for l = 0 and
-// t = 2 for l = m-1. Advances (l, t) to the next present strip; returns
-// false past the last one.
-__device__ inline bool next_strip(int m, int& l, int& t) {
-  ++t;
-  if (t == 3 || (t == 2 && l == m - 1)) { ++l; t = 0; }
-  if (l >= m) return false;
-  if (t == 0 && l == 0) t = 1;
-  return true;
+// Position in the chunk stream of a cell: strip (layer l, kind t) and chunk ch.
+struct StripPos {
+  int l, t, ch;
+};
+// First strip of the stream (D_0).
+__device__ inline StripPos stream_begin() { return StripPos{0, 1, 0}; }
+// Advances to the next chunk; false past the end of the stream.
+__device__ inline bool stream_next(StripPos& p, int m, int nch) {
+  if (++p.ch < nch) return true;
+  p.ch = 0;
+  ++p.t;
+  if (p.t == 3 || (p.t == 2 && p.l == m - 1)) { ++p.l; p.t = 0; }
+  return p.l < m;
+}
+__device__ inline bool last_chunk_of_layer(const StripPos& p, int m, int nch) {
+  return p.ch == nch - 1 && (p.t == 2 || (p.t == 1 && p.l == m - 1));
 }
 
-template <int NCH, int CT, bool PF, bool BF16>
+template <int NCH, int CT, int R, bool BF16>
 __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int ntile) {
   using TB = typename std::conditional<BF16, __hip_bfloat16, float>::type;
   constexpr int NS = 16 * CT;
@@ -253,19 +256,16 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
   const int64_t bsz = (int64_t)b * ld;
   const float dt2 = (float)a.dt2;
   const int tsz = NS * kp;
+  // hidden layer j >= 1 of this cell, first source of the tile
+  auto hrow = [&](auto* base, int j) { return base + (c.hid_off + (int64_t)(j - 1) * ld) * ns + (int64_t)s0 * ld; };
 
-  AFrag<BF16> Acur[NCH], Anxt[PF ? NCH : 1];
-  auto load_strip = [&](auto& A, int sl, int st) {
-    const int j = 2 * sl + st - 1;
-    const TB* base = blk + (int64_t)j * bsz;
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      const int kk = ch * 16 + g * 4;
-      if (!active || ch >= nch || arow >= b) A[ch].zero();
-      else if (st == 0) A[ch].load_t(base, ld, kk, arow, b);
-      else if (kk < ld) A[ch].load(base + (int64_t)arow * ld + kk);
-      else A[ch].zero();
-    }
+  auto load_chunk = [&](AFrag<BF16>& A, const StripPos& p) {
+    const TB* base = blk + (int64_t)(2 * p.l + p.t - 1) * bsz;
+    const int kk = p.ch * 16 + g * 4;
+    if (!active || arow >= b) A.zero();
+    else if (p.t == 0) A.load_t(base, ld, kk, arow, b);
+    else if (kk < ld) A.load(base + (int64_t)arow * ld + kk);
+    else A.zero();
   };
   // layer items of this thread: item i covers column icol_i and rows
   // 4 q_i .. 4 q_i + 3 of a transposed tile; NS * 4 * NCH items over
@@ -275,116 +275,135 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
 #pragma unroll
   for (int i = 0; i < CT; ++i) {
     const int item = tid + i * 64 * NCH;
-    icol[i] = item % NS;
-    iq[i] = item / NS;
-    iok[i] = iq[i] < 4 * nch;
+    iq[i] = item % (4 * NCH);
+    icol[i] = item / (4 * NCH);
+    iok[i] = iq[i] < 4 * nch && 4 * iq[i] < ld && icol[i] < nsl;
   }
   // X_j values of the thread's items (zero outside the cell or the tile)
   auto load_layer = [&](float4 (&v)[CT], int j) {
 #pragma unroll
     for (int i = 0; i < CT; ++i) {
-      float x[4];
+      v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (iok[i]) {
+        if (j == 0) {
+          float x[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int kk = 4 * iq[i] + e;
-        float t = 0.f;
-        if (iok[i] && kk < b && icol[i] < nsl) {
-          if (j == 0) t = ycur[(int64_t)gat[kk] * ns + s0 + icol[i]];
-          else t = hcur[(c.hid_off + (int64_t)(j - 1) * b + kk) * ns + s0 + icol[i]];
+          for (int e = 0; e < 4; ++e) {
+            const int kk = 4 * iq[i] + e;
+            x[e] = (kk < b) ? ycur[(int64_t)gat[kk] * ns + s0 + icol[i]] : 0.f;
+          }
+          v[i] = make_float4(x[0], x[1], x[2], x[3]);
+        } else {
+          v[i] = *reinterpret_cast<const float4*>(hrow(hcur, j) + (int64_t)icol[i] * ld + 4 * iq[i]);
         }
-        x[e] = t;
       }
-      v[i] = make_float4(x[0], x[1], x[2], x[3]);
     }
   };
   auto store_layer = [&](const float4 (&v)[CT], int j) {
     float* T = lds + (j % 3) * tsz;
 #pragma unroll
     for (int i = 0; i < CT; ++i)
-      if (iok[i]) *reinterpret_cast<float4*>(T + icol[i] * kp + 4 * iq[i]) = v[i];
+      if (iq[i] < 4 * NCH) *reinterpret_cast<float4*>(T + icol[i] * kp + 4 * iq[i]) = v[i];
+  };
+  // previous-level values of the layer's outputs owned by this lane
+  auto load_old = [&](float4 (&o)[CT], int j) {
+    const int row0 = w * 16 + 4 * g;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int col = ct * 16 + li;
+      o[ct] = (active && row0 < b && col < nsl)
+                  ? *reinterpret_cast<const float4*>(hrow(hold, j) + (int64_t)col * ld + row0)
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   };
 
+  float4 xn[CT];
   {
-    float4 v[CT];
-    load_layer(v, 0);
-    store_layer(v, 0);
-    if (m > 1) {
-      load_layer(v, 1);
-      store_layer(v, 1);
+    load_layer(xn, 0);
+    store_layer(xn, 0);
+    load_layer(xn, 1 < m ? 1 : 0);
+    if (m > 1) store_layer(xn, 1);
+    if (m > 2) load_layer(xn, 2);
+  }
+  // the ring: chunk stream positions q .. q+R-1
+  AFrag<BF16> ring[R];
+  StripPos pf = stream_begin();   // next chunk to fetch
+  bool pf_ok = true;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    if (pf_ok) {
+      load_chunk(ring[u], pf);
+      pf_ok = stream_next(pf, m, nch);
+    } else {
+      ring[u].zero();
     }
   }
-  load_strip(Acur, 0, 1);                      // D_0
   __syncthreads();
-  int pl = 0, pt = 1;                          // strip held in Acur
-  for (int ly = 0; ly < m; ++ly) {
-    float4 xn[CT];
-    if (ly + 2 < m) load_layer(xn, ly + 2);    // in flight during this layer's products
-    float ho[CT][4];
-    if (ly >= 1 && active) {
+  StripPos p = stream_begin();    // chunk consumed next
+  float4 ho[CT];
+  floatx4 acc[CT];
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
+  for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+  bool more = true;
+  while (more) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = w * 16 + 4 * g + r, col = ct * 16 + li;
-          ho[ct][r] = (row < b && col < nsl)
-                          ? hold[(c.hid_off + (int64_t)(ly - 1) * b + row) * ns + s0 + col] : 0.f;
-        }
-    }
-    floatx4 acc[CT];
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // the strips of this layer, in order
-    while (pl == ly) {
-      int nl = pl, nt = pt;
-      const bool more = next_strip(m, nl, nt);
-      if (PF && more) load_strip(Anxt, nl, nt);
-      if (active) mfma_strip<NCH, CT, BF16>(acc, Acur, lds + ((ly + pt + 2) % 3) * tsz, kp, nch, g, li);
+    for (int u = 0; u < R; ++u) {
       if (more) {
-        if constexpr (PF) {
-#pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) Acur[ch] = Anxt[ch];
-        } else {
-          load_strip(Acur, nl, nt);
+        const AFrag<BF16> cur = ring[u];
+        if (pf_ok) {
+          load_chunk(ring[u], pf);
+          pf_ok = stream_next(pf, m, nch);
         }
-      }
-      pl = more ? nl : m;
-      pt = nt;
-    }
-    if (active) {
-      const float* Tl = lds + (ly % 3) * tsz;
+        const int ly = p.l;
+        if (active) mfma_chunk<CT, BF16>(acc, cur, lds + ((ly + p.t + 2) % 3) * tsz, kp, p.ch, g, li);
+        if (p.ch == 0 && p.t == (ly == 0 ? 1 : 0) && ly >= 1) load_old(ho, ly);
+        if (last_chunk_of_layer(p, m, nch)) {
+          if (active) {
+            const float* Tl = lds + (ly % 3) * tsz;
+            const int row0 = w * 16 + 4 * g;
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int col = ct * 16 + li;
+            for (int ct = 0; ct < CT; ++ct) {
+              const int col = ct * 16 + li;
+              if (row0 < b && col < nsl) {
+                if (ly == 0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = w * 16 + 4 * g + r;
-          if (row < b && col < nsl) {
-            if (ly == 0) {
-              phi[(c.u1_off + row) * ns + s0 + col] = acc[ct][r];
-            } else {
-              const int64_t hi = (c.hid_off + (int64_t)(ly - 1) * b + row) * ns + s0 + col;
-              hold[hi] = 2.f * Tl[col * kp + row] - ho[ct][r] + dt2 * acc[ct][r];
+                  for (int r = 0; r < 4; ++r)
+                    if (row0 + r < b) phi[(c.u1_off + row0 + r) * ns + s0 + col] = acc[ct][r];
+                } else {
+                  const float4 xc = *reinterpret_cast<const float4*>(Tl + col * kp + row0);
+                  float4 o;
+                  o.x = 2.f * xc.x - ho[ct].x + dt2 * acc[ct][0];
+                  o.y = 2.f * xc.y - ho[ct].y + dt2 * acc[ct][1];
+                  o.z = 2.f * xc.z - ho[ct].z + dt2 * acc[ct][2];
+                  o.w = 2.f * xc.w - ho[ct].w + dt2 * acc[ct][3];
+                  *reinterpret_cast<float4*>(hrow(hold, ly) + (int64_t)col * ld + row0) = o;
+                }
+              }
             }
           }
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+          if (ly + 2 < m) {
+            __syncthreads();                     // every wave is done with X_{ly-1}
+            store_layer(xn, ly + 2);
+            __syncthreads();
+            if (ly + 3 < m) load_layer(xn, ly + 3);
+          }
         }
+        more = stream_next(p, m, nch);
       }
-    }
-    if (ly + 2 < m) {
-      __syncthreads();                         // every wave is done with X_{ly-1}
-      store_layer(xn, ly + 2);
-      __syncthreads();
     }
   }
 }
 
-template <int NCH, int CT, bool PF, bool BF16>
+template <int NCH, int CT, int R, bool BF16>
 static void launch_mfma(const StepArgs& a, hipStream_t st) {
   constexpr int NS = 16 * CT;
   const int kp = 16 * NCH + 4;
   const size_t lds = 3 * (size_t)NS * kp * sizeof(float);
   const int ntile = (a.ns + NS - 1) / NS;
   const int groups = (a.ncell + 7) / 8;
-  hipLaunchKernelGGL((k_cell_mfma<NCH, CT, PF, BF16>), dim3(groups * 8 * ntile), dim3(64 * NCH), lds, st, a, kp,
+  hipLaunchKernelGGL((k_cell_mfma<NCH, CT, R, BF16>), dim3(groups * 8 * ntile), dim3(64 * NCH), lds, st, a, kp,
                      ntile);
 }
 
@@ -394,10 +413,10 @@ static void launch_variant(const StepArgs& a, int variant, hipStream_t st) {
   // chunks: use the 32-source tile there
   if (3 * 64 * (16 * NCH + 4) * 4 > 160 * 1024) variant |= 2;
   switch (variant) {
-    case 0: launch_mfma<NCH, 4, true, BF16>(a, st); break;
-    case 1: launch_mfma<NCH, 4, false, BF16>(a, st); break;
-    case 2: launch_mfma<NCH, 2, true, BF16>(a, st); break;
-    default: launch_mfma<NCH, 2, false, BF16>(a, st); break;
+    case 0: launch_mfma<NCH, 4, 4, BF16>(a, st); break;
+    case 1: launch_mfma<NCH, 4, 2, BF16>(a, st); break;
+    case 2: launch_mfma<NCH, 2, 4, BF16>(a, st); break;
+    default: launch_mfma<NCH, 2, 8, BF16>(a, st); break;
   }
 }
 
@@ -560,8 +579,8 @@ static hipError_t rec_impl(const StepArgs& a, hipStream_t st) {
 int cell_variants(const StepArgs& a) { return (a.prec == SFROM_F64 || a.max_b > 256) ? 1 : 5; }
 
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st) {
-  // variants 0..3: matrix-core kernel (source tile 64/32, with/without strip
-  // prefetch); 4 (and FP64): the scalar kernel
+  // variants 0..3: matrix-core kernel (source tile 64 with 4 or 2 chunks in
+  // flight, 32 with 4 or 8); 4 (and FP64): the scalar kernel
   if (a.prec == SFROM_F64 || a.max_b > 256 || a.cell_variant >= 4) {
     if (a.prec == SFROM_F64) return cell_impl<double, double, double>(a, st);
     if (a.prec == SFROM_F32) return cell_impl<float, float, float>(a, st);

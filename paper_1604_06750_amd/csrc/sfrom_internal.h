@@ -77,7 +77,9 @@ struct OnlineCell {
   int32_t ld;        // row stride of every stored block (b rounded up to 4, zero padded)
   int32_t pad_;
   int64_t blk_off;   // elements into the block array: D_0, C_0, ..., D_{m-1} (b x ld each)
-  int64_t hid_off;   // rows into the hidden state ((m-1) b rows of n_s)
+  int64_t hid_off;   // padded rows into the hidden state: layer l >= 1 of the
+                     // cell is an n_s x ld block (source-major, rows b..ld-1
+                     // zero) starting at element (hid_off + (l-1) ld) n_s
   int64_t u1_off;    // rows into the gather map / phi scratch (b rows)
 };
 
@@ -236,7 +238,8 @@ struct sfrom {
   std::vector<int32_t> cell_m;
   double shift = 0.0;
   double build_ms = 0.0;
-  int64_t n_hidden_dofs = 0;
+  int64_t n_hidden_dofs = 0;   // sum of (m-1) b
+  int64_t n_hidden_rows = 0;   // sum of (m-1) ld (padded state rows)
   int64_t block_elems = 0;
   std::vector<sfrom_impl::OnlineCell> ocells;
   std::vector<sfrom_impl::OnlinePiece> opieces;
