@@ -481,11 +481,15 @@ __device__ inline void piece_body(const StepArgs& a, const OnlinePiece& pc, int 
   }
 }
 
-template <typename T, typename TA, int MAXB>
+template <typename T, typename TA, int MAXB, bool UNI>
 __global__ __launch_bounds__(256) void k_piece_phase(StepArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)a.npiece * a.ns) return;
-  const int p = (int)(gid / a.ns), s = (int)(gid % a.ns);
+  int p = (int)(gid / a.ns);
+  const int s = (int)(gid % a.ns);
+  // n_s a multiple of 64: one piece per wavefront, so its descriptor,
+  // incidence list and inverse mass are read through the scalar cache
+  if constexpr (UNI) p = __builtin_amdgcn_readfirstlane(p);
   const OnlinePiece pc = a.d_pieces[p];
   switch (pc.ncell) {
     case 2: piece_body<T, TA, MAXB, 2>(a, pc, s); break;
@@ -560,10 +564,17 @@ template <typename T, typename TA>
 static hipError_t piece_impl(const StepArgs& a, hipStream_t st) {
   const int64_t np = (int64_t)a.npiece * a.ns;
   const dim3 g((np + 255) / 256), b(256);
-  if (a.max_bp <= 4) hipLaunchKernelGGL((k_piece_phase<T, TA, 4>), g, b, 0, st, a);
-  else if (a.max_bp <= 9) hipLaunchKernelGGL((k_piece_phase<T, TA, 9>), g, b, 0, st, a);
-  else if (a.max_bp <= 16) hipLaunchKernelGGL((k_piece_phase<T, TA, 16>), g, b, 0, st, a);
-  else hipLaunchKernelGGL((k_piece_phase<T, TA, 32>), g, b, 0, st, a);
+  if (a.ns % 64 == 0) {
+    if (a.max_bp <= 4) hipLaunchKernelGGL((k_piece_phase<T, TA, 4, true>), g, b, 0, st, a);
+    else if (a.max_bp <= 9) hipLaunchKernelGGL((k_piece_phase<T, TA, 9, true>), g, b, 0, st, a);
+    else if (a.max_bp <= 16) hipLaunchKernelGGL((k_piece_phase<T, TA, 16, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_piece_phase<T, TA, 32, true>), g, b, 0, st, a);
+  } else {
+    if (a.max_bp <= 4) hipLaunchKernelGGL((k_piece_phase<T, TA, 4, false>), g, b, 0, st, a);
+    else if (a.max_bp <= 9) hipLaunchKernelGGL((k_piece_phase<T, TA, 9, false>), g, b, 0, st, a);
+    else if (a.max_bp <= 16) hipLaunchKernelGGL((k_piece_phase<T, TA, 16, false>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_piece_phase<T, TA, 32, false>), g, b, 0, st, a);
+  }
   return hipGetLastError();
 }
 
