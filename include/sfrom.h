@@ -271,6 +271,74 @@ int sfrom_export_cell(sfrom_t* h, int32_t cell, int32_t* n_i, int32_t* nnz_i,
 int sfrom_export_piece(sfrom_t* h, int32_t piece, int32_t* k_p, int32_t* b_p,
                        int64_t* global_node, double* S_p);
 
+/* ------------------------------------------------------------------------
+ * Learned off-line stage (no counterpart in the paper, which builds every
+ * cell by block Lanczos, Sec. 5 and App. C). A small 3D CNN maps a cell's
+ * medium to the Cholesky factors of its S-fraction blocks Ghat^k, G^k for
+ * k = 2..m; layer 1 is computed in closed form from B, W and A (Ghat^1 =
+ * W^T B^{-1} W, G^1 = -(Ghat^1)^{-1} X^T A X (Ghat^1)^{-1}, X = B^{-1} W),
+ * so every predicted pivot is SPD and the ROM stays Stieltjes (Prop.
+ * prop1stil). A predicted cell is kept only if its ROM transfer function
+ * matches the exact cell transfer function W^T (A + zB)^{-1} W to a
+ * tolerance at 16 points z = -sigma_j^2, sigma_j = (j + 1/2) omega_max / 16;
+ * other cells are built by block Lanczos.
+ *
+ * Network: input x[n][2][8][8][8] (log sigma, log rho of the cell's voxels,
+ * [channel][z][y][x], float, device memory); conv3d(2 -> conv_ch, 3^3, zero
+ * padding) + ReLU; 2^3 average pooling; dense(64 conv_ch -> hidden) + ReLU;
+ * dense(hidden -> n_out). Parameters are one float vector [W1 (conv_ch, 2,
+ * 3, 3, 3), b1, W2 (hidden, 64 conv_ch), b2, W3 (n_out, hidden), b3],
+ * row-major. Outputs are normalised: factor = y * sd + mu per output.
+ * Factor vectors are, for k = 2..m, the rows of the lower triangle of
+ * chol(Ghat^k) and then of chol(G^k + eps I), eps = 1e-10 tr(G^k) / b:
+ * n_out = (m - 1) b (b + 1).
+ * ---------------------------------------------------------------------- */
+typedef struct sfrom_surrogate sfrom_surrogate_t;
+
+/* Network on `device`, launching on `hip_stream` (NULL = null stream).
+ * Errors: EINVAL, EDEVICE, ENOMEM. */
+int sfrom_surrogate_create(sfrom_surrogate_t** out, int32_t device, void* hip_stream, int32_t conv_ch,
+                           int32_t hidden, int32_t n_out);
+void sfrom_surrogate_destroy(sfrom_surrogate_t* s);
+const char* sfrom_surrogate_last_error(const sfrom_surrogate_t* s);
+int sfrom_surrogate_param_count(const sfrom_surrogate_t* s, int64_t* n);
+/* Host parameter vector in; resets the Adam moments. Errors: ENONFINITE. */
+int sfrom_surrogate_set_params(sfrom_surrogate_t* s, const float* theta);
+int sfrom_surrogate_get_params(sfrom_surrogate_t* s, float* theta);
+/* Output normalisation (host, n_out floats each, sd > 0). */
+int sfrom_surrogate_set_scale(sfrom_surrogate_t* s, const float* mu, const float* sd);
+/* Mean squared error of the batch (x: n inputs, t: n x n_out normalised
+ * targets, device) and its gradient (host, param_count floats; either
+ * output may be NULL). */
+int sfrom_surrogate_gradients(sfrom_surrogate_t* s, const float* x, const float* t, int32_t n, float* loss,
+                              float* grad);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) on the batch; *loss (host, may
+ * be NULL) is the loss before the step. */
+int sfrom_surrogate_train_step(sfrom_surrogate_t* s, const float* x, const float* t, int32_t n, float lr,
+                               float* loss);
+/* Normalised outputs y (device, n x n_out) for inputs x (device); bf16 != 0
+ * rounds weights and activations to bfloat16 at every layer input (float
+ * accumulation). */
+int sfrom_surrogate_forward(sfrom_surrogate_t* s, const float* x, int32_t n, int32_t bf16, float* y);
+
+/* Factor vectors (device, n x n_out floats) of the listed cells of a built
+ * ROM (the training targets). All listed cells must have the same b and m
+ * with n_out = (m - 1) b (b + 1). Errors: ESTATE, EINVAL, ENOTSPD. */
+int sfrom_surrogate_targets(sfrom_t* h, int32_t n, const int32_t* cells, float* t);
+
+/* sfrom_build with the learned stage for the n candidate cells `cells`
+ * (host ids; inputs x on the device, one per candidate, all candidates with
+ * the same b and m and n_out = (m - 1) b (b + 1)): prediction with bfloat16
+ * operands, closed-form layer 1, the transfer-function test with
+ * `omega_max` and `tol`, and block Lanczos for every rejected or
+ * non-candidate cell. accepted[i] (host, n) is 1 when candidate i kept its
+ * predicted blocks; mismatch[i] (host, n, may be NULL) is its largest
+ * relative transfer-function mismatch. Errors: as sfrom_build, plus
+ * EINVAL for a candidate list that does not match the network. */
+int sfrom_build_learned(sfrom_t* h, const sfrom_build_opts* opts, sfrom_surrogate_t* s, int32_t n,
+                        const int32_t* cells, const float* x, double omega_max, double tol,
+                        int32_t* accepted, double* mismatch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -332,8 +332,16 @@ void make_columns(sfrom_t* h, Columns& out, int32_t count, const int64_t* colptr
 // off-line build
 // ---------------------------------------------------------------------------
 
-void build(sfrom_t* h, const sfrom_build_opts* o) {
-  auto t0 = std::chrono::steady_clock::now();
+// Host-side state of one build: per-cell workspace layout and limits.
+struct BuildCtx {
+  std::vector<BuildCell> bcells;   // workspace offsets relative to the cell's own slice
+  std::vector<int64_t> wsize;      // doubles of workspace per cell
+  std::vector<int64_t> soff;       // offset of each piece basis in d_S
+  double* d_S = nullptr;
+  int max_m = 0, max_b = 0, max_n = 0;
+};
+
+void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
   REQUIRE(o != nullptr, SFROM_EINVAL, "null build options");
   REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle: no device for the build");
   finalize_partition(h);
@@ -423,10 +431,13 @@ void build(sfrom_t* h, const sfrom_build_opts* o) {
     soff[p] = (int64_t)S.size();
     S.insert(S.end(), h->pieces[p].S.begin(), h->pieces[p].S.end());
   }
-  double* d_S = dupload(h, S);
+  ctx.d_S = dupload(h, S);
+  ctx.soff = soff;
   // ---- per-cell workspace sizes -----------------------------------------------
-  std::vector<BuildCell> bcells(nc);
-  std::vector<int64_t> wsize(nc);
+  std::vector<BuildCell>& bcells = ctx.bcells;
+  std::vector<int64_t>& wsize = ctx.wsize;
+  bcells.assign(nc, BuildCell{});
+  wsize.assign(nc, 0);
   for (int i = 0; i < nc; ++i) {
     const CellDef& c = h->cells[i];
     BuildCell& bc = bcells[i];
@@ -449,94 +460,271 @@ void build(sfrom_t* h, const sfrom_build_opts* o) {
     bc.status = 0;
     wsize[i] = off;
   }
-  // batch so that the workspace stays within a budget
-  const int64_t budget = (int64_t)8 << 30;   // bytes
-  int per_batch = o->cells_per_batch > 0 ? o->cells_per_batch : nc;
-  int64_t wmax = *std::max_element(wsize.begin(), wsize.end());
+  ctx.max_m = max_m; ctx.max_b = max_b; ctx.max_n = max_n;
+}
+
+// Runs `body` on batches of the listed cells: uploads each batch's cell
+// operators, skeleton maps and workspace descriptors, so that body(bb, ids)
+// can launch per-cell kernels (blockIdx.x = position in `ids`).
+template <class F>
+void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std::vector<int32_t>& list, F&& body) {
+  if (list.empty()) return;
+  const int64_t budget = (int64_t)8 << 30;   // bytes of workspace
+  int64_t wmax = 0;
+  for (int32_t i : list) wmax = std::max(wmax, ctx.wsize[i]);
+  int per_batch = o->cells_per_batch > 0 ? o->cells_per_batch : (int)list.size();
   per_batch = (int)std::max<int64_t>(1, std::min<int64_t>(per_batch, budget / (wmax * 8)));
-  const int64_t wbytes_cap = wmax * per_batch;
-  double* d_work = dalloc<double>(h, (size_t)wbytes_cap);
+  double* d_work = dalloc<double>(h, (size_t)(wmax * per_batch));
   BuildCell* d_bc = dalloc<BuildCell>(h, per_batch);
-  OnlineCell* d_oc_batch = nullptr;
-  for (int c0 = 0; c0 < nc; c0 += per_batch) {
-    const int cnt = std::min(per_batch, nc - c0);
-    std::vector<int32_t> rowptr, col, wrow, wcol, wbp, wkp;
-    std::vector<double> av, bd;
-    std::vector<int64_t> wsoff;
-    std::vector<BuildCell> bcb(bcells.begin() + c0, bcells.begin() + c0 + cnt);
-    int64_t woff = 0;
-    for (int t = 0; t < cnt; ++t) {
-      const int i = c0 + t;
-      const CellDef& c = h->cells[i];
-      BuildCell& bc = bcb[t];
-      bc.rp_off = (int64_t)rowptr.size();
-      bc.csr_off = (int64_t)col.size();
-      bc.b_off = (int64_t)bd.size();
-      rowptr.insert(rowptr.end(), c.rowptr.begin(), c.rowptr.end());
-      col.insert(col.end(), c.col.begin(), c.col.end());
-      av.insert(av.end(), c.a.begin(), c.a.end());
-      bd.insert(bd.end(), c.b.begin(), c.b.end());
-      bc.w_off = (int64_t)wrow.size();
-      std::map<int32_t, int32_t> pcol;
-      for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) pcol[h->cell_pieces[i][q]] = h->cell_piece_col[i][q];
-      int nw = 0;
-      for (int r = 0; r < c.n; ++r) {
-        const int32_t p = h->piece_of_node[c.gnode[r]];
-        if (p < 0) continue;
-        wrow.push_back(r);
-        wcol.push_back(pcol[p]);
-        wsoff.push_back(soff[p] + h->pos_in_piece[c.gnode[r]]);
-        wbp.push_back(h->pieces[p].b);
-        wkp.push_back((int32_t)h->pieces[p].gnode.size());
-        ++nw;
+  try {
+    for (size_t c0 = 0; c0 < list.size(); c0 += per_batch) {
+      const int cnt = (int)std::min<size_t>(per_batch, list.size() - c0);
+      std::vector<int32_t> ids(list.begin() + c0, list.begin() + c0 + cnt);
+      std::vector<int32_t> rowptr, col, wrow, wcol, wbp, wkp;
+      std::vector<double> av, bd;
+      std::vector<int64_t> wsoff;
+      std::vector<BuildCell> bcb(cnt);
+      int64_t woff = 0;
+      for (int t = 0; t < cnt; ++t) {
+        const int i = ids[t];
+        const CellDef& c = h->cells[i];
+        BuildCell& bc = bcb[t];
+        bc = ctx.bcells[i];
+        bc.rp_off = (int64_t)rowptr.size();
+        bc.csr_off = (int64_t)col.size();
+        bc.b_off = (int64_t)bd.size();
+        rowptr.insert(rowptr.end(), c.rowptr.begin(), c.rowptr.end());
+        col.insert(col.end(), c.col.begin(), c.col.end());
+        av.insert(av.end(), c.a.begin(), c.a.end());
+        bd.insert(bd.end(), c.b.begin(), c.b.end());
+        bc.w_off = (int64_t)wrow.size();
+        std::map<int32_t, int32_t> pcol;
+        for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) pcol[h->cell_pieces[i][q]] = h->cell_piece_col[i][q];
+        int nw = 0;
+        for (int r = 0; r < c.n; ++r) {
+          const int32_t p = h->piece_of_node[c.gnode[r]];
+          if (p < 0) continue;
+          wrow.push_back(r);
+          wcol.push_back(pcol[p]);
+          wsoff.push_back(ctx.soff[p] + h->pos_in_piece[c.gnode[r]]);
+          wbp.push_back(h->pieces[p].b);
+          wkp.push_back((int32_t)h->pieces[p].gnode.size());
+          ++nw;
+        }
+        bc.nw = nw;
+        // rebase workspace offsets into this batch's work array
+        const int64_t base = woff;
+        bc.band_off += base; bc.v_off += base; bc.x_off += base; bc.av_off += base;
+        bc.am_off += base; bc.q_off += base; bc.s_off += base; bc.r_off += base; bc.out_off += base;
+        woff += ctx.wsize[i];
       }
-      bc.nw = nw;
-      // rebase workspace offsets into this batch's work array
-      const int64_t base = woff;
-      bc.band_off += base; bc.v_off += base; bc.x_off += base; bc.av_off += base;
-      bc.am_off += base; bc.q_off += base; bc.s_off += base; bc.r_off += base; bc.out_off += base;
-      woff += wsize[i];
+      int32_t* d_rp = dupload(h, rowptr);
+      int32_t* d_col = dupload(h, col);
+      double* d_a = dupload(h, av);
+      double* d_bd = dupload(h, bd);
+      int32_t* d_wrow = dupload(h, wrow);
+      int32_t* d_wcol = dupload(h, wcol);
+      int64_t* d_wsoff = dupload(h, wsoff);
+      int32_t* d_wbp = dupload(h, wbp);
+      int32_t* d_wkp = dupload(h, wkp);
+      HIPCHK(hipMemcpy(d_bc, bcb.data(), cnt * sizeof(BuildCell), hipMemcpyHostToDevice));
+      BuildBatch bb;
+      bb.ncell = cnt;
+      bb.max_m = ctx.max_m; bb.max_b = ctx.max_b; bb.max_n = ctx.max_n;
+      bb.shift = o->shift;
+      bb.d_cells = d_bc;
+      bb.d_rowptr = d_rp; bb.d_col = d_col; bb.d_a = d_a; bb.d_bdiag = d_bd;
+      bb.d_wrow = d_wrow; bb.d_wcol = d_wcol; bb.d_wsoff = d_wsoff; bb.d_wbp = d_wbp; bb.d_wkp = d_wkp;
+      bb.d_S = ctx.d_S;
+      bb.d_work = d_work;
+      try {
+        body(bb, ids);
+      } catch (...) {
+        dfree(d_rp); dfree(d_col); dfree(d_a); dfree(d_bd);
+        dfree(d_wrow); dfree(d_wcol); dfree(d_wsoff); dfree(d_wbp); dfree(d_wkp);
+        throw;
+      }
+      dfree(d_rp); dfree(d_col); dfree(d_a); dfree(d_bd);
+      dfree(d_wrow); dfree(d_wcol); dfree(d_wsoff); dfree(d_wbp); dfree(d_wkp);
     }
-    int32_t* d_rp = dupload(h, rowptr);
-    int32_t* d_col = dupload(h, col);
-    double* d_a = dupload(h, av);
-    double* d_bd = dupload(h, bd);
-    int32_t* d_wrow = dupload(h, wrow);
-    int32_t* d_wcol = dupload(h, wcol);
-    int64_t* d_wsoff = dupload(h, wsoff);
-    int32_t* d_wbp = dupload(h, wbp);
-    int32_t* d_wkp = dupload(h, wkp);
-    HIPCHK(hipMemcpy(d_bc, bcb.data(), cnt * sizeof(BuildCell), hipMemcpyHostToDevice));
-    BuildBatch bb;
-    bb.ncell = cnt;
-    bb.max_m = max_m; bb.max_b = max_b; bb.max_n = max_n;
-    bb.shift = o->shift;
-    bb.d_cells = d_bc;
-    bb.d_rowptr = d_rp; bb.d_col = d_col; bb.d_a = d_a; bb.d_bdiag = d_bd;
-    bb.d_wrow = d_wrow; bb.d_wcol = d_wcol; bb.d_wsoff = d_wsoff; bb.d_wbp = d_wbp; bb.d_wkp = d_wkp;
-    bb.d_S = d_S;
-    bb.d_work = d_work;
-    HIPCHK(launch_build(bb, h->stream));
-    HIPCHK(launch_pack(cnt, d_bc, d_work, h->d_ocells + c0, h->prec, h->d_blocks, h->d_rom64,
-                       h->d_rom64_off + c0, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    HIPCHK(hipMemcpy(bcb.data(), d_bc, cnt * sizeof(BuildCell), hipMemcpyDeviceToHost));
-    dfree(d_rp); dfree(d_col); dfree(d_a); dfree(d_bd);
-    dfree(d_wrow); dfree(d_wcol); dfree(d_wsoff); dfree(d_wbp); dfree(d_wkp);
-    for (int t = 0; t < cnt; ++t) {
-      const int st = bcb[t].status;
-      if (st == 0) continue;
-      dfree(d_work); dfree(d_bc); dfree(d_S);
-      const std::string cell = "cell " + std::to_string(c0 + t) + ": ";
-      free_rom(h);
-      if (st == 1) { h->err = cell + "-(A_i + s B_i) is not positive definite (A_i not <= 0)"; throw Fail{SFROM_ENOTNSD}; }
-      if (st == 2) { h->err = cell + "Krylov/Lanczos block lost rank (Assumption 1)"; throw Fail{SFROM_EBREAKDOWN}; }
-      if (st == 3) { h->err = cell + "S-fraction pivot not SPD (Assumption 2)"; throw Fail{SFROM_ENOTSPD}; }
-      h->err = cell + "non-finite S-fraction"; throw Fail{SFROM_ENONFINITE};
-    }
+  } catch (...) {
+    dfree(d_work); dfree(d_bc);
+    throw;
   }
-  (void)d_oc_batch;
-  dfree(d_work); dfree(d_bc); dfree(d_S);
+  dfree(d_work); dfree(d_bc);
+}
+
+// Status of the batch's cells after the build kernels; throws the first
+// failure (freeing the partial ROM).
+void check_batch_status(sfrom_t* h, const BuildBatch& bb, const std::vector<int32_t>& ids) {
+  std::vector<BuildCell> bcb(ids.size());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(bcb.data(), bb.d_cells, ids.size() * sizeof(BuildCell), hipMemcpyDeviceToHost));
+  for (size_t t = 0; t < ids.size(); ++t) {
+    const int st = bcb[t].status;
+    if (st == 0) continue;
+    const std::string cell = "cell " + std::to_string(ids[t]) + ": ";
+    free_rom(h);
+    if (st == 1) { h->err = cell + "-(A_i + s B_i) is not positive definite (A_i not <= 0)"; throw Fail{SFROM_ENOTNSD}; }
+    if (st == 2) { h->err = cell + "Krylov/Lanczos block lost rank (Assumption 1)"; throw Fail{SFROM_EBREAKDOWN}; }
+    if (st == 3) { h->err = cell + "S-fraction pivot not SPD (Assumption 2)"; throw Fail{SFROM_ENOTSPD}; }
+    h->err = cell + "non-finite S-fraction"; throw Fail{SFROM_ENONFINITE};
+  }
+}
+
+// Plain block-Lanczos build (Alg. alg1red stage 1) of the listed cells.
+void build_lanczos(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std::vector<int32_t>& list) {
+  for_batches(h, o, ctx, list, [&](BuildBatch& bb, const std::vector<int32_t>& ids) {
+    std::vector<OnlineCell> ocb(ids.size());
+    std::vector<int64_t> r64b(ids.size());
+    for (size_t t = 0; t < ids.size(); ++t) { ocb[t] = h->ocells[ids[t]]; r64b[t] = h->rom64_off[ids[t]]; }
+    OnlineCell* d_ocb = dupload(h, ocb);
+    int64_t* d_r64b = dupload(h, r64b);
+    HIPCHK(launch_build(bb, h->stream));
+    HIPCHK(launch_pack((int32_t)ids.size(), bb.d_cells, bb.d_work, d_ocb, h->prec, h->d_blocks, h->d_rom64, d_r64b,
+                       h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    dfree(d_ocb); dfree(d_r64b);
+    check_batch_status(h, bb, ids);
+  });
+}
+
+// Build with the learned stage for the candidate cells (see sfrom.h).
+void build_learned(sfrom_t* h, const sfrom_build_opts* o, sfrom_surrogate* sur, int n, const int32_t* cells,
+                   const float* x, double omega_max, double tol, int32_t* accepted, double* mismatch) {
+  auto t0 = std::chrono::steady_clock::now();
+  REQUIRE(sur != nullptr && n >= 0 && (n == 0 || (cells && x && accepted)), SFROM_EINVAL, "bad learned-build arguments");
+  REQUIRE(omega_max > 0.0 && std::isfinite(omega_max) && tol > 0.0, SFROM_EINVAL, "omega_max and tol must be positive");
+  BuildCtx ctx;
+  build_layout(h, o, ctx);
+  const int nc = (int)h->cells.size();
+  const int P = surrogate_outputs(sur);
+  std::vector<char> is_cand(nc, 0);
+  std::vector<int32_t> cand(cells, cells + n);
+  int b0 = -1, m0 = -1;
+  for (int32_t id : cand) {
+    REQUIRE(id >= 0 && id < nc && !is_cand[id], SFROM_EINVAL, "bad or repeated candidate cell");
+    is_cand[id] = 1;
+    if (b0 < 0) { b0 = h->cell_b[id]; m0 = h->cell_m[id]; }
+    REQUIRE(h->cell_b[id] == b0 && h->cell_m[id] == m0, SFROM_EINVAL, "candidate cells must share b and m");
+  }
+  if (n > 0) {
+    REQUIRE(m0 >= 2 && (int64_t)(m0 - 1) * b0 * (b0 + 1) == P, SFROM_EINVAL,
+            "network outputs do not match the candidates' (m, b)");
+  }
+  std::vector<double> z(16);
+  for (int j = 0; j < 16; ++j) {
+    const double sg = (j + 0.5) * omega_max / 16.0;
+    z[j] = -sg * sg;
+  }
+  std::vector<double> mis(n, 0.0);
+  std::vector<int32_t> acc(n, 0);
+  float* d_y = nullptr;
+  try {
+    if (n > 0) {
+      d_y = dalloc<float>(h, (size_t)n * P);
+      HIPCHK(hipStreamSynchronize(h->stream));
+      HIPCHK(surrogate_predict(sur, x, n, d_y));
+      HIPCHK(hipDeviceSynchronize());
+    }
+    size_t done = 0;
+    for_batches(h, o, ctx, cand, [&](BuildBatch& bb, const std::vector<int32_t>& ids) {
+      const size_t pos0 = done;
+      done += ids.size();
+      double* d_mis = dalloc<double>(h, ids.size());
+      HIPCHK(hipMemsetAsync(d_mis, 0, ids.size() * sizeof(double), h->stream));
+      HIPCHK(launch_learned_check(bb, d_y + pos0 * P, P, z.data(), 16, d_mis, h->stream));
+      std::vector<double> mb(ids.size());
+      std::vector<BuildCell> bcb(ids.size());
+      HIPCHK(hipMemcpyAsync(mb.data(), d_mis, ids.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(bcb.data(), bb.d_cells, ids.size() * sizeof(BuildCell), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      std::vector<int32_t> take(ids.size());
+      std::vector<OnlineCell> ocb(ids.size());
+      std::vector<int64_t> r64b(ids.size());
+      for (size_t t = 0; t < ids.size(); ++t) {
+        const bool ok = bcb[t].status == 0 && mb[t] <= tol;
+        take[t] = ok ? 1 : 0;
+        mis[pos0 + t] = bcb[t].status == 0 ? mb[t] : 1e300;
+        acc[pos0 + t] = take[t];
+        ocb[t] = h->ocells[ids[t]];
+        r64b[t] = h->rom64_off[ids[t]];
+      }
+      int32_t* d_take = dupload(h, take);
+      OnlineCell* d_ocb = dupload(h, ocb);
+      int64_t* d_r64b = dupload(h, r64b);
+      HIPCHK(launch_pack_normal((int32_t)ids.size(), bb.d_cells, bb.d_work, d_ocb, d_take, h->prec, h->d_blocks,
+                                h->d_rom64, d_r64b, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      dfree(d_take); dfree(d_ocb); dfree(d_r64b); dfree(d_mis);
+    });
+    std::vector<int32_t> rest;
+    for (int i = 0; i < nc; ++i)
+      if (!is_cand[i]) rest.push_back(i);
+    for (int t = 0; t < n; ++t)
+      if (!acc[t]) rest.push_back(cand[t]);
+    std::sort(rest.begin(), rest.end());
+    build_lanczos(h, o, ctx, rest);
+  } catch (...) {
+    dfree(d_y);
+    dfree(ctx.d_S);
+    throw;
+  }
+  dfree(d_y);
+  dfree(ctx.d_S);
+  for (int t = 0; t < n; ++t) {
+    accepted[t] = acc[t];
+    if (mismatch) mismatch[t] = mis[t];
+  }
+  h->built = true;
+  h->masses_dirty = true;
+  h->src_dirty = h->rec_dirty = true;
+  auto t1 = std::chrono::steady_clock::now();
+  h->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+// Factor-vector targets of built cells (see sfrom.h).
+void factor_targets(sfrom_t* h, int n, const int32_t* cells, float* t) {
+  REQUIRE(h->built, SFROM_ESTATE, "no ROM: build first");
+  REQUIRE(n > 0 && cells && t, SFROM_EINVAL, "bad target arguments");
+  const int nc = (int)h->ocells.size();
+  int b0 = -1, m0 = -1;
+  for (int k = 0; k < n; ++k) {
+    REQUIRE(cells[k] >= 0 && cells[k] < nc, SFROM_EINVAL, "bad cell id");
+    const OnlineCell& oc = h->ocells[cells[k]];
+    if (b0 < 0) { b0 = oc.b; m0 = oc.m; }
+    REQUIRE(oc.b == b0 && oc.m == m0, SFROM_EINVAL, "cells must share b and m");
+  }
+  REQUIRE(m0 >= 2, SFROM_EINVAL, "targets need m >= 2");
+  const int P = (m0 - 1) * b0 * (b0 + 1);
+  std::vector<int32_t> ids(cells, cells + n);
+  int32_t* d_ids = dupload(h, ids);
+  double* d_scr = dalloc<double>(h, (size_t)n * b0 * b0);
+  std::vector<int32_t> bad(n, 0);
+  int32_t* d_bad = dupload(h, bad);
+  const hipError_t e = launch_factor_targets(h->d_rom64, h->d_rom64_off, d_ids, n, b0, m0, d_scr, t, P, d_bad,
+                                             h->stream);
+  if (e == hipSuccess) hipMemcpyAsync(bad.data(), d_bad, n * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+  hipStreamSynchronize(h->stream);
+  dfree(d_ids); dfree(d_scr); dfree(d_bad);
+  HIPCHK(e);
+  for (int k = 0; k < n; ++k)
+    REQUIRE(!bad[k], SFROM_ENOTSPD, "cell " + std::to_string(cells[k]) + ": a deep block is not positive definite");
+}
+
+void build(sfrom_t* h, const sfrom_build_opts* o) {
+  auto t0 = std::chrono::steady_clock::now();
+  BuildCtx ctx;
+  build_layout(h, o, ctx);
+  std::vector<int32_t> all(h->cells.size());
+  for (size_t i = 0; i < all.size(); ++i) all[i] = (int32_t)i;
+  try {
+    build_lanczos(h, o, ctx, all);
+  } catch (...) {
+    dfree(ctx.d_S);
+    throw;
+  }
+  dfree(ctx.d_S);
   h->built = true;
   h->masses_dirty = true;
   h->src_dirty = h->rec_dirty = true;
@@ -1146,6 +1334,20 @@ int sfrom_add_piece(sfrom_t* h, int32_t piece, int32_t k_p, const int64_t* globa
 int sfrom_build(sfrom_t* h, const sfrom_build_opts* opts) {
   API_BEGIN(h)
   build(h, opts);
+  API_END(h)
+}
+
+int sfrom_build_learned(sfrom_t* h, const sfrom_build_opts* opts, sfrom_surrogate_t* s, int32_t n,
+                        const int32_t* cells, const float* x, double omega_max, double tol,
+                        int32_t* accepted, double* mismatch) {
+  API_BEGIN(h)
+  build_learned(h, opts, s, n, cells, x, omega_max, tol, accepted, mismatch);
+  API_END(h)
+}
+
+int sfrom_surrogate_targets(sfrom_t* h, int32_t n, const int32_t* cells, float* t) {
+  API_BEGIN(h)
+  factor_targets(h, n, cells, t);
   API_END(h)
 }
 

@@ -724,4 +724,374 @@ hipError_t launch_piece_mass(const MassArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Learned off-line stage: S-fraction from predicted Cholesky factors, the
+// transfer-function fallback test, and factor targets of built cells.
+// Workspace regions of a cell (see the build's layout): out = S-fraction
+// (Ghat^1..m, G^1..m), av = scratch, am = on-line blocks in FP64 (D_0, C_0,
+// ..., D_{m-1}, column-major b x b), r = (Ghat^1)^{-1}, q = R factors or
+// the dense ROM matrix, s = transfer functions, v = A X or Z, x = X.
+// ---------------------------------------------------------------------------
+
+// Lower Cholesky factor stored as the row-major lower triangle of a b x b
+// matrix: element (i, j), j <= i, at i (i + 1) / 2 + j.
+__device__ inline int tri_index(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// S-fraction of a candidate cell: layer 1 in closed form from B, W and A
+// (Ghat^1 = W^T B^{-1} W, G^1 = -(Ghat^1)^{-1} X^T A X (Ghat^1)^{-1},
+// X = B^{-1} W, which k_krylov_start has written), layers 2..m from the
+// predicted factors as L L^T + eps I (eps = 1e-10 tr / b), so every pivot is
+// SPD by construction.
+__global__ __launch_bounds__(NT) void k_learned_sfraction(BuildBatch bb, const float* __restrict__ y, int P) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c)) return;
+  const int n = c.n, b = c.b, m = c.m;
+  const int64_t bb2 = (int64_t)b * b;
+  const double* X = bb.d_work + c.x_off;
+  const double* bd = bb.d_bdiag + c.b_off;
+  double* AX = bb.d_work + c.v_off;
+  double* out = bb.d_work + c.out_off;
+  double* Gh = out;
+  double* G = out + m * bb2;
+  double* T = bb.d_work + c.av_off;
+  double* T2 = T + bb2;
+  double* Gi = T2 + bb2;
+  double* Wk = Gi + bb2;
+  double* fac = Wk + bb2;
+  const int32_t* rp = bb.d_rowptr + c.rp_off;
+  const int32_t* col = bb.d_col + c.csr_off;
+  const double* a = bb.d_a + c.csr_off;
+  // Ghat^1 = X^T B X
+  for (int idx = threadIdx.x; idx < b * b; idx += NT) {
+    const int i = idx % b, j = idx / b;
+    double acc = 0.0;
+    for (int r = 0; r < n; ++r) acc += X[r + (int64_t)i * n] * bd[r] * X[r + (int64_t)j * n];
+    Gh[idx] = acc;
+  }
+  // A X
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) {
+    const int r = (int)(idx % n), j = (int)(idx / n);
+    double acc = 0.0;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) acc += a[k] * X[col[k] + (int64_t)j * n];
+    AX[idx] = acc;
+  }
+  __syncthreads();
+  wg_symmetrize(b, Gh, b);
+  wg_gemm<true, false>(b, b, n, 1.0, X, n, AX, n, 0.0, T, b);          // X^T A X
+  if (!wg_inverse(b, Gh, b, Gi, b, Wk, fac)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
+  wg_gemm<false, false>(b, b, b, 1.0, T, b, Gi, b, 0.0, T2, b);
+  wg_gemm<false, false>(b, b, b, -1.0, Gi, b, T2, b, 0.0, G, b);
+  wg_symmetrize(b, G, b);
+  // deep layers from the factors
+  const float* yc = y + (int64_t)blockIdx.x * P;
+  const int nt = b * (b + 1) / 2;
+  for (int k = 1; k < m; ++k) {
+    for (int which = 0; which < 2; ++which) {
+      const float* f = yc + (int64_t)(2 * (k - 1) + which) * nt;
+      for (int idx = threadIdx.x; idx < b * b; idx += NT) {
+        const int i = idx % b, j = idx / b;
+        T[idx] = (j <= i) ? (double)f[tri_index(i, j)] : 0.0;
+      }
+      __syncthreads();
+      double* M = (which == 0 ? Gh : G) + k * bb2;
+      wg_gemm<false, true>(b, b, b, 1.0, T, b, T, b, 0.0, M, b);
+      __shared__ double s_tr;
+      if (threadIdx.x == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < b; ++i) tr += M[i + (int64_t)i * b];
+        s_tr = tr;
+      }
+      __syncthreads();
+      const double eps = 1e-10 * s_tr / b;
+      for (int i = threadIdx.x; i < b; i += NT) M[i + (int64_t)i * b] += eps;
+      __syncthreads();
+      wg_symmetrize(b, M, b);
+    }
+  }
+}
+
+// On-line blocks in FP64 of a cell whose S-fraction is in `out`, with
+// R_k = chol(Ghat^k) (k >= 2) as the change of variables of the hidden
+// layers: D_0 = -G^1, C_0 = G^1 R_2, D_l = -R_l^T (G^l + G^{l-1}) R_l,
+// C_l = R_l^T G^l R_{l+1}; also (Ghat^1)^{-1} for the transfer function.
+__global__ __launch_bounds__(NT) void k_sfraction_to_normal(BuildBatch bb) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c)) return;
+  const int b = c.b, m = c.m;
+  const int64_t bb2 = (int64_t)b * b;
+  const double* Gh = bb.d_work + c.out_off;
+  const double* G = Gh + m * bb2;
+  double* R = bb.d_work + c.q_off;          // R_1..R_{m-1} (0-based layers)
+  double* blk = bb.d_work + c.am_off;
+  double* T = bb.d_work + c.av_off;
+  double* T2 = T + bb2;
+  double* Wk = T2 + bb2;
+  double* fac = Wk + bb2;
+  double* Gi = bb.d_work + c.r_off;
+  if (!wg_inverse(b, Gh, b, Gi, b, Wk, fac)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
+  for (int k = 1; k < m; ++k) {
+    double* Rk = R + (k - 1) * bb2;
+    wg_copy(b, b, Gh + k * bb2, b, Rk, b);
+    if (!(wg_potrf(b, Rk, b) > 0.0)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
+    for (int idx = threadIdx.x; idx < b * b; idx += NT) {
+      const int i = idx % b, j = idx / b;
+      if (i < j) Rk[idx] = 0.0;
+    }
+    __syncthreads();
+  }
+  for (int l = 0; l < m; ++l) {
+    double* D = blk + 2 * l * bb2;
+    if (l == 0) {
+      for (int idx = threadIdx.x; idx < b * b; idx += NT) D[idx] = -G[idx];
+      __syncthreads();
+    } else {
+      const double* Rl = R + (l - 1) * bb2;
+      for (int idx = threadIdx.x; idx < b * b; idx += NT) T[idx] = G[l * bb2 + idx] + G[(l - 1) * bb2 + idx];
+      __syncthreads();
+      wg_gemm<false, false>(b, b, b, 1.0, T, b, Rl, b, 0.0, T2, b);
+      wg_gemm<true, false>(b, b, b, -1.0, Rl, b, T2, b, 0.0, D, b);
+      wg_symmetrize(b, D, b);
+    }
+    if (l + 1 < m) {
+      double* Cb = blk + (2 * l + 1) * bb2;
+      const double* Rn = R + l * bb2;
+      wg_gemm<false, false>(b, b, b, 1.0, G + l * bb2, b, Rn, b, 0.0, T2, b);
+      if (l == 0) wg_copy(b, b, T2, b, Cb, b);
+      else wg_gemm<true, false>(b, b, b, 1.0, R + (l - 1) * bb2, b, T2, b, 0.0, Cb, b);
+    }
+  }
+}
+
+// Exact cell transfer function F(z) = W^T (A + z B)^{-1} W from the band
+// factor of -(A + z B) that k_band_chol left (shift z < 0); F goes to s.
+__global__ __launch_bounds__(NT) void k_tf_exact(BuildBatch bb) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c)) return;
+  const int n = c.n, b = c.b, w = c.w, ld = w + 1;
+  const double* band = bb.d_work + c.band_off;
+  double* Wd = bb.d_work + c.v_off;
+  double* X = bb.d_work + c.x_off;
+  double* F = bb.d_work + c.s_off;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) Wd[idx] = 0.0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < c.nw; k += NT) {
+    const int64_t e = c.w_off + k;
+    const int row = bb.d_wrow[e], col0 = bb.d_wcol[e], bp = bb.d_wbp[e], kp = bb.d_wkp[e];
+    const double* sp = bb.d_S + bb.d_wsoff[e];
+    for (int l = 0; l < bp; ++l) Wd[row + (int64_t)(col0 + l) * n] = sp[(int64_t)l * kp];
+  }
+  __syncthreads();
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) X[idx] = Wd[idx];
+  __syncthreads();
+  for (int r = 0; r < n; ++r) {
+    const double* cr = band + (int64_t)r * ld;
+    const double ip = 1.0 / cr[0];
+    for (int cc = threadIdx.x; cc < b; cc += NT) X[r + (int64_t)cc * n] *= ip;
+    __syncthreads();
+    const int lim = min(w, n - 1 - r);
+    for (int idx = threadIdx.x; idx < lim * b; idx += NT) {
+      const int d = idx % lim + 1, cc = idx / lim;
+      X[r + d + (int64_t)cc * n] -= cr[d] * X[r + (int64_t)cc * n];
+    }
+    __syncthreads();
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    const double ip = 1.0 / band[(int64_t)r * ld];
+    for (int cc = threadIdx.x; cc < b; cc += NT) X[r + (int64_t)cc * n] *= ip;
+    __syncthreads();
+    const int lim = min(w, r);
+    for (int idx = threadIdx.x; idx < lim * b; idx += NT) {
+      const int d = idx % lim + 1, cc = idx / lim;
+      X[r - d + (int64_t)cc * n] -= band[(int64_t)(r - d) * ld + d] * X[r + (int64_t)cc * n];
+    }
+    __syncthreads();
+  }
+  // (A + z B)^{-1} = -(band factor)^{-1}
+  wg_gemm<true, false>(b, b, n, -1.0, Wd, n, X, n, 0.0, F, b);
+}
+
+// ROM transfer function U^1(z) = E_1^T (L' + z D')^{-1} E_1 of the on-line
+// blocks (D' = blkdiag((Ghat^1)^{-1}, I, ..., I)) via the Cholesky factor of
+// M = -(L' + z D') (SPD for z < 0): U^1 = -Z^T Z with Z = chol(M)^{-1} E_1.
+// mis[cell] = max(mis, ||U^1 - F||_F / ||F||_F).
+__global__ __launch_bounds__(NT) void k_tf_rom(BuildBatch bb, double z, double* __restrict__ mis) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c)) return;
+  const int b = c.b, m = c.m, mb = m * b;
+  const int64_t bb2 = (int64_t)b * b;
+  const double* blk = bb.d_work + c.am_off;
+  const double* Gi = bb.d_work + c.r_off;
+  double* M = bb.d_work + c.q_off;
+  double* Z = bb.d_work + c.v_off;
+  const double* F = bb.d_work + c.s_off;
+  double* U = bb.d_work + c.s_off + bb2;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)mb * mb; idx += NT) {
+    const int i = (int)(idx % mb), j = (int)(idx / mb);
+    const int li = i / b, lj = j / b, ri = i % b, rj = j % b;
+    double v = 0.0;
+    if (li == lj) {
+      v = -blk[2 * li * bb2 + ri + (int64_t)rj * b];
+      if (li == 0) v -= z * Gi[ri + (int64_t)rj * b];
+      else if (ri == rj) v -= z;
+    } else if (lj == li + 1) {
+      v = -blk[(2 * li + 1) * bb2 + ri + (int64_t)rj * b];           // -C_li
+    } else if (li == lj + 1) {
+      v = -blk[(2 * lj + 1) * bb2 + rj + (int64_t)ri * b];           // -C_lj^T
+    }
+    M[idx] = v;
+  }
+  __syncthreads();
+  if (!(wg_potrf(mb, M, mb) > 0.0)) {
+    if (threadIdx.x == 0) mis[blockIdx.x] = 1e300;
+    return;
+  }
+  for (int64_t idx = threadIdx.x; idx < (int64_t)mb * b; idx += NT) {
+    const int i = (int)(idx % mb), j = (int)(idx / mb);
+    Z[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < mb; ++j) {
+    const double ip = 1.0 / M[j + (int64_t)j * mb];
+    for (int cc = threadIdx.x; cc < b; cc += NT) Z[j + (int64_t)cc * mb] *= ip;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < (mb - 1 - j) * b; idx += NT) {
+      const int i = j + 1 + idx % (mb - 1 - j), cc = idx / (mb - 1 - j);
+      Z[i + (int64_t)cc * mb] -= M[i + (int64_t)j * mb] * Z[j + (int64_t)cc * mb];
+    }
+    __syncthreads();
+  }
+  wg_gemm<true, false>(b, b, mb, -1.0, Z, mb, Z, mb, 0.0, U, b);
+  __shared__ double s_num[NT], s_den[NT];
+  double num = 0.0, den = 0.0;
+  for (int idx = threadIdx.x; idx < b * b; idx += NT) {
+    const double d = U[idx] - F[idx];
+    num += d * d;
+    den += F[idx] * F[idx];
+  }
+  s_num[threadIdx.x] = num;
+  s_den[threadIdx.x] = den;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      s_num[threadIdx.x] += s_num[threadIdx.x + st];
+      s_den[threadIdx.x] += s_den[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = sqrt(s_num[0] / s_den[0]);
+    mis[blockIdx.x] = fmax(mis[blockIdx.x], (r == r) ? r : 1e300);
+  }
+}
+
+// Copies the S-fraction to rom64 and packs the FP64 on-line blocks of the
+// cells with take[cell] != 0 into the on-line layout (row-major b x ld,
+// diagonal blocks symmetrised).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pack_normal(const BuildCell* bc, const double* work, const OnlineCell* oc,
+                                                    const int32_t* take, T* blocks, double* rom64,
+                                                    const int64_t* rom64_off) {
+  const BuildCell& c = bc[blockIdx.x];
+  if (!take[blockIdx.x] || c.status != ST_OK) return;
+  const OnlineCell& o = oc[blockIdx.x];
+  const int b = c.b, m = c.m;
+  const int64_t bb2 = (int64_t)b * b;
+  const double* src = work + c.out_off;
+  double* r64 = rom64 + rom64_off[blockIdx.x];
+  for (int64_t idx = threadIdx.x; idx < 2 * m * bb2; idx += NT) r64[idx] = src[idx];
+  const double* blk = work + c.am_off;
+  T* dst = blocks + o.blk_off;
+  const int ld = o.ld;
+  const int64_t bsz = (int64_t)b * ld;
+  for (int64_t idx = threadIdx.x; idx < (2 * m - 1) * bsz; idx += NT) {
+    const int j = (int)(idx / bsz);
+    const int r = (int)((idx % bsz) / ld), cc = (int)(idx % ld);
+    double v = 0.0;
+    if (cc < b) {
+      const double* B = blk + j * bb2;
+      v = (j & 1) ? B[r + (int64_t)cc * b] : 0.5 * (B[r + (int64_t)cc * b] + B[cc + (int64_t)r * b]);
+    }
+    dst[idx] = cvt<T>(v);
+  }
+}
+
+// Targets of built cells: rows of the lower Cholesky factors of Ghat^k and
+// G^k + eps I (eps = 1e-10 tr(G^k) / b), k = 2..m, one cell per workgroup;
+// scratch holds b^2 doubles per cell.
+__global__ __launch_bounds__(NT) void k_factor_targets(const double* rom64, const int64_t* rom64_off,
+                                                       const int32_t* cells, int b, int m, double* scratch,
+                                                       float* out, int P, int32_t* bad) {
+  const int i = cells[blockIdx.x];
+  const int64_t bb2 = (int64_t)b * b;
+  const double* Gh = rom64 + rom64_off[i];
+  const double* G = Gh + m * bb2;
+  double* T = scratch + (int64_t)blockIdx.x * bb2;
+  float* o = out + (int64_t)blockIdx.x * P;
+  const int nt = b * (b + 1) / 2;
+  for (int k = 1; k < m; ++k) {
+    for (int which = 0; which < 2; ++which) {
+      const double* M = (which == 0 ? Gh : G) + k * bb2;
+      __shared__ double s_tr;
+      if (threadIdx.x == 0) {
+        double tr = 0.0;
+        for (int q = 0; q < b; ++q) tr += M[q + (int64_t)q * b];
+        s_tr = tr;
+      }
+      __syncthreads();
+      const double eps = (which == 1) ? 1e-10 * s_tr / b : 0.0;
+      for (int idx = threadIdx.x; idx < b * b; idx += NT) T[idx] = M[idx] + ((idx % b == idx / b) ? eps : 0.0);
+      __syncthreads();
+      if (!(wg_potrf(b, T, b) > 0.0)) { if (threadIdx.x == 0) bad[blockIdx.x] = 1; return; }
+      float* f = o + (int64_t)(2 * (k - 1) + which) * nt;
+      for (int idx = threadIdx.x; idx < nt; idx += NT) {
+        // row-major lower triangle: idx -> (r, q)
+        int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) / 2.0);
+        while (r * (r + 1) / 2 > idx) --r;
+        while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+        const int q = idx - r * (r + 1) / 2;
+        f[idx] = (float)T[r + (int64_t)q * b];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_learned_check(const BuildBatch& bb, const float* y, int P, const double* z, int nz, double* mis,
+                                hipStream_t st) {
+  const dim3 grid(bb.ncell), block(NT);
+  hipLaunchKernelGGL(k_krylov_start, grid, block, 0, st, bb);
+  hipLaunchKernelGGL(k_learned_sfraction, grid, block, 0, st, bb, y, P);
+  hipLaunchKernelGGL(k_sfraction_to_normal, grid, block, 0, st, bb);
+  for (int j = 0; j < nz; ++j) {
+    BuildBatch bz = bb;
+    bz.shift = z[j];
+    hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bz);
+    hipLaunchKernelGGL(k_tf_exact, grid, block, 0, st, bz);
+    hipLaunchKernelGGL(k_tf_rom, grid, block, 0, st, bz, z[j], mis);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_normal(int32_t ncell, const BuildCell* d_bcells, const double* d_work,
+                              const OnlineCell* d_ocells, const int32_t* d_take, int32_t prec, void* d_blocks,
+                              double* d_rom64, const int64_t* d_rom64_off, hipStream_t st) {
+  const dim3 grid(ncell), block(NT);
+  if (prec == SFROM_F64)
+    hipLaunchKernelGGL(k_pack_normal<double>, grid, block, 0, st, d_bcells, d_work, d_ocells, d_take, (double*)d_blocks, d_rom64, d_rom64_off);
+  else if (prec == SFROM_F32)
+    hipLaunchKernelGGL(k_pack_normal<float>, grid, block, 0, st, d_bcells, d_work, d_ocells, d_take, (float*)d_blocks, d_rom64, d_rom64_off);
+  else
+    hipLaunchKernelGGL(k_pack_normal<__hip_bfloat16>, grid, block, 0, st, d_bcells, d_work, d_ocells, d_take, (__hip_bfloat16*)d_blocks, d_rom64, d_rom64_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_targets(const double* d_rom64, const int64_t* d_rom64_off, const int32_t* d_cells, int n,
+                                 int b, int m, double* d_scratch, float* d_out, int P, int32_t* d_bad,
+                                 hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_factor_targets, dim3(n), dim3(NT), 0, st, d_rom64, d_rom64_off, d_cells, b, m, d_scratch,
+                     d_out, P, d_bad);
+  return hipGetLastError();
+}
+
 }  // namespace sfrom_impl

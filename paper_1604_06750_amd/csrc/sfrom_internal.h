@@ -118,6 +118,22 @@ struct BuildBatch {
 };
 hipError_t launch_build(const BuildBatch& bb, hipStream_t st);
 
+// Learned off-line stage (cells of one batch): S-fraction from the
+// predicted factors y (one row of P floats per cell), its on-line blocks in
+// FP64 and the transfer-function mismatch against the exact cell transfer
+// function at the nz points z[] (max into mis[cell], which the caller
+// zeroes).
+hipError_t launch_learned_check(const BuildBatch& bb, const float* y, int P, const double* z, int nz, double* mis,
+                                hipStream_t st);
+// Packs the cells with take[cell] != 0 from their FP64 on-line blocks.
+hipError_t launch_pack_normal(int32_t ncell, const BuildCell* d_bcells, const double* d_work,
+                              const OnlineCell* d_ocells, const int32_t* d_take, int32_t prec, void* d_blocks,
+                              double* d_rom64, const int64_t* d_rom64_off, hipStream_t st);
+// Cholesky-factor targets (P floats per cell) of built cells.
+hipError_t launch_factor_targets(const double* d_rom64, const int64_t* d_rom64_off, const int32_t* d_cells, int n,
+                                 int b, int m, double* d_scratch, float* d_out, int P, int32_t* d_bad,
+                                 hipStream_t st);
+
 // Pack the double S-fraction of one batch into the on-line layout.
 hipError_t launch_pack(int32_t ncell, BuildCell* d_bcells, double* d_work,
                        const OnlineCell* d_ocells, int32_t prec, void* d_blocks,
@@ -172,6 +188,10 @@ hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st);
 hipError_t launch_piece_phase(const StepArgs& a, hipStream_t st);
 hipError_t launch_receivers(const StepArgs& a, hipStream_t st);
+// Surrogate network (surrogate.hip): number of outputs, and BF16-operand
+// prediction of the unnormalised outputs for n inputs (device pointers).
+int surrogate_outputs(const sfrom_surrogate* s);
+hipError_t surrogate_predict(sfrom_surrogate* s, const float* x, int n, float* out);
 // ORs 1 into *flag if any of n state values (double for F64, else float) is
 // not finite
 hipError_t launch_nonfinite(const void* x, int64_t n, int prec, int32_t* flag, hipStream_t st);

@@ -38,3 +38,35 @@ def setup(h, wl, sources=True, receivers=True):
     if receivers:
         cp, rw, vl = S.sfrom_point_columns(h, node_ids(wl.nvox, wl.receivers), mp)
         S.sfrom_set_receivers(h, cp, rw, vl, project=False)
+
+
+def interior_cells(wl):
+    """Ids (x-fastest over the cut grid) of the 8^3-voxel cells that touch no
+    wall: the cells the learned off-line stage predicts."""
+    lo = [np.concatenate([[0], np.asarray(c)]) for c in wl.cuts]
+    hi = [np.concatenate([np.asarray(c), [n]]) for c, n in zip(wl.cuts, wl.nvox)]
+    ncx, ncy, ncz = (len(a) for a in lo)
+    out = []
+    for k in range(ncz):
+        for j in range(ncy):
+            for i in range(ncx):
+                box = [(lo[0][i], hi[0][i]), (lo[1][j], hi[1][j]), (lo[2][k], hi[2][k])]
+                inner = 0 < i < ncx - 1 and 0 < j < ncy - 1 and 0 < k < ncz - 1
+                if inner and all(b - a == 8 for a, b in box):
+                    out.append(i + ncx * (j + ncy * k))
+    return np.asarray(out, dtype=np.int32)
+
+
+def cell_features(wl, cells):
+    """Network inputs of the given cells: log sigma and log rho of each cell's
+    8^3 voxels, float32 [cell][channel][z][y][x]."""
+    lo = [np.concatenate([[0], np.asarray(c)]) for c in wl.cuts]
+    ncx, ncy = len(lo[0]), len(lo[1])
+    ls, lr = np.log(wl.sigma), np.log(wl.rho)
+    out = np.empty((len(cells), 2, 8, 8, 8), np.float32)
+    for t, c in enumerate(cells):
+        i, j, k = c % ncx, (c // ncx) % ncy, c // (ncx * ncy)
+        x0, y0, z0 = lo[0][i], lo[1][j], lo[2][k]
+        out[t, 0] = ls[x0:x0 + 8, y0:y0 + 8, z0:z0 + 8].transpose(2, 1, 0)
+        out[t, 1] = lr[x0:x0 + 8, y0:y0 + 8, z0:z0 + 8].transpose(2, 1, 0)
+    return out

@@ -81,6 +81,19 @@ _SIGS = {
     "sfrom_export_cell": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                           _P, _P, _P, _P, _P],
     "sfrom_export_piece": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P],
+    "sfrom_surrogate_create": [C.POINTER(_P), C.c_int32, _P, C.c_int32, C.c_int32, C.c_int32],
+    "sfrom_surrogate_destroy": [_P],
+    "sfrom_surrogate_last_error": [_P],
+    "sfrom_surrogate_param_count": [_P, C.POINTER(C.c_int64)],
+    "sfrom_surrogate_set_params": [_P, _P],
+    "sfrom_surrogate_get_params": [_P, _P],
+    "sfrom_surrogate_set_scale": [_P, _P, _P],
+    "sfrom_surrogate_gradients": [_P, _P, _P, C.c_int32, C.POINTER(C.c_float), _P],
+    "sfrom_surrogate_train_step": [_P, _P, _P, C.c_int32, C.c_float, C.POINTER(C.c_float)],
+    "sfrom_surrogate_forward": [_P, _P, C.c_int32, C.c_int32, _P],
+    "sfrom_surrogate_targets": [_P, C.c_int32, _P, _P],
+    "sfrom_build_learned": [_P, C.POINTER(sfrom_build_opts), _P, C.c_int32, _P, _P, C.c_double, C.c_double,
+                            _P, _P],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -88,6 +101,8 @@ for _name, _args in _SIGS.items():
     _f.restype = C.c_int
 _lib.sfrom_destroy.restype = None
 _lib.sfrom_last_error.restype = C.c_char_p
+_lib.sfrom_surrogate_destroy.restype = None
+_lib.sfrom_surrogate_last_error.restype = C.c_char_p
 
 EXPORTED = tuple(_SIGS)
 
@@ -322,3 +337,94 @@ def sfrom_export_piece(h, piece):
     g = np.empty(k.value, np.int64); S = np.empty(k.value * bp.value)
     _check(h, _lib.sfrom_export_piece(h, piece, C.byref(k), C.byref(bp), _ptr(g), _ptr(S)))
     return g, S.reshape(bp.value, k.value).T.copy()
+
+
+# ---------------------------------------------------------------------------
+# learned off-line stage
+# ---------------------------------------------------------------------------
+
+def _scheck(s, rc):
+    if rc != 0:
+        msg = _lib.sfrom_surrogate_last_error(s).decode() if s else ""
+        raise SfromError(rc, msg)
+
+
+def sfrom_surrogate_create(device: int, stream: int, conv_ch: int, hidden: int, n_out: int):
+    s = _P()
+    rc = _lib.sfrom_surrogate_create(C.byref(s), device, _P(stream) if stream else None, conv_ch, hidden, n_out)
+    if rc != 0:
+        raise SfromError(rc, "sfrom_surrogate_create failed")
+    return s
+
+
+def sfrom_surrogate_destroy(s):
+    _lib.sfrom_surrogate_destroy(s)
+
+
+def sfrom_surrogate_last_error(s) -> str:
+    return _lib.sfrom_surrogate_last_error(s).decode()
+
+
+def sfrom_surrogate_param_count(s) -> int:
+    n = C.c_int64()
+    _scheck(s, _lib.sfrom_surrogate_param_count(s, C.byref(n)))
+    return n.value
+
+
+def sfrom_surrogate_set_params(s, theta):
+    theta = _host(theta, np.float32)
+    _scheck(s, _lib.sfrom_surrogate_set_params(s, _ptr(theta)))
+
+
+def sfrom_surrogate_get_params(s):
+    out = np.empty(sfrom_surrogate_param_count(s), np.float32)
+    _scheck(s, _lib.sfrom_surrogate_get_params(s, _ptr(out)))
+    return out
+
+
+def sfrom_surrogate_set_scale(s, mu, sd):
+    mu = _host(mu, np.float32); sd = _host(sd, np.float32)
+    _scheck(s, _lib.sfrom_surrogate_set_scale(s, _ptr(mu), _ptr(sd)))
+
+
+def sfrom_surrogate_gradients(s, x, t):
+    """x, t: float32 CUDA tensors (n x 1024, n x n_out). Returns (loss, grad)."""
+    loss = C.c_float()
+    g = np.empty(sfrom_surrogate_param_count(s), np.float32)
+    _scheck(s, _lib.sfrom_surrogate_gradients(s, _dev(x), _dev(t), x.shape[0], C.byref(loss), _ptr(g)))
+    return float(loss.value), g
+
+
+def sfrom_surrogate_train_step(s, x, t, lr):
+    loss = C.c_float()
+    _scheck(s, _lib.sfrom_surrogate_train_step(s, _dev(x), _dev(t), x.shape[0], lr, C.byref(loss)))
+    return float(loss.value)
+
+
+def sfrom_surrogate_forward(s, x, y, bf16=True):
+    _scheck(s, _lib.sfrom_surrogate_forward(s, _dev(x), x.shape[0], 1 if bf16 else 0, _dev(y)))
+
+
+def sfrom_surrogate_targets(h, cells, t):
+    """cells: host int32 ids; t: float32 CUDA tensor (n x n_out)."""
+    cells = _host(cells, np.int32)
+    _check(h, _lib.sfrom_surrogate_targets(h, len(cells), _ptr(cells), _dev(t)))
+
+
+def sfrom_build_learned(h, m, shift, prec, s, cells, x, omega_max, tol, m_per_cell=None, cells_per_batch=0):
+    """Returns (accepted int32 array, mismatch float64 array) per candidate."""
+    cells = _host(cells, np.int32)
+    o = sfrom_build_opts()
+    o.m = m
+    keep = None
+    if m_per_cell is not None:
+        keep = _host(m_per_cell, np.int32)
+        o.m_per_cell = keep.ctypes.data_as(C.POINTER(C.c_int32))
+    o.shift = shift
+    o.online_prec = prec
+    o.cells_per_batch = cells_per_batch
+    acc = np.zeros(len(cells), np.int32)
+    mis = np.zeros(len(cells), np.float64)
+    _check(h, _lib.sfrom_build_learned(h, C.byref(o), s, len(cells), _ptr(cells), _dev(x) if len(cells) else None,
+                                       omega_max, tol, _ptr(acc), _ptr(mis)))
+    return acc, mis
