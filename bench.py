@@ -209,6 +209,7 @@ def main():
         build_ms.append(S.sfrom_get_info(h)["build_ms"])
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    built_info = S.sfrom_get_info(h)
     cell_ms, cell_n = S.sfrom_profile_read(h, S.KERNEL_CELL)
     piece_ms, piece_n = S.sfrom_profile_read(h, S.KERNEL_PIECE)
     rec_ms, rec_n = S.sfrom_profile_read(h, S.KERNEL_RECEIVERS)
@@ -302,7 +303,7 @@ def main():
                          f"{args.modes_edge} edge + 1 corner modes per piece, {ns} sources, {nr} receivers, "
                          f"{nt} leapfrog steps at 0.5 fine CFL; job = off-line build + on-line run"),
             "n_fine": info["n"], "n_cells": info["n_cells"], "n_pieces": info["n_pieces"],
-            "rom_dofs": info["n_piece_dofs"] + info["n_hidden_dofs"], "max_b": info["max_b"],
+            "rom_dofs": built_info["n_piece_dofs"] + built_info["n_hidden_dofs"], "max_b": info["max_b"],
         },
         "roofline": roofline,
         "rel_l2_vs_rom_fp64": rel_l2_rom64,

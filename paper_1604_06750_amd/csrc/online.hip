@@ -178,13 +178,38 @@ struct AFrag<true> {
   __device__ void zero() { v = shortx4{0, 0, 0, 0}; }
 };
 
-// acc[ct] += A chunk x Bt chunk (column tile ct); Bt is a transposed LDS tile
-template <int CT, bool BF16>
-__device__ inline void mfma_chunk(floatx4 (&acc)[CT], const AFrag<BF16>& A, const float* Bt, int kp, int ch,
-                                  int g, int li) {
-  float4 bv[CT];
+// B fragments of chunk ch: column tile ct reads its 4 consecutive k of the
+// transposed LDS tile Bt
+template <int CT>
+__device__ inline void load_b(float4 (&bv)[CT], const float* Bt, int kp, int ch, int g, int li) {
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) bv[ct] = *reinterpret_cast<const float4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
+}
+
+// acc[ct] += A chunk x B chunk for column tile ct, reading that tile's B
+// fragment from LDS just before its products (fewer live registers; the
+// dependent products of one tile are interleaved with other waves')
+template <int CT, bool BF16>
+__device__ inline void mma_chunk_lean(floatx4 (&acc)[CT], const AFrag<BF16>& A, const float* Bt, int kp, int ch,
+                                      int g, int li) {
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const float4 bv = *reinterpret_cast<const float4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
+    if constexpr (!BF16) {
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.x, bv.x, acc[ct], 0, 0, 0);
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.y, bv.y, acc[ct], 0, 0, 0);
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.z, bv.z, acc[ct], 0, 0, 0);
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.w, bv.w, acc[ct], 0, 0, 0);
+    } else {
+      const shortx4 bb = shortx4{f2bf(bv.x), f2bf(bv.y), f2bf(bv.z), f2bf(bv.w)};
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.v, bb, acc[ct], 0, 0, 0);
+    }
+  }
+}
+
+// acc[ct] += A chunk x B chunk (column tile ct)
+template <int CT, bool BF16>
+__device__ inline void mma_chunk(floatx4 (&acc)[CT], const AFrag<BF16>& A, const float4 (&bv)[CT]) {
   // consecutive MFMAs go to independent accumulators (column tiles)
   if constexpr (!BF16) {
 #pragma unroll
@@ -222,8 +247,8 @@ __device__ inline bool last_chunk_of_layer(const StripPos& p, int m, int nch) {
   return p.ch == nch - 1 && (p.t == 2 || (p.t == 1 && p.l == m - 1));
 }
 
-template <int NCH, int CT, int R, bool BF16>
-__global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int ntile) {
+template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, bool BF16>
+__global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp, int ntile) {
   using TB = typename std::conditional<BF16, __hip_bfloat16, float>::type;
   constexpr int NS = 16 * CT;
   extern __shared__ float lds[];
@@ -300,7 +325,7 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
     }
   };
   auto store_layer = [&](const float4 (&v)[CT], int j) {
-    float* T = lds + (j % 3) * tsz;
+    float* T = lds + (j % TS) * tsz;
 #pragma unroll
     for (int i = 0; i < CT; ++i)
       if (iq[i] < 4 * NCH) *reinterpret_cast<float4*>(T + icol[i] * kp + 4 * iq[i]) = v[i];
@@ -323,7 +348,7 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
     store_layer(xn, 0);
     load_layer(xn, 1 < m ? 1 : 0);
     if (m > 1) store_layer(xn, 1);
-    if (m > 2) load_layer(xn, 2);
+    if (!(LEAN && TS == 2) && m > 2) load_layer(xn, 2);
   }
   // the ring: chunk stream positions q .. q+R-1
   AFrag<BF16> ring[R];
@@ -355,11 +380,30 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
           pf_ok = stream_next(pf, m, nch);
         }
         const int ly = p.l;
-        if (active) mfma_chunk<CT, BF16>(acc, cur, lds + ((ly + p.t + 2) % 3) * tsz, kp, p.ch, g, li);
-        if (p.ch == 0 && p.t == (ly == 0 ? 1 : 0) && ly >= 1) load_old(ho, ly);
+        if (active) {
+          const float* Bt = lds + ((ly + p.t + TS - 1) % TS) * tsz;
+          if constexpr (LEAN) {
+            mma_chunk_lean<CT, BF16>(acc, cur, Bt, kp, p.ch, g, li);
+          } else {
+            float4 bv[CT];
+            load_b<CT>(bv, Bt, kp, p.ch, g, li);
+            mma_chunk<CT, BF16>(acc, cur, bv);
+          }
+        }
+        if (HO && p.ch == 0 && p.t == (ly == 0 ? 1 : 0) && ly >= 1) load_old(ho, ly);
+        if (TS == 2 && p.t == 0 && p.ch == nch - 1 && ly + 1 < m) {
+          // two tiles: X_{ly+1} replaces X_{ly-1} once every wave is done
+          // with C_{ly-1}^T X_{ly-1}
+          if (LEAN) load_layer(xn, ly + 1);
+          __syncthreads();
+          store_layer(xn, ly + 1);
+          __syncthreads();
+          if (!LEAN && ly + 2 < m) load_layer(xn, ly + 2);
+        }
         if (last_chunk_of_layer(p, m, nch)) {
+          if (!HO && ly >= 1) load_old(ho, ly);
           if (active) {
-            const float* Tl = lds + (ly % 3) * tsz;
+            const float* Tl = lds + (ly % TS) * tsz;
             const int row0 = w * 16 + 4 * g;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
@@ -383,7 +427,7 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
           }
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-          if (ly + 2 < m) {
+          if (TS == 3 && ly + 2 < m) {
             __syncthreads();                     // every wave is done with X_{ly-1}
             store_layer(xn, ly + 2);
             __syncthreads();
@@ -396,27 +440,36 @@ __global__ __launch_bounds__(64 * NCH) void k_cell_mfma(StepArgs a, int kp, int 
   }
 }
 
-template <int NCH, int CT, int R, bool BF16>
+template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, bool BF16>
 static void launch_mfma(const StepArgs& a, hipStream_t st) {
   constexpr int NS = 16 * CT;
   const int kp = 16 * NCH + 4;
-  const size_t lds = 3 * (size_t)NS * kp * sizeof(float);
+  const size_t lds = (size_t)TS * NS * kp * sizeof(float);
   const int ntile = (a.ns + NS - 1) / NS;
   const int groups = (a.ncell + 7) / 8;
-  hipLaunchKernelGGL((k_cell_mfma<NCH, CT, R, BF16>), dim3(groups * 8 * ntile), dim3(64 * NCH), lds, st, a, kp,
-                     ntile);
+  hipLaunchKernelGGL((k_cell_mfma<NCH, CT, R, HO, TS, MINW, LEAN, BF16>), dim3(groups * 8 * ntile), dim3(64 * NCH), lds,
+                     st, a, kp, ntile);
+}
+
+// waves per SIMD that `TS` tiles of 64 sources let the LDS hold
+template <int NCH, int TS>
+constexpr int lds_waves() {
+  constexpr int bytes = TS * 64 * (16 * NCH + 4) * 4;
+  constexpr int wgs = (160 * 1024) / bytes;
+  constexpr int w = (wgs * NCH + 3) / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
 template <int NCH, bool BF16>
 static void launch_variant(const StepArgs& a, int variant, hipStream_t st) {
   // three layer tiles of 64 sources exceed the 160 KiB of LDS beyond 12
   // chunks: use the 32-source tile there
-  if (3 * 64 * (16 * NCH + 4) * 4 > 160 * 1024) variant |= 2;
+  if (3 * 64 * (16 * NCH + 4) * 4 > 160 * 1024) variant = 3;
   switch (variant) {
-    case 0: launch_mfma<NCH, 4, 4, BF16>(a, st); break;
-    case 1: launch_mfma<NCH, 4, 2, BF16>(a, st); break;
-    case 2: launch_mfma<NCH, 2, 4, BF16>(a, st); break;
-    default: launch_mfma<NCH, 2, 8, BF16>(a, st); break;
+    case 0: launch_mfma<NCH, 4, 4, false, 3, lds_waves<NCH, 3>(), false, BF16>(a, st); break;
+    case 1: launch_mfma<NCH, 4, 4, false, 2, lds_waves<NCH, 2>(), false, BF16>(a, st); break;
+    case 2: launch_mfma<NCH, 4, 4, false, 2, lds_waves<NCH, 2>(), true, BF16>(a, st); break;
+    default: launch_mfma<NCH, 2, 4, true, 3, 1, false, BF16>(a, st); break;
   }
 }
 
@@ -590,8 +643,11 @@ static hipError_t rec_impl(const StepArgs& a, hipStream_t st) {
 int cell_variants(const StepArgs& a) { return (a.prec == SFROM_F64 || a.max_b > 256) ? 1 : 5; }
 
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st) {
-  // variants 0..3: matrix-core kernel (source tile 64 with 4 or 2 chunks in
-  // flight, 32 with 4 or 8); 4 (and FP64): the scalar kernel
+  // variants 0..3: matrix-core kernel with 4 chunks in flight and the
+  // register budget of the waves the LDS admits (source tile 64 with three
+  // layer tiles; two tiles; two tiles with per-tile B reads and the next
+  // layer read at its store; source tile 32); 4 (and FP64): the scalar
+  // kernel
   if (a.prec == SFROM_F64 || a.max_b > 256 || a.cell_variant >= 4) {
     if (a.prec == SFROM_F64) return cell_impl<double, double, double>(a, st);
     if (a.prec == SFROM_F32) return cell_impl<float, float, float>(a, st);
