@@ -103,6 +103,8 @@ void free_rom(sfrom_t* h) {
   dfree(h->d_inc_cell); dfree(h->d_inc_col);
   dfree(h->d_src); dfree(h->d_rptr); dfree(h->d_rrow); dfree(h->d_rval);
   dfree(h->d_y[0]); dfree(h->d_y[1]); dfree(h->d_h[0]); dfree(h->d_h[1]); dfree(h->d_phi); dfree(h->d_flag);
+  for (auto& bk : h->buckets) dfree(bk.d_list);
+  h->buckets.clear();
   h->built = false;
   h->state_ns = -1;
   h->src_dirty = h->rec_dirty = true;
@@ -461,6 +463,24 @@ void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
     wsize[i] = off;
   }
   ctx.max_m = max_m; ctx.max_b = max_b; ctx.max_n = max_n;
+  // cell-phase buckets: cells grouped by the strip count of the matrix-core
+  // kernel instantiation they need (4, 6, 7, 8, 9, 10, 12, 16 strips)
+  auto inst = [](int b) {
+    const int q = (b + 15) / 16;
+    return q <= 4 ? 4 : q <= 6 ? 6 : q <= 10 ? q : q <= 12 ? 12 : 16;
+  };
+  std::map<int, std::vector<int32_t>> groups;
+  for (int i = 0; i < nc; ++i) groups[inst(h->cell_b[i])].push_back(i);
+  for (auto& kv : groups) {
+    sfrom::CellBucket bk;
+    bk.count = (int32_t)kv.second.size();
+    for (int32_t i : kv.second) {
+      bk.max_b = std::max(bk.max_b, h->cell_b[i]);
+      bk.max_m = std::max(bk.max_m, h->cell_m[i]);
+    }
+    bk.d_list = dupload(h, kv.second);
+    h->buckets.push_back(bk);
+  }
 }
 
 // Runs `body` on batches of the listed cells: uploads each batch's cell
@@ -925,7 +945,40 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   a.phi = h->d_phi; a.w = d_w;
   a.d_rptr = h->d_rptr; a.d_rrow = h->d_rrow; a.d_rval = h->d_rval;
   a.traces = d_tr;
-  a.cell_variant = autotune_cell(h, a);
+  a.d_cell_list = nullptr;
+  a.nlist = a.ncell;
+  // one cell-phase launch per bucket of cells with the same strip count
+  // (matrix-core precisions), each with its own autotuned variant
+  const bool use_buckets = a.prec != SFROM_F64 && a.max_b <= 256 && h->buckets.size() > 1;
+  std::vector<StepArgs> ba;
+  if (use_buckets) {
+    int largest = 0;
+    for (size_t k = 0; k < h->buckets.size(); ++k) {
+      auto& bk = h->buckets[k];
+      StepArgs ab = a;
+      ab.d_cell_list = bk.d_list;
+      ab.nlist = bk.count;
+      ab.max_b = bk.max_b;
+      ab.max_m = bk.max_m;
+      bk.variant = ab.cell_variant = autotune_cell(h, ab);
+      ba.push_back(ab);
+      if (bk.count > h->buckets[largest].count) largest = (int)k;
+    }
+    h->tuned_variant = h->buckets[largest].variant;
+    a.cell_variant = h->tuned_variant;
+  } else {
+    a.cell_variant = autotune_cell(h, a);
+  }
+  auto cell_phase = [&](const StepArgs& x, hipStream_t st) -> hipError_t {
+    if (!use_buckets) return launch_cell_phase(x, st);
+    for (StepArgs ab : ba) {
+      ab.y_cur = x.y_cur; ab.y_old = x.y_old; ab.h_cur = x.h_cur; ab.h_old = x.h_old;
+      ab.step = x.step; ab.trace_step = x.trace_step;
+      const hipError_t e = launch_cell_phase(ab, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   const bool graph = h->use_graph && !h->profiling && n_steps > 0;
   std::vector<int64_t> key;
   if (graph) {
@@ -935,6 +988,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
     key = {n_steps, dbits, (int64_t)(intptr_t)d_w, (int64_t)(intptr_t)d_tr, (int64_t)h->cur,
            (int64_t)(intptr_t)h->d_y[0], (int64_t)(intptr_t)h->d_h[0], (int64_t)(intptr_t)h->d_phi,
            (int64_t)ns, (int64_t)nr, (int64_t)a.cell_variant, (int64_t)(intptr_t)h->d_blocks};
+    for (const StepArgs& ab : ba) key.push_back(ab.cell_variant);
     if (h->graph_exec && key == h->graph_key) {
       HIPCHK(hipGraphLaunch(h->graph_exec, h->stream));
       h->graph_launches++;
@@ -957,7 +1011,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
       a.y_cur = h->d_y[cur]; a.y_old = h->d_y[1 - cur];
       a.h_cur = h->d_h[cur]; a.h_old = h->d_h[1 - cur];
       a.step = s; a.trace_step = s;
-      timed(h, 0, [&] { return launch_cell_phase(a, ls); });
+      timed(h, 0, [&] { return cell_phase(a, ls); });
       timed(h, 1, [&] { return launch_piece_phase(a, ls); });
       timed(h, 2, [&] { return launch_receivers(a, ls); });
       cur = 1 - cur;

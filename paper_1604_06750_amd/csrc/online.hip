@@ -64,7 +64,7 @@ template <typename T, typename TB, typename TA>
 __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
   extern __shared__ unsigned char smem_raw[];
   TA* X = reinterpret_cast<TA*>(smem_raw);
-  const OnlineCell c = a.d_cells[blockIdx.x];
+  const OnlineCell c = a.d_cells[a.d_cell_list ? a.d_cell_list[blockIdx.x] : (int)blockIdx.x];
   const int m = c.m, b = c.b, ld = c.ld, ns = a.ns;
   const int s0 = blockIdx.y * nst;
   const int nsl = min(nst, ns - s0);
@@ -261,7 +261,8 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
     const int grp = bid / (8 * ntile), r = bid % (8 * ntile);
     tile = r / 8;
     cell = grp * 8 + r % 8;
-    if (cell >= a.ncell) return;
+    if (cell >= a.nlist) return;
+    if (a.d_cell_list) cell = a.d_cell_list[cell];
   }
   const OnlineCell c = a.d_cells[cell];
   const int m = c.m, b = c.b, ld = c.ld, ns = a.ns;
@@ -446,7 +447,7 @@ static void launch_mfma(const StepArgs& a, hipStream_t st) {
   const int kp = 16 * NCH + 4;
   const size_t lds = (size_t)TS * NS * kp * sizeof(float);
   const int ntile = (a.ns + NS - 1) / NS;
-  const int groups = (a.ncell + 7) / 8;
+  const int groups = (a.nlist + 7) / 8;
   hipLaunchKernelGGL((k_cell_mfma<NCH, CT, R, HO, TS, MINW, LEAN, BF16>), dim3(groups * 8 * ntile), dim3(64 * NCH), lds,
                      st, a, kp, ntile);
 }
@@ -608,7 +609,7 @@ template <typename T, typename TB, typename TA>
 static hipError_t cell_impl(const StepArgs& a, hipStream_t st) {
   const int nst = cell_tile(a, sizeof(TA));
   const size_t lds = (size_t)a.max_m * a.max_b * nst * sizeof(TA);
-  const dim3 g1(a.ncell, (a.ns + nst - 1) / nst);
+  const dim3 g1(a.nlist, (a.ns + nst - 1) / nst);
   hipLaunchKernelGGL((k_cell_phase<T, TB, TA>), g1, dim3(CELL_NT), lds, st, a, nst);
   return hipGetLastError();
 }

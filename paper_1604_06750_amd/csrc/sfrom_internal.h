@@ -182,6 +182,10 @@ struct StepArgs {
   void* traces;                  // n_steps x n_rec x ns
   int64_t trace_step;            // which slice to write
   int32_t cell_variant;          // kernel variant of the cell phase (autotuned)
+  // cell phase over a subset: cells d_cell_list[0..nlist) (all cells, in
+  // order, when d_cell_list is null and nlist == ncell)
+  const int32_t* d_cell_list;
+  int32_t nlist;
 };
 hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
 // the three parts of a step, for per-kernel timing
@@ -325,6 +329,13 @@ struct sfrom {
   double prof_ms[4] = {0, 0, 0, 0};
   // autotuned cell-phase variant per (precision, max_b, max_m, n_s)
   std::map<std::tuple<int, int, int, int>, int> tuned;
+  // cells grouped by the row-strip count of the matrix-core kernel they
+  // need; one cell-phase launch (and autotuned variant) per group
+  struct CellBucket {
+    int32_t max_b = 0, max_m = 0, count = 0, variant = -1;
+    int32_t* d_list = nullptr;
+  };
+  std::vector<CellBucket> buckets;
   int tuned_variant = -1;
   float tuned_ms = 0.f;
 
