@@ -358,42 +358,65 @@ __global__ __launch_bounds__(NT) void k_normalize(BuildBatch bb, int j) {
 }
 
 // X = (A + sB)^{-1} B q_j = -C^{-1} (B q_j) with the banded factor.
+// Solves (L L^T) x = t for one right-hand side per lane: L is the band
+// Cholesky factor (column-major band, column c holding L[c..c+w][c]) and t
+// is column `col` of the row-major n x b array T, overwritten by x. Each
+// lane touches only its own column, so no barrier is needed; the band
+// entries are wave-uniform (scalar loads) and a row's neighbours are read
+// together.
+__device__ void lane_band_solve(const double* __restrict__ band, int ld, int w, int n, int b, double* T, int col) {
+  // forward: L y = t, y[r] = (t[r] - sum_d L[r][r-d] y[r-d]) / L[r][r]
+  for (int r = 0; r < n; ++r) {
+    double acc = T[(int64_t)r * b + col];
+    const int lim = min(w, r);
+    int d = 1;
+    for (; d + 3 <= lim; d += 4) {
+      const double y0 = T[(int64_t)(r - d) * b + col], y1 = T[(int64_t)(r - d - 1) * b + col];
+      const double y2 = T[(int64_t)(r - d - 2) * b + col], y3 = T[(int64_t)(r - d - 3) * b + col];
+      acc -= band[(int64_t)(r - d) * ld + d] * y0;
+      acc -= band[(int64_t)(r - d - 1) * ld + d + 1] * y1;
+      acc -= band[(int64_t)(r - d - 2) * ld + d + 2] * y2;
+      acc -= band[(int64_t)(r - d - 3) * ld + d + 3] * y3;
+    }
+    for (; d <= lim; ++d) acc -= band[(int64_t)(r - d) * ld + d] * T[(int64_t)(r - d) * b + col];
+    T[(int64_t)r * b + col] = acc / band[(int64_t)r * ld];
+  }
+  // backward: L^T x = y, x[r] = (y[r] - sum_d L[r+d][r] x[r+d]) / L[r][r]
+  for (int r = n - 1; r >= 0; --r) {
+    const double* cr = band + (int64_t)r * ld;
+    double acc = T[(int64_t)r * b + col];
+    const int lim = min(w, n - 1 - r);
+    int d = 1;
+    for (; d + 3 <= lim; d += 4) {
+      const double x0 = T[(int64_t)(r + d) * b + col], x1 = T[(int64_t)(r + d + 1) * b + col];
+      const double x2 = T[(int64_t)(r + d + 2) * b + col], x3 = T[(int64_t)(r + d + 3) * b + col];
+      acc -= cr[d] * x0;
+      acc -= cr[d + 1] * x1;
+      acc -= cr[d + 2] * x2;
+      acc -= cr[d + 3] * x3;
+    }
+    for (; d <= lim; ++d) acc -= cr[d] * T[(int64_t)(r + d) * b + col];
+    T[(int64_t)r * b + col] = acc / cr[0];
+  }
+}
+
+// X = (A + s B)^{-1} B q_j = -C^{-1} B q_j with C = -(A + sB) = L L^T (the
+// band factor); one lane per column of the block, row-major staging in the
+// free A V region.
 __global__ __launch_bounds__(NT) void k_shift_solve(BuildBatch bb, int j) {
   BuildCell& c = bb.d_cells[blockIdx.x];
   if (cell_failed(c) || j + 1 >= c.m) return;
   const int n = c.n, b = c.b, w = c.w, ld = w + 1;
   const double* band = bb.d_work + c.band_off;
   double* X = bb.d_work + c.x_off;
+  double* T = bb.d_work + c.av_off;
   const double* q = bb.d_work + c.v_off + (int64_t)j * b * n;
   const double* bd = bb.d_bdiag + c.b_off;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) X[idx] = bd[idx % n] * q[idx];
-  __syncthreads();
-  // forward: L y = r
-  for (int r = 0; r < n; ++r) {
-    const double* cr = band + (int64_t)r * ld;
-    const double ip = 1.0 / cr[0];
-    for (int cc = threadIdx.x; cc < b; cc += NT) X[r + (int64_t)cc * n] *= ip;
-    __syncthreads();
-    const int lim = min(w, n - 1 - r);
-    for (int idx = threadIdx.x; idx < lim * b; idx += NT) {
-      const int d = idx % lim + 1, cc = idx / lim;
-      X[r + d + (int64_t)cc * n] -= cr[d] * X[r + (int64_t)cc * n];
-    }
-    __syncthreads();
+  for (int col = threadIdx.x; col < b; col += blockDim.x) {
+    for (int r = 0; r < n; ++r) T[(int64_t)r * b + col] = bd[r] * q[r + (int64_t)col * n];
+    lane_band_solve(band, ld, w, n, b, T, col);
+    for (int r = 0; r < n; ++r) X[r + (int64_t)col * n] = -T[(int64_t)r * b + col];
   }
-  // backward: L^T x = y
-  for (int r = n - 1; r >= 0; --r) {
-    const double ip = 1.0 / band[(int64_t)r * ld];
-    for (int cc = threadIdx.x; cc < b; cc += NT) X[r + (int64_t)cc * n] *= ip;
-    __syncthreads();
-    const int lim = min(w, r);
-    for (int idx = threadIdx.x; idx < lim * b; idx += NT) {
-      const int d = idx % lim + 1, cc = idx / lim;
-      X[r - d + (int64_t)cc * n] -= band[(int64_t)(r - d) * ld + d] * X[r + (int64_t)cc * n];
-    }
-    __syncthreads();
-  }
-  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) X[idx] = -X[idx];
 }
 
 // K3: A V (local CSR) then A^m = V^T (A V), symmetrised.
@@ -554,7 +577,8 @@ hipError_t launch_build(const BuildBatch& bb, hipStream_t st) {
   for (int j = 0; j < bb.max_m; ++j) {
     hipLaunchKernelGGL(k_cgs2, grid, block, 0, st, bb, j);
     hipLaunchKernelGGL(k_normalize, grid, block, 0, st, bb, j);
-    if (j + 1 < bb.max_m) hipLaunchKernelGGL(k_shift_solve, grid, block, 0, st, bb, j);
+    // one lane per right-hand side
+    if (j + 1 < bb.max_m) hipLaunchKernelGGL(k_shift_solve, grid, dim3(std::min(NT, (bb.max_b + 63) / 64 * 64)), 0, st, bb, j);
   }
   hipLaunchKernelGGL(k_project, grid, block, 0, st, bb);
   hipLaunchKernelGGL(k_lanczos, grid, block, 0, st, bb);
@@ -870,7 +894,7 @@ __global__ __launch_bounds__(NT) void k_tf_exact(BuildBatch bb) {
   const int n = c.n, b = c.b, w = c.w, ld = w + 1;
   const double* band = bb.d_work + c.band_off;
   double* Wd = bb.d_work + c.v_off;
-  double* X = bb.d_work + c.x_off;
+  double* T = bb.d_work + c.av_off;
   double* F = bb.d_work + c.s_off;
   for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) Wd[idx] = 0.0;
   __syncthreads();
@@ -881,33 +905,13 @@ __global__ __launch_bounds__(NT) void k_tf_exact(BuildBatch bb) {
     for (int l = 0; l < bp; ++l) Wd[row + (int64_t)(col0 + l) * n] = sp[(int64_t)l * kp];
   }
   __syncthreads();
-  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) X[idx] = Wd[idx];
+  for (int col = threadIdx.x; col < b; col += NT) {
+    for (int r = 0; r < n; ++r) T[(int64_t)r * b + col] = Wd[r + (int64_t)col * n];
+    lane_band_solve(band, ld, w, n, b, T, col);
+  }
   __syncthreads();
-  for (int r = 0; r < n; ++r) {
-    const double* cr = band + (int64_t)r * ld;
-    const double ip = 1.0 / cr[0];
-    for (int cc = threadIdx.x; cc < b; cc += NT) X[r + (int64_t)cc * n] *= ip;
-    __syncthreads();
-    const int lim = min(w, n - 1 - r);
-    for (int idx = threadIdx.x; idx < lim * b; idx += NT) {
-      const int d = idx % lim + 1, cc = idx / lim;
-      X[r + d + (int64_t)cc * n] -= cr[d] * X[r + (int64_t)cc * n];
-    }
-    __syncthreads();
-  }
-  for (int r = n - 1; r >= 0; --r) {
-    const double ip = 1.0 / band[(int64_t)r * ld];
-    for (int cc = threadIdx.x; cc < b; cc += NT) X[r + (int64_t)cc * n] *= ip;
-    __syncthreads();
-    const int lim = min(w, r);
-    for (int idx = threadIdx.x; idx < lim * b; idx += NT) {
-      const int d = idx % lim + 1, cc = idx / lim;
-      X[r - d + (int64_t)cc * n] -= band[(int64_t)(r - d) * ld + d] * X[r + (int64_t)cc * n];
-    }
-    __syncthreads();
-  }
-  // (A + z B)^{-1} = -(band factor)^{-1}
-  wg_gemm<true, false>(b, b, n, -1.0, Wd, n, X, n, 0.0, F, b);
+  // (A + z B)^{-1} = -(L L^T)^{-1}; T is row-major n x b
+  wg_gemm<true, true>(b, b, n, -1.0, Wd, n, T, b, 0.0, F, b);
 }
 
 // ROM transfer function U^1(z) = E_1^T (L' + z D')^{-1} E_1 of the on-line

@@ -221,6 +221,47 @@ def test_cell_variants_match_oracle(dev):
         assert e <= 1e-4
 
 
+def test_widest_cells_and_buckets(dev):
+    """25 face + 4 edge + 1 corner modes: interior cells reach b = 206 (the
+    16-strip matrix-core kernel) while wall cells fall into smaller strip
+    buckets, all in one run; FP32 against the oracle (1e-4)."""
+    S, P = _lib()
+    wl = synth.workload("small", modes_face=25, modes_edge=4, m=3, n_steps=300)
+    run = pipeline.setup(wl)
+    pipeline.build_all(run)
+    ref = pipeline.rom_traces(run)
+    tr, _, info = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w)
+    e = rel(tr, ref)
+    print(f"max_b {info['max_b']}: FP32 rel L2 vs oracle {e:.2e}")
+    assert info["max_b"] > 192
+    assert e <= 1e-4
+
+
+def test_zero_steps_and_repeated_runs(dev):
+    """A run of zero steps changes nothing; two runs of n steps equal one run
+    of 2n steps (the state carries over)."""
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3, n_steps=200)
+    run = pipeline.setup(wl)
+    h = _handle(S)
+    try:
+        P.setup(h, wl)
+        S.sfrom_build(h, wl.m, wl.shift, S.SFROM_F64)
+        info = S.sfrom_get_info(h)
+        shp = (info["n_receivers"], info["n_sources"])
+        full = np.zeros((200,) + shp)
+        S.sfrom_run(h, 200, run.dt, run.w, full)
+        S.sfrom_reset(h)
+        a = np.zeros((100,) + shp)
+        S.sfrom_run(h, 100, run.dt, run.w[:100], a)
+        S.sfrom_run(h, 0, run.dt, run.w[:0], np.zeros((0,) + shp))
+        b = np.zeros((100,) + shp)
+        S.sfrom_run(h, 100, run.dt, run.w[100:], b)
+    finally:
+        S.sfrom_destroy(h)
+    assert np.array_equal(np.concatenate([a, b]), full)
+
+
 def test_breakdown_is_reported(dev):
     """A partition whose Krylov blocks lose rank (a corner node with no
     interior neighbour in a 2D slab, m = 2) must fail with EBREAKDOWN."""
