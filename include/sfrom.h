@@ -223,8 +223,9 @@ int sfrom_set_graph(sfrom_t* h, int32_t enable);
 
 /* Kernel variant of the on-line cell phase: -1 (default) lets the
  * autotuner time the variants on the first run and keep the fastest; 0..3
- * pin a matrix-core tiling, 4 the scalar kernel (F64 always uses the scalar
- * kernel). Meant for tests and tuning studies. */
+ * pin a matrix-core tiling (FP32, BF16 or FP64 matrix instructions by the
+ * on-line precision), 4 the scalar kernel. Meant for tests and tuning
+ * studies. */
 int sfrom_set_cell_variant(sfrom_t* h, int32_t variant);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around

@@ -139,7 +139,31 @@ __global__ __launch_bounds__(CELL_NT) void k_cell_phase(StepArgs a, int nst) {
 // ---------------------------------------------------------------------------
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// Precision modes of the matrix-core cell phase: 0 = FP32 blocks and state,
+// 1 = BF16 blocks with FP32 accumulation and state, 2 = FP64.
+template <int PM>
+struct Prec;
+template <>
+struct Prec<0> {
+  using T = float; using TB = float; using V4 = float4; using ACC = floatx4;
+};
+template <>
+struct Prec<1> {
+  using T = float; using TB = __hip_bfloat16; using V4 = float4; using ACC = floatx4;
+};
+template <>
+struct Prec<2> {
+  using T = double; using TB = double; using V4 = double4; using ACC = doublex4;
+};
+template <typename V4, typename T>
+__device__ inline V4 mk4(T a, T b, T c, T d) {
+  V4 v;
+  v.x = a; v.y = b; v.z = c; v.w = d;
+  return v;
+}
 
 __device__ inline short f2bf(float f) {
   // round to nearest even (the state is finite; NaN propagates as NaN)
@@ -148,10 +172,10 @@ __device__ inline short f2bf(float f) {
   return (short)(u >> 16);
 }
 
-template <bool BF16>
+template <int PM>
 struct AFrag;
 template <>
-struct AFrag<false> {
+struct AFrag<0> {
   float4 v;
   __device__ void load(const float* p) { v = *reinterpret_cast<const float4*>(p); }
   // A[i][k..k+3] = C[k..k+3][i] of a row-major block with row stride ld,
@@ -165,7 +189,23 @@ struct AFrag<false> {
   __device__ void zero() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
 };
 template <>
-struct AFrag<true> {
+struct AFrag<2> {
+  double4 v;
+  __device__ void load(const double* p) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    const double2 a = q[0], b = q[1];
+    v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+  }
+  __device__ void load_t(const double* base, int ld, int k, int i, int nrow) {
+    v.x = (k < nrow) ? base[(int64_t)k * ld + i] : 0.0;
+    v.y = (k + 1 < nrow) ? base[(int64_t)(k + 1) * ld + i] : 0.0;
+    v.z = (k + 2 < nrow) ? base[(int64_t)(k + 2) * ld + i] : 0.0;
+    v.w = (k + 3 < nrow) ? base[(int64_t)(k + 3) * ld + i] : 0.0;
+  }
+  __device__ void zero() { v.x = v.y = v.z = v.w = 0.0; }
+};
+template <>
+struct AFrag<1> {
   shortx4 v;
   __device__ void load(const __hip_bfloat16* p) { v = *reinterpret_cast<const shortx4*>(p); }
   __device__ void load_t(const __hip_bfloat16* base_, int ld, int k, int i, int nrow) {
@@ -180,26 +220,32 @@ struct AFrag<true> {
 
 // B fragments of chunk ch: column tile ct reads its 4 consecutive k of the
 // transposed LDS tile Bt
-template <int CT>
-__device__ inline void load_b(float4 (&bv)[CT], const float* Bt, int kp, int ch, int g, int li) {
+template <int CT, typename V4, typename T>
+__device__ inline void load_b(V4 (&bv)[CT], const T* Bt, int kp, int ch, int g, int li) {
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) bv[ct] = *reinterpret_cast<const float4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
+  for (int ct = 0; ct < CT; ++ct) bv[ct] = *reinterpret_cast<const V4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
 }
 
 // acc[ct] += A chunk x B chunk for column tile ct, reading that tile's B
 // fragment from LDS just before its products (fewer live registers; the
 // dependent products of one tile are interleaved with other waves')
-template <int CT, bool BF16>
-__device__ inline void mma_chunk_lean(floatx4 (&acc)[CT], const AFrag<BF16>& A, const float* Bt, int kp, int ch,
-                                      int g, int li) {
+template <int CT, int PM>
+__device__ inline void mma_chunk_lean(typename Prec<PM>::ACC (&acc)[CT], const AFrag<PM>& A,
+                                      const typename Prec<PM>::T* Bt, int kp, int ch, int g, int li) {
+  using V4 = typename Prec<PM>::V4;
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
-    const float4 bv = *reinterpret_cast<const float4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
-    if constexpr (!BF16) {
+    const V4 bv = *reinterpret_cast<const V4*>(Bt + (ct * 16 + li) * kp + ch * 16 + g * 4);
+    if constexpr (PM == 0) {
       acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.x, bv.x, acc[ct], 0, 0, 0);
       acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.y, bv.y, acc[ct], 0, 0, 0);
       acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.z, bv.z, acc[ct], 0, 0, 0);
       acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.w, bv.w, acc[ct], 0, 0, 0);
+    } else if constexpr (PM == 2) {
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v.x, bv.x, acc[ct], 0, 0, 0);
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v.y, bv.y, acc[ct], 0, 0, 0);
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v.z, bv.z, acc[ct], 0, 0, 0);
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v.w, bv.w, acc[ct], 0, 0, 0);
     } else {
       const shortx4 bb = shortx4{f2bf(bv.x), f2bf(bv.y), f2bf(bv.z), f2bf(bv.w)};
       acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.v, bb, acc[ct], 0, 0, 0);
@@ -208,10 +254,11 @@ __device__ inline void mma_chunk_lean(floatx4 (&acc)[CT], const AFrag<BF16>& A, 
 }
 
 // acc[ct] += A chunk x B chunk (column tile ct)
-template <int CT, bool BF16>
-__device__ inline void mma_chunk(floatx4 (&acc)[CT], const AFrag<BF16>& A, const float4 (&bv)[CT]) {
+template <int CT, int PM>
+__device__ inline void mma_chunk(typename Prec<PM>::ACC (&acc)[CT], const AFrag<PM>& A,
+                                 const typename Prec<PM>::V4 (&bv)[CT]) {
   // consecutive MFMAs go to independent accumulators (column tiles)
-  if constexpr (!BF16) {
+  if constexpr (PM == 0) {
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.x, bv[ct].x, acc[ct], 0, 0, 0);
 #pragma unroll
@@ -220,6 +267,15 @@ __device__ inline void mma_chunk(floatx4 (&acc)[CT], const AFrag<BF16>& A, const
     for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.z, bv[ct].z, acc[ct], 0, 0, 0);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v.w, bv[ct].w, acc[ct], 0, 0, 0);
+  } else if constexpr (PM == 2) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v.x, bv[ct].x, acc[ct], 0, 0, 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v.y, bv[ct].y, acc[ct], 0, 0, 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v.z, bv[ct].z, acc[ct], 0, 0, 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v.w, bv[ct].w, acc[ct], 0, 0, 0);
   } else {
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
@@ -247,11 +303,15 @@ __device__ inline bool last_chunk_of_layer(const StripPos& p, int m, int nch) {
   return p.ch == nch - 1 && (p.t == 2 || (p.t == 1 && p.l == m - 1));
 }
 
-template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, bool BF16>
+template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, int PM>
 __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp, int ntile) {
-  using TB = typename std::conditional<BF16, __hip_bfloat16, float>::type;
+  using T = typename Prec<PM>::T;
+  using TB = typename Prec<PM>::TB;
+  using V4 = typename Prec<PM>::V4;
+  using ACC = typename Prec<PM>::ACC;
   constexpr int NS = 16 * CT;
-  extern __shared__ float lds[];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
   // Workgroups are dealt to the 8 XCDs round-robin; the source tiles of one
   // cell are placed 8 workgroup ids apart so that they land on the same XCD
   // close in time and share its L2 copy of the cell's blocks.
@@ -273,19 +333,19 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
   const int nch = (b + 15) >> 4;
   const bool active = w < nch;
   const int arow = w * 16 + li;
-  const float* __restrict__ ycur = reinterpret_cast<const float*>(a.y_cur);
-  const float* __restrict__ hcur = reinterpret_cast<const float*>(a.h_cur);
-  float* __restrict__ hold = reinterpret_cast<float*>(a.h_old);
-  float* __restrict__ phi = reinterpret_cast<float*>(a.phi);
+  const T* __restrict__ ycur = reinterpret_cast<const T*>(a.y_cur);
+  const T* __restrict__ hcur = reinterpret_cast<const T*>(a.h_cur);
+  T* __restrict__ hold = reinterpret_cast<T*>(a.h_old);
+  T* __restrict__ phi = reinterpret_cast<T*>(a.phi);
   const int32_t* __restrict__ gat = a.d_gather + c.u1_off;
   const TB* __restrict__ blk = reinterpret_cast<const TB*>(a.d_blocks) + c.blk_off;
   const int64_t bsz = (int64_t)b * ld;
-  const float dt2 = (float)a.dt2;
+  const T dt2 = (T)a.dt2;
   const int tsz = NS * kp;
   // hidden layer j >= 1 of this cell, first source of the tile
   auto hrow = [&](auto* base, int j) { return base + (c.hid_off + (int64_t)(j - 1) * ld) * ns + (int64_t)s0 * ld; };
 
-  auto load_chunk = [&](AFrag<BF16>& A, const StripPos& p) {
+  auto load_chunk = [&](AFrag<PM>& A, const StripPos& p) {
     const TB* base = blk + (int64_t)(2 * p.l + p.t - 1) * bsz;
     const int kk = p.ch * 16 + g * 4;
     if (!active || arow >= b) A.zero();
@@ -306,44 +366,44 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
     iok[i] = iq[i] < 4 * nch && 4 * iq[i] < ld && icol[i] < nsl;
   }
   // X_j values of the thread's items (zero outside the cell or the tile)
-  auto load_layer = [&](float4 (&v)[CT], int j) {
+  auto load_layer = [&](V4 (&v)[CT], int j) {
 #pragma unroll
     for (int i = 0; i < CT; ++i) {
-      v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      v[i] = mk4<V4, T>(0, 0, 0, 0);
       if (iok[i]) {
         if (j == 0) {
-          float x[4];
+          T x[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int kk = 4 * iq[i] + e;
-            x[e] = (kk < b) ? ycur[(int64_t)gat[kk] * ns + s0 + icol[i]] : 0.f;
+            x[e] = (kk < b) ? ycur[(int64_t)gat[kk] * ns + s0 + icol[i]] : (T)0;
           }
-          v[i] = make_float4(x[0], x[1], x[2], x[3]);
+          v[i] = mk4<V4, T>(x[0], x[1], x[2], x[3]);
         } else {
-          v[i] = *reinterpret_cast<const float4*>(hrow(hcur, j) + (int64_t)icol[i] * ld + 4 * iq[i]);
+          v[i] = *reinterpret_cast<const V4*>(hrow(hcur, j) + (int64_t)icol[i] * ld + 4 * iq[i]);
         }
       }
     }
   };
-  auto store_layer = [&](const float4 (&v)[CT], int j) {
-    float* T = lds + (j % TS) * tsz;
+  auto store_layer = [&](const V4 (&v)[CT], int j) {
+    T* tile = lds + (j % TS) * tsz;
 #pragma unroll
     for (int i = 0; i < CT; ++i)
-      if (iq[i] < 4 * NCH) *reinterpret_cast<float4*>(T + icol[i] * kp + 4 * iq[i]) = v[i];
+      if (iq[i] < 4 * NCH) *reinterpret_cast<V4*>(tile + icol[i] * kp + 4 * iq[i]) = v[i];
   };
   // previous-level values of the layer's outputs owned by this lane
-  auto load_old = [&](float4 (&o)[CT], int j) {
+  auto load_old = [&](V4 (&o)[CT], int j) {
     const int row0 = w * 16 + 4 * g;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int col = ct * 16 + li;
       o[ct] = (active && row0 < b && col < nsl)
-                  ? *reinterpret_cast<const float4*>(hrow(hold, j) + (int64_t)col * ld + row0)
-                  : make_float4(0.f, 0.f, 0.f, 0.f);
+                  ? *reinterpret_cast<const V4*>(hrow(hold, j) + (int64_t)col * ld + row0)
+                  : mk4<V4, T>(0, 0, 0, 0);
     }
   };
 
-  float4 xn[CT];
+  V4 xn[CT];
   {
     load_layer(xn, 0);
     store_layer(xn, 0);
@@ -352,7 +412,7 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
     if (!(LEAN && TS == 2) && m > 2) load_layer(xn, 2);
   }
   // the ring: chunk stream positions q .. q+R-1
-  AFrag<BF16> ring[R];
+  AFrag<PM> ring[R];
   StripPos pf = stream_begin();   // next chunk to fetch
   bool pf_ok = true;
 #pragma unroll
@@ -366,32 +426,32 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
   }
   __syncthreads();
   StripPos p = stream_begin();    // chunk consumed next
-  float4 ho[CT];
-  floatx4 acc[CT];
+  V4 ho[CT];
+  ACC acc[CT];
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int ct = 0; ct < CT; ++ct) acc[ct] = ACC{0, 0, 0, 0};
   bool more = true;
   while (more) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       if (more) {
-        const AFrag<BF16> cur = ring[u];
+        const AFrag<PM> cur = ring[u];
         if (pf_ok) {
           load_chunk(ring[u], pf);
           pf_ok = stream_next(pf, m, nch);
         }
         const int ly = p.l;
         if (active) {
-          const float* Bt = lds + ((ly + p.t + TS - 1) % TS) * tsz;
+          const T* Bt = lds + ((ly + p.t + TS - 1) % TS) * tsz;
           if constexpr (LEAN) {
-            mma_chunk_lean<CT, BF16>(acc, cur, Bt, kp, p.ch, g, li);
+            mma_chunk_lean<CT, PM>(acc, cur, Bt, kp, p.ch, g, li);
           } else {
-            float4 bv[CT];
+            V4 bv[CT];
             load_b<CT>(bv, Bt, kp, p.ch, g, li);
-            mma_chunk<CT, BF16>(acc, cur, bv);
+            mma_chunk<CT, PM>(acc, cur, bv);
           }
         }
-        if (HO && p.ch == 0 && p.t == (ly == 0 ? 1 : 0) && ly >= 1) load_old(ho, ly);
+        if (HO && PM != 2 && p.ch == 0 && p.t == (ly == 0 ? 1 : 0) && ly >= 1) load_old(ho, ly);
         if (TS == 2 && p.t == 0 && p.ch == nch - 1 && ly + 1 < m) {
           // two tiles: X_{ly+1} replaces X_{ly-1} once every wave is done
           // with C_{ly-1}^T X_{ly-1}
@@ -402,9 +462,32 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
           if (!LEAN && ly + 2 < m) load_layer(xn, ly + 2);
         }
         if (last_chunk_of_layer(p, m, nch)) {
-          if (!HO && ly >= 1) load_old(ho, ly);
-          if (active) {
-            const float* Tl = lds + (ly % TS) * tsz;
+          if (!HO && ly >= 1 && PM != 2) load_old(ho, ly);
+          if constexpr (PM == 2) {
+            // the FP64 product leaves rows 16 w + g + 4 r of column li in
+            // register r (the FP32 one rows 16 w + 4 g + r), so the epilogue
+            // moves single elements
+            if (active) {
+              const T* Tl = lds + (ly % TS) * tsz;
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) {
+                const int col = ct * 16 + li;
+                if (col >= nsl) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int row = w * 16 + g + 4 * r;
+                  if (row >= b) continue;
+                  if (ly == 0) {
+                    phi[(c.u1_off + row) * ns + s0 + col] = acc[ct][r];
+                  } else {
+                    T* hp = hrow(hold, ly) + (int64_t)col * ld + row;
+                    *hp = (T)2 * Tl[col * kp + row] - *hp + dt2 * acc[ct][r];
+                  }
+                }
+              }
+            }
+          } else if (active) {
+            const T* Tl = lds + (ly % TS) * tsz;
             const int row0 = w * 16 + 4 * g;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
@@ -415,19 +498,19 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
                   for (int r = 0; r < 4; ++r)
                     if (row0 + r < b) phi[(c.u1_off + row0 + r) * ns + s0 + col] = acc[ct][r];
                 } else {
-                  const float4 xc = *reinterpret_cast<const float4*>(Tl + col * kp + row0);
-                  float4 o;
-                  o.x = 2.f * xc.x - ho[ct].x + dt2 * acc[ct][0];
-                  o.y = 2.f * xc.y - ho[ct].y + dt2 * acc[ct][1];
-                  o.z = 2.f * xc.z - ho[ct].z + dt2 * acc[ct][2];
-                  o.w = 2.f * xc.w - ho[ct].w + dt2 * acc[ct][3];
-                  *reinterpret_cast<float4*>(hrow(hold, ly) + (int64_t)col * ld + row0) = o;
+                  const V4 xc = *reinterpret_cast<const V4*>(Tl + col * kp + row0);
+                  V4 o;
+                  o.x = (T)2 * xc.x - ho[ct].x + dt2 * acc[ct][0];
+                  o.y = (T)2 * xc.y - ho[ct].y + dt2 * acc[ct][1];
+                  o.z = (T)2 * xc.z - ho[ct].z + dt2 * acc[ct][2];
+                  o.w = (T)2 * xc.w - ho[ct].w + dt2 * acc[ct][3];
+                  *reinterpret_cast<V4*>(hrow(hold, ly) + (int64_t)col * ld + row0) = o;
                 }
               }
             }
           }
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+          for (int ct = 0; ct < CT; ++ct) acc[ct] = ACC{0, 0, 0, 0};
           if (TS == 3 && ly + 2 < m) {
             __syncthreads();                     // every wave is done with X_{ly-1}
             store_layer(xn, ly + 2);
@@ -441,50 +524,61 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
   }
 }
 
-template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, bool BF16>
+template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, int PM>
 static void launch_mfma(const StepArgs& a, hipStream_t st) {
   constexpr int NS = 16 * CT;
   const int kp = 16 * NCH + 4;
-  const size_t lds = (size_t)TS * NS * kp * sizeof(float);
+  const size_t lds = (size_t)TS * NS * kp * sizeof(typename Prec<PM>::T);
   const int ntile = (a.ns + NS - 1) / NS;
   const int groups = (a.nlist + 7) / 8;
-  hipLaunchKernelGGL((k_cell_mfma<NCH, CT, R, HO, TS, MINW, LEAN, BF16>), dim3(groups * 8 * ntile), dim3(64 * NCH), lds,
+  hipLaunchKernelGGL((k_cell_mfma<NCH, CT, R, HO, TS, MINW, LEAN, PM>), dim3(groups * 8 * ntile), dim3(64 * NCH), lds,
                      st, a, kp, ntile);
 }
 
-// waves per SIMD that `TS` tiles of 64 sources let the LDS hold
-template <int NCH, int TS>
-constexpr int lds_waves() {
-  constexpr int bytes = TS * 64 * (16 * NCH + 4) * 4;
-  constexpr int wgs = (160 * 1024) / bytes;
-  constexpr int w = (wgs * NCH + 3) / 4;
+constexpr int LDS_BYTES = 160 * 1024;
+
+// LDS bytes of TS layer tiles of NS sources at NCH strips, ES-byte elements
+constexpr int tile_bytes(int NCH, int TS, int NS, int ES) { return TS * NS * (16 * NCH + 4) * ES; }
+
+// waves per SIMD that the LDS admits for workgroups of NCH waves
+constexpr int lds_waves(int NCH, int bytes) {
+  const int wgs = LDS_BYTES / bytes;
+  const int w = (wgs * NCH + 3) / 4;
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-template <int NCH, bool BF16>
+template <int NCH, int PM>
 static void launch_variant(const StepArgs& a, int variant, hipStream_t st) {
-  // three layer tiles of 64 sources exceed the 160 KiB of LDS beyond 12
-  // chunks: use the 32-source tile there
-  if (3 * 64 * (16 * NCH + 4) * 4 > 160 * 1024) variant = 3;
+  constexpr int ES = sizeof(typename Prec<PM>::T);
+  constexpr int B3 = tile_bytes(NCH, 3, 64, ES), B2 = tile_bytes(NCH, 2, 64, ES);
+  // the fallback: 32-source tile, three layer tiles when they fit, else two
+  constexpr int TS32 = tile_bytes(NCH, 3, 32, ES) <= LDS_BYTES ? 3 : 2;
+  if ((variant == 0 && B3 > LDS_BYTES) || ((variant == 1 || variant == 2) && B2 > LDS_BYTES)) variant = 3;
   switch (variant) {
-    case 0: launch_mfma<NCH, 4, 4, false, 3, lds_waves<NCH, 3>(), false, BF16>(a, st); break;
-    case 1: launch_mfma<NCH, 4, 4, false, 2, lds_waves<NCH, 2>(), false, BF16>(a, st); break;
-    case 2: launch_mfma<NCH, 4, 4, false, 2, lds_waves<NCH, 2>(), true, BF16>(a, st); break;
-    default: launch_mfma<NCH, 2, 4, true, 3, 1, false, BF16>(a, st); break;
+    case 0:
+      if constexpr (B3 <= LDS_BYTES) launch_mfma<NCH, 4, 4, false, 3, lds_waves(NCH, B3), false, PM>(a, st);
+      break;
+    case 1:
+      if constexpr (B2 <= LDS_BYTES) launch_mfma<NCH, 4, 4, false, 2, lds_waves(NCH, B2), false, PM>(a, st);
+      break;
+    case 2:
+      if constexpr (B2 <= LDS_BYTES) launch_mfma<NCH, 4, 4, false, 2, lds_waves(NCH, B2), true, PM>(a, st);
+      break;
+    default: launch_mfma<NCH, 2, 4, PM != 2, TS32, 1, false, PM>(a, st); break;
   }
 }
 
-template <bool BF16>
+template <int PM>
 static hipError_t mfma_dispatch(const StepArgs& a, int variant, hipStream_t st) {
   const int need = (a.max_b + 15) / 16;
-  if (need <= 4) launch_variant<4, BF16>(a, variant, st);
-  else if (need <= 6) launch_variant<6, BF16>(a, variant, st);
-  else if (need <= 7) launch_variant<7, BF16>(a, variant, st);
-  else if (need <= 8) launch_variant<8, BF16>(a, variant, st);
-  else if (need <= 9) launch_variant<9, BF16>(a, variant, st);
-  else if (need <= 10) launch_variant<10, BF16>(a, variant, st);
-  else if (need <= 12) launch_variant<12, BF16>(a, variant, st);
-  else if (need <= 16) launch_variant<16, BF16>(a, variant, st);
+  if (need <= 4) launch_variant<4, PM>(a, variant, st);
+  else if (need <= 6) launch_variant<6, PM>(a, variant, st);
+  else if (need <= 7) launch_variant<7, PM>(a, variant, st);
+  else if (need <= 8) launch_variant<8, PM>(a, variant, st);
+  else if (need <= 9) launch_variant<9, PM>(a, variant, st);
+  else if (need <= 10) launch_variant<10, PM>(a, variant, st);
+  else if (need <= 12) launch_variant<12, PM>(a, variant, st);
+  else if (need <= 16) launch_variant<16, PM>(a, variant, st);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -641,21 +735,22 @@ static hipError_t rec_impl(const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int cell_variants(const StepArgs& a) { return (a.prec == SFROM_F64 || a.max_b > 256) ? 1 : 5; }
+int cell_variants(const StepArgs& a) { return a.max_b > 256 ? 1 : 5; }
 
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st) {
-  // variants 0..3: matrix-core kernel with 4 chunks in flight and the
-  // register budget of the waves the LDS admits (source tile 64 with three
-  // layer tiles; two tiles; two tiles with per-tile B reads and the next
-  // layer read at its store; source tile 32); 4 (and FP64): the scalar
-  // kernel
-  if (a.prec == SFROM_F64 || a.max_b > 256 || a.cell_variant >= 4) {
+  // variants 0..3: matrix-core kernel (FP32, BF16 blocks or FP64) with 4
+  // chunks in flight and the register budget of the waves the LDS admits
+  // (source tile 64 with three layer tiles; two tiles; two tiles with
+  // per-tile B reads and the next layer read at its store; source tile 32);
+  // 4: the scalar kernel
+  if (a.max_b > 256 || a.cell_variant >= 4) {
     if (a.prec == SFROM_F64) return cell_impl<double, double, double>(a, st);
     if (a.prec == SFROM_F32) return cell_impl<float, float, float>(a, st);
     return cell_impl<float, __hip_bfloat16, float>(a, st);
   }
-  if (a.prec == SFROM_F32) return mfma_dispatch<false>(a, a.cell_variant, st);
-  return mfma_dispatch<true>(a, a.cell_variant, st);
+  if (a.prec == SFROM_F32) return mfma_dispatch<0>(a, a.cell_variant, st);
+  if (a.prec == SFROM_F64) return mfma_dispatch<2>(a, a.cell_variant, st);
+  return mfma_dispatch<1>(a, a.cell_variant, st);
 }
 
 hipError_t launch_piece_phase(const StepArgs& a, hipStream_t st) {

@@ -254,10 +254,33 @@ def _trace_arg(traces):
     return _ptr(traces), 0
 
 
+def _check_buffers(h, n_steps, w, traces, prec):
+    """The library cannot see buffer sizes: refuse a trace buffer of the
+    wrong element type or too few elements, and a short wavelet, before any
+    kernel writes to them."""
+    info = sfrom_get_info(h)
+    need = int(n_steps) * info["n_receivers"] * info["n_sources"]
+    itemsize = 8 if prec == SFROM_F64 else 4
+    t_item = traces.element_size() if hasattr(traces, "element_size") else np.asarray(traces).itemsize
+    t_count = traces.numel() if hasattr(traces, "numel") else np.asarray(traces).size
+    if n_steps > 0:
+        if t_item != itemsize:
+            raise ValueError(f"traces must hold {itemsize}-byte values for this precision (got {t_item})")
+        if t_count < need:
+            raise ValueError(f"traces hold {t_count} values, the run writes {need}")
+        if hasattr(traces, "is_contiguous") and not traces.is_contiguous():
+            raise ValueError("traces must be contiguous")
+        w_count = w.numel() if hasattr(w, "numel") else np.asarray(w).size
+        w_item = w.element_size() if hasattr(w, "element_size") else 8
+        if w_count < n_steps or w_item != 8:
+            raise ValueError("the wavelet needs n_steps float64 samples")
+
+
 def sfrom_run(h, n_steps, dt, w, traces):
     """w: numpy float64 (host) or torch float64 CUDA tensor; traces: numpy
     or torch array of n_steps x n_r x n_s in the on-line precision (float64
     for F64, float32 otherwise)."""
+    _check_buffers(h, n_steps, w, traces, sfrom_get_info(h)["online_prec"])
     wp, wdev, keep = _wave_arg(w)
     tp, tdev = _trace_arg(traces)
     _check(h, _lib.sfrom_run(h, n_steps, dt, wp, wdev, tp, tdev))
@@ -268,6 +291,7 @@ def sfrom_fine_reset(h):
 
 
 def sfrom_fine_run(h, n_steps, dt, w, traces, prec=SFROM_F32):
+    _check_buffers(h, n_steps, w, traces, prec)
     wp, wdev, keep = _wave_arg(w)
     tp, tdev = _trace_arg(traces)
     _check(h, _lib.sfrom_fine_run(h, n_steps, dt, wp, wdev, tp, tdev, prec))

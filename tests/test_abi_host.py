@@ -162,3 +162,19 @@ def test_device_calls_refused_on_host_handle(host):
     with pytest.raises(S.SfromError) as e:
         S.sfrom_build(h, 3, -0.02)
     assert e.value.name == "EDEVICE"
+
+
+def test_binding_refuses_undersized_or_mistyped_buffers(monkeypatch):
+    """The library cannot see device buffer sizes, so the binding checks the
+    trace buffer's element size and count and the wavelet length before a
+    run writes to them."""
+    S = _lib()
+    monkeypatch.setattr(S, "sfrom_get_info", lambda h: {"n_receivers": 3, "n_sources": 2, "online_prec": S.SFROM_F64})
+    with pytest.raises(ValueError):
+        S._check_buffers(None, 10, np.zeros(10), np.zeros((10, 3, 2), np.float32), S.SFROM_F64)
+    with pytest.raises(ValueError):
+        S._check_buffers(None, 10, np.zeros(10), np.zeros((9, 3, 2), np.float64), S.SFROM_F64)
+    with pytest.raises(ValueError):
+        S._check_buffers(None, 10, np.zeros(5), np.zeros((10, 3, 2), np.float32), S.SFROM_F32)
+    S._check_buffers(None, 10, np.zeros(10), np.zeros((10, 3, 2), np.float64), S.SFROM_F64)
+    S._check_buffers(None, 0, np.zeros(0), np.zeros((0, 3, 2), np.float32), S.SFROM_F64)

@@ -182,9 +182,10 @@ def test_uneven_layers_per_cell(dev):
 
 
 def test_uneven_layers_matrix_cores(dev):
-    """Per-cell layer counts 1..4 in one launch of the FP32 matrix-core cell
-    phase (every variant) and the scalar kernel: m = 1 has only D_0, m = 2
-    no interior layer, so each branch of the strip sequence is exercised."""
+    """Per-cell layer counts 1..4 in one launch of the matrix-core cell phase
+    (every variant, FP32 and FP64) and the scalar kernel: m = 1 has only D_0,
+    m = 2 no interior layer, so each branch of the strip sequence is
+    exercised."""
     S, P = _lib()
     wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3, n_steps=300)
     run = pipeline.setup(wl)
@@ -194,12 +195,13 @@ def test_uneven_layers_matrix_cores(dev):
         Ai, bi = part.cell_operator(i, sigma, rho)
         run.blocks[i] = build_cell(Ai, bi, part.cell_W(i), wl.shift, int(mpc[i]))
     ref = pipeline.rom_traces(run)
-    for v in range(5):
-        tr, _, info = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w, m_per_cell=mpc, variant=v)
-        e = rel(tr, ref)
-        print(f"variant {v} (used {info['cell_variant']}): rel L2 vs oracle {e:.2e}")
-        assert info["cell_variant"] == v
-        assert e <= 1e-4
+    for prec, tol in ((S.SFROM_F32, 1e-4), (S.SFROM_F64, 1e-10)):
+        for v in range(5):
+            tr, _, info = _gpu_rom(wl, prec, run.dt, run.w, m_per_cell=mpc, variant=v)
+            e = rel(tr, ref)
+            print(f"prec {prec} variant {v} (used {info['cell_variant']}): rel L2 vs oracle {e:.2e}")
+            assert info["cell_variant"] == v
+            assert e <= tol
 
 
 def test_cell_variants_match_oracle(dev):
