@@ -551,6 +551,8 @@ void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std
       BuildBatch bb;
       bb.ncell = cnt;
       bb.max_m = ctx.max_m; bb.max_b = ctx.max_b; bb.max_n = ctx.max_n;
+      bb.max_w = 0;
+      for (const BuildCell& x : bcb) bb.max_w = std::max(bb.max_w, x.w);
       bb.shift = o->shift;
       bb.d_cells = d_bc;
       bb.d_rowptr = d_rp; bb.d_col = d_col; bb.d_a = d_a; bb.d_bdiag = d_bd;

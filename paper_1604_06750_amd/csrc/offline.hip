@@ -362,48 +362,67 @@ __global__ __launch_bounds__(NT) void k_normalize(BuildBatch bb, int j) {
 // Cholesky factor (column-major band, column c holding L[c..c+w][c]) and t
 // is column `col` of the row-major n x b array T, overwritten by x. Each
 // lane touches only its own column, so no barrier is needed; the band
-// entries are wave-uniform (scalar loads) and a row's neighbours are read
-// together.
-__device__ void lane_band_solve(const double* __restrict__ band, int ld, int w, int n, int b, double* T, int col) {
+// entries are wave-uniform (scalar loads). When `win` is given it holds
+// (w + 1) x b doubles in LDS: a ring of the last w + 1 solved rows, so the
+// w neighbours of a row are read from LDS instead of from T.
+__device__ void lane_band_solve(const double* __restrict__ band, int ld, int w, int n, int b, double* T, int col,
+                                double* win) {
+  const int W = w + 1;
   // forward: L y = t, y[r] = (t[r] - sum_d L[r][r-d] y[r-d]) / L[r][r]
+  int head = 0;                                    // r mod W
   for (int r = 0; r < n; ++r) {
     double acc = T[(int64_t)r * b + col];
     const int lim = min(w, r);
-    int d = 1;
-    for (; d + 3 <= lim; d += 4) {
-      const double y0 = T[(int64_t)(r - d) * b + col], y1 = T[(int64_t)(r - d - 1) * b + col];
-      const double y2 = T[(int64_t)(r - d - 2) * b + col], y3 = T[(int64_t)(r - d - 3) * b + col];
-      acc -= band[(int64_t)(r - d) * ld + d] * y0;
-      acc -= band[(int64_t)(r - d - 1) * ld + d + 1] * y1;
-      acc -= band[(int64_t)(r - d - 2) * ld + d + 2] * y2;
-      acc -= band[(int64_t)(r - d - 3) * ld + d + 3] * y3;
+    if (win) {
+      int idx = head;
+#pragma unroll 4
+      for (int d = 1; d <= lim; ++d) {
+        idx = (idx == 0) ? W - 1 : idx - 1;
+        acc -= band[(int64_t)(r - d) * ld + d] * win[idx * b + col];
+      }
+    } else {
+#pragma unroll 4
+      for (int d = 1; d <= lim; ++d) acc -= band[(int64_t)(r - d) * ld + d] * T[(int64_t)(r - d) * b + col];
     }
-    for (; d <= lim; ++d) acc -= band[(int64_t)(r - d) * ld + d] * T[(int64_t)(r - d) * b + col];
-    T[(int64_t)r * b + col] = acc / band[(int64_t)r * ld];
+    const double y = acc / band[(int64_t)r * ld];
+    T[(int64_t)r * b + col] = y;
+    if (win) win[head * b + col] = y;
+    head = (head + 1 == W) ? 0 : head + 1;
   }
   // backward: L^T x = y, x[r] = (y[r] - sum_d L[r+d][r] x[r+d]) / L[r][r]
+  head = (n - 1) % W;                              // r mod W
   for (int r = n - 1; r >= 0; --r) {
     const double* cr = band + (int64_t)r * ld;
     double acc = T[(int64_t)r * b + col];
     const int lim = min(w, n - 1 - r);
-    int d = 1;
-    for (; d + 3 <= lim; d += 4) {
-      const double x0 = T[(int64_t)(r + d) * b + col], x1 = T[(int64_t)(r + d + 1) * b + col];
-      const double x2 = T[(int64_t)(r + d + 2) * b + col], x3 = T[(int64_t)(r + d + 3) * b + col];
-      acc -= cr[d] * x0;
-      acc -= cr[d + 1] * x1;
-      acc -= cr[d + 2] * x2;
-      acc -= cr[d + 3] * x3;
+    if (win) {
+      int idx = head;
+#pragma unroll 4
+      for (int d = 1; d <= lim; ++d) {
+        idx = (idx + 1 == W) ? 0 : idx + 1;
+        acc -= cr[d] * win[idx * b + col];
+      }
+    } else {
+#pragma unroll 4
+      for (int d = 1; d <= lim; ++d) acc -= cr[d] * T[(int64_t)(r + d) * b + col];
     }
-    for (; d <= lim; ++d) acc -= cr[d] * T[(int64_t)(r + d) * b + col];
-    T[(int64_t)r * b + col] = acc / cr[0];
+    const double x = acc / cr[0];
+    T[(int64_t)r * b + col] = x;
+    if (win) win[head * b + col] = x;
+    head = (head == 0) ? W - 1 : head - 1;
   }
+}
+
+// LDS bytes of the solve's window for a batch (0: solve from T)
+inline size_t solve_window_bytes(const BuildBatch& bb) {
+  const size_t bytes = (size_t)(bb.max_w + 1) * bb.max_b * sizeof(double);
+  return bytes <= 64 * 1024 ? bytes : 0;
 }
 
 // X = (A + s B)^{-1} B q_j = -C^{-1} B q_j with C = -(A + sB) = L L^T (the
 // band factor); one lane per column of the block, row-major staging in the
 // free A V region.
-__global__ __launch_bounds__(NT) void k_shift_solve(BuildBatch bb, int j) {
+__global__ __launch_bounds__(NT) void k_shift_solve(BuildBatch bb, int j, int use_win) {
   BuildCell& c = bb.d_cells[blockIdx.x];
   if (cell_failed(c) || j + 1 >= c.m) return;
   const int n = c.n, b = c.b, w = c.w, ld = w + 1;
@@ -412,9 +431,11 @@ __global__ __launch_bounds__(NT) void k_shift_solve(BuildBatch bb, int j) {
   double* T = bb.d_work + c.av_off;
   const double* q = bb.d_work + c.v_off + (int64_t)j * b * n;
   const double* bd = bb.d_bdiag + c.b_off;
+  extern __shared__ double sw_win[];
+  double* win = use_win ? sw_win : nullptr;
   for (int col = threadIdx.x; col < b; col += blockDim.x) {
     for (int r = 0; r < n; ++r) T[(int64_t)r * b + col] = bd[r] * q[r + (int64_t)col * n];
-    lane_band_solve(band, ld, w, n, b, T, col);
+    lane_band_solve(band, ld, w, n, b, T, col, win);
     for (int r = 0; r < n; ++r) X[r + (int64_t)col * n] = -T[(int64_t)r * b + col];
   }
 }
@@ -577,8 +598,11 @@ hipError_t launch_build(const BuildBatch& bb, hipStream_t st) {
   for (int j = 0; j < bb.max_m; ++j) {
     hipLaunchKernelGGL(k_cgs2, grid, block, 0, st, bb, j);
     hipLaunchKernelGGL(k_normalize, grid, block, 0, st, bb, j);
-    // one lane per right-hand side
-    if (j + 1 < bb.max_m) hipLaunchKernelGGL(k_shift_solve, grid, dim3(std::min(NT, (bb.max_b + 63) / 64 * 64)), 0, st, bb, j);
+    // one lane per right-hand side, neighbours from an LDS window
+    const size_t wb = solve_window_bytes(bb);
+    if (j + 1 < bb.max_m)
+      hipLaunchKernelGGL(k_shift_solve, grid, dim3(std::min(NT, (bb.max_b + 63) / 64 * 64)), wb, st, bb, j,
+                         wb > 0 ? 1 : 0);
   }
   hipLaunchKernelGGL(k_project, grid, block, 0, st, bb);
   hipLaunchKernelGGL(k_lanczos, grid, block, 0, st, bb);
@@ -888,7 +912,7 @@ __global__ __launch_bounds__(NT) void k_sfraction_to_normal(BuildBatch bb) {
 
 // Exact cell transfer function F(z) = W^T (A + z B)^{-1} W from the band
 // factor of -(A + z B) that k_band_chol left (shift z < 0); F goes to s.
-__global__ __launch_bounds__(NT) void k_tf_exact(BuildBatch bb) {
+__global__ __launch_bounds__(NT) void k_tf_exact(BuildBatch bb, int use_win) {
   BuildCell& c = bb.d_cells[blockIdx.x];
   if (cell_failed(c)) return;
   const int n = c.n, b = c.b, w = c.w, ld = w + 1;
@@ -905,9 +929,11 @@ __global__ __launch_bounds__(NT) void k_tf_exact(BuildBatch bb) {
     for (int l = 0; l < bp; ++l) Wd[row + (int64_t)(col0 + l) * n] = sp[(int64_t)l * kp];
   }
   __syncthreads();
+  extern __shared__ double tf_win[];
+  double* win = use_win ? tf_win : nullptr;
   for (int col = threadIdx.x; col < b; col += NT) {
     for (int r = 0; r < n; ++r) T[(int64_t)r * b + col] = Wd[r + (int64_t)col * n];
-    lane_band_solve(band, ld, w, n, b, T, col);
+    lane_band_solve(band, ld, w, n, b, T, col, win);
   }
   __syncthreads();
   // (A + z B)^{-1} = -(L L^T)^{-1}; T is row-major n x b
@@ -1070,7 +1096,8 @@ hipError_t launch_learned_check(const BuildBatch& bb, const float* y, int P, con
     BuildBatch bz = bb;
     bz.shift = z[j];
     hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bz);
-    hipLaunchKernelGGL(k_tf_exact, grid, block, 0, st, bz);
+    const size_t wb = solve_window_bytes(bz);
+    hipLaunchKernelGGL(k_tf_exact, grid, block, wb, st, bz, wb > 0 ? 1 : 0);
     hipLaunchKernelGGL(k_tf_rom, grid, block, 0, st, bz, z[j], mis);
   }
   return hipGetLastError();

@@ -102,6 +102,7 @@ struct OnlinePiece {
 struct BuildBatch {
   int32_t ncell;
   int32_t max_m, max_b, max_n;
+  int32_t max_w;              // largest band width of the batch's cells
   double shift;
   BuildCell* d_cells;
   const int32_t* d_rowptr;
