@@ -489,7 +489,11 @@ void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
 template <class F>
 void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std::vector<int32_t>& list, F&& body) {
   if (list.empty()) return;
-  const int64_t budget = (int64_t)8 << 30;   // bytes of workspace
+  // workspace budget: up to 32 GiB (HBM holds 288 GB), at most half of the
+  // memory that is free now
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)32 << 30, (int64_t)(free_b / 2)));
   int64_t wmax = 0;
   for (int32_t i : list) wmax = std::max(wmax, ctx.wsize[i]);
   int per_batch = o->cells_per_batch > 0 ? o->cells_per_batch : (int)list.size();
