@@ -413,9 +413,73 @@ __device__ void lane_band_solve(const double* __restrict__ band, int ld, int w, 
   }
 }
 
-// LDS bytes of the solve's window for a batch (0: solve from T)
+// Workgroup form of the same solve with the band column staged in LDS:
+// every thread calls it; thread `col` < b owns right-hand side col. The
+// forward sweep is right-looking (after y[r] is known, the next w partial
+// sums in the LDS ring `win` are updated from column r of L, which is read
+// contiguously), the backward sweep left-looking with four partial sums.
+// win holds (w + 1) x b doubles, colbuf w + 1 doubles.
+__device__ void wg_band_solve(const double* __restrict__ band, int ld, int w, int n, int b, double* T,
+                              double* win, double* colbuf) {
+  const int W = w + 1;
+  const int col = threadIdx.x;
+  const bool own = col < b;
+  if (own)
+    for (int q = 0; q < min(W, n); ++q) win[q * b + col] = T[(int64_t)q * b + col];
+  int head = 0;
+  for (int r = 0; r < n; ++r) {
+    const int lim = min(w, n - 1 - r);
+    for (int k = threadIdx.x; k <= lim; k += blockDim.x) colbuf[k] = band[(int64_t)r * ld + k];
+    __syncthreads();
+    if (own) {
+      const double y = win[head * b + col] / colbuf[0];
+      T[(int64_t)r * b + col] = y;
+      int idx = head;
+      for (int d = 1; d <= lim; ++d) {
+        idx = (idx + 1 == W) ? 0 : idx + 1;
+        win[idx * b + col] -= colbuf[d] * y;
+      }
+      if (r + W < n) win[head * b + col] = T[(int64_t)(r + W) * b + col];
+    }
+    head = (head + 1 == W) ? 0 : head + 1;
+    __syncthreads();
+  }
+  head = (n - 1) % W;
+  for (int r = n - 1; r >= 0; --r) {
+    const int lim = min(w, n - 1 - r);
+    for (int k = threadIdx.x; k <= lim; k += blockDim.x) colbuf[k] = band[(int64_t)r * ld + k];
+    __syncthreads();
+    if (own) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int idx = head;
+      int d = 1;
+      for (; d + 3 <= lim; d += 4) {
+        idx = (idx + 1 == W) ? 0 : idx + 1;
+        a0 += colbuf[d] * win[idx * b + col];
+        idx = (idx + 1 == W) ? 0 : idx + 1;
+        a1 += colbuf[d + 1] * win[idx * b + col];
+        idx = (idx + 1 == W) ? 0 : idx + 1;
+        a2 += colbuf[d + 2] * win[idx * b + col];
+        idx = (idx + 1 == W) ? 0 : idx + 1;
+        a3 += colbuf[d + 3] * win[idx * b + col];
+      }
+      for (; d <= lim; ++d) {
+        idx = (idx + 1 == W) ? 0 : idx + 1;
+        a0 += colbuf[d] * win[idx * b + col];
+      }
+      const double x = (T[(int64_t)r * b + col] - ((a0 + a1) + (a2 + a3))) / colbuf[0];
+      T[(int64_t)r * b + col] = x;
+      win[head * b + col] = x;
+    }
+    head = (head == 0) ? W - 1 : head - 1;
+    __syncthreads();
+  }
+}
+
+// LDS bytes of the solve's window and band column for a batch (0: the
+// per-lane solve from T)
 inline size_t solve_window_bytes(const BuildBatch& bb) {
-  const size_t bytes = (size_t)(bb.max_w + 1) * bb.max_b * sizeof(double);
+  const size_t bytes = (size_t)(bb.max_w + 1) * (bb.max_b + 1) * sizeof(double);
   return bytes <= 64 * 1024 ? bytes : 0;
 }
 
@@ -432,12 +496,15 @@ __global__ __launch_bounds__(NT) void k_shift_solve(BuildBatch bb, int j, int us
   const double* q = bb.d_work + c.v_off + (int64_t)j * b * n;
   const double* bd = bb.d_bdiag + c.b_off;
   extern __shared__ double sw_win[];
-  double* win = use_win ? sw_win : nullptr;
-  for (int col = threadIdx.x; col < b; col += blockDim.x) {
+  for (int col = threadIdx.x; col < b; col += blockDim.x)
     for (int r = 0; r < n; ++r) T[(int64_t)r * b + col] = bd[r] * q[r + (int64_t)col * n];
-    lane_band_solve(band, ld, w, n, b, T, col, win);
-    for (int r = 0; r < n; ++r) X[r + (int64_t)col * n] = -T[(int64_t)r * b + col];
+  if (use_win && b <= (int)blockDim.x) {
+    wg_band_solve(band, ld, w, n, b, T, sw_win, sw_win + (int64_t)(w + 1) * b);
+  } else {
+    for (int col = threadIdx.x; col < b; col += blockDim.x) lane_band_solve(band, ld, w, n, b, T, col, nullptr);
   }
+  for (int col = threadIdx.x; col < b; col += blockDim.x)
+    for (int r = 0; r < n; ++r) X[r + (int64_t)col * n] = -T[(int64_t)r * b + col];
 }
 
 // K3: A V (local CSR) then A^m = V^T (A V), symmetrised.
@@ -930,10 +997,12 @@ __global__ __launch_bounds__(NT) void k_tf_exact(BuildBatch bb, int use_win) {
   }
   __syncthreads();
   extern __shared__ double tf_win[];
-  double* win = use_win ? tf_win : nullptr;
-  for (int col = threadIdx.x; col < b; col += NT) {
+  for (int col = threadIdx.x; col < b; col += NT)
     for (int r = 0; r < n; ++r) T[(int64_t)r * b + col] = Wd[r + (int64_t)col * n];
-    lane_band_solve(band, ld, w, n, b, T, col, win);
+  if (use_win && b <= NT) {
+    wg_band_solve(band, ld, w, n, b, T, tf_win, tf_win + (int64_t)(w + 1) * b);
+  } else {
+    for (int col = threadIdx.x; col < b; col += NT) lane_band_solve(band, ld, w, n, b, T, col, nullptr);
   }
   __syncthreads();
   // (A + z B)^{-1} = -(L L^T)^{-1}; T is row-major n x b
