@@ -415,41 +415,76 @@ __device__ void lane_band_solve(const double* __restrict__ band, int ld, int w, 
 
 // Workgroup form of the same solve with the band column staged in LDS:
 // every thread calls it; thread `col` < b owns right-hand side col. The
-// forward sweep is right-looking (after y[r] is known, the next w partial
-// sums in the LDS ring `win` are updated from column r of L, which is read
-// contiguously), the backward sweep left-looking with four partial sums.
-// win holds (w + 1) x b doubles, colbuf w + 1 doubles.
+// forward sweep is right-looking: the LDS ring `win` accumulates the
+// updates -sum_c L[r][c] y[c] of the next w rows, and once y[r] is known
+// column r of L (read contiguously) updates them. The backward sweep is
+// left-looking with four partial sums. Global reads on the sweep's critical
+// path (the next band column, the next right-hand side) are issued one row
+// ahead, so their latency overlaps the row's arithmetic. win holds
+// (w + 1) x b doubles, colbuf w + 1 doubles.
 __device__ void wg_band_solve(const double* __restrict__ band, int ld, int w, int n, int b, double* T,
                               double* win, double* colbuf) {
   const int W = w + 1;
-  const int col = threadIdx.x;
+  const int col = threadIdx.x, nt = blockDim.x;
   const bool own = col < b;
+  // band column r of L (entries 0..min(w, n-1-r)): the first 4 nt entries
+  // travel through registers (fetched a row ahead), any further ones are
+  // copied when staged
+  auto fetch = [&](int r, double (&c)[4]) {
+    const int lim = min(w, n - 1 - r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = col + i * nt;
+      c[i] = (k <= lim) ? band[(int64_t)r * ld + k] : 0.0;
+    }
+  };
+  auto stage = [&](int r, const double (&c)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (col + i * nt <= w) colbuf[col + i * nt] = c[i];
+    const int lim = min(w, n - 1 - r);
+    for (int k = col + 4 * nt; k <= lim; k += nt) colbuf[k] = band[(int64_t)r * ld + k];
+  };
   if (own)
-    for (int q = 0; q < min(W, n); ++q) win[q * b + col] = T[(int64_t)q * b + col];
+    for (int q = 0; q < W; ++q) win[q * b + col] = 0.0;
+  double c[4];
+  fetch(0, c);
+  stage(0, c);
+  double t_next = own ? T[col] : 0.0;
+  __syncthreads();
   int head = 0;
   for (int r = 0; r < n; ++r) {
     const int lim = min(w, n - 1 - r);
-    for (int k = threadIdx.x; k <= lim; k += blockDim.x) colbuf[k] = band[(int64_t)r * ld + k];
-    __syncthreads();
+    if (r + 1 < n) fetch(r + 1, c);
     if (own) {
-      const double y = win[head * b + col] / colbuf[0];
+      const double t_r = t_next;
+      if (r + 1 < n) t_next = T[(int64_t)(r + 1) * b + col];
+      const double y = (t_r + win[head * b + col]) / colbuf[0];
       T[(int64_t)r * b + col] = y;
       int idx = head;
       for (int d = 1; d <= lim; ++d) {
         idx = (idx + 1 == W) ? 0 : idx + 1;
         win[idx * b + col] -= colbuf[d] * y;
       }
-      if (r + W < n) win[head * b + col] = T[(int64_t)(r + W) * b + col];
+      win[head * b + col] = 0.0;                 // the slot now collects row r + W
     }
     head = (head + 1 == W) ? 0 : head + 1;
     __syncthreads();
+    if (r + 1 < n) stage(r + 1, c);
+    __syncthreads();
   }
   head = (n - 1) % W;
+  fetch(n - 1, c);
+  __syncthreads();
+  stage(n - 1, c);
+  double y_next = own ? T[(int64_t)(n - 1) * b + col] : 0.0;
+  __syncthreads();
   for (int r = n - 1; r >= 0; --r) {
     const int lim = min(w, n - 1 - r);
-    for (int k = threadIdx.x; k <= lim; k += blockDim.x) colbuf[k] = band[(int64_t)r * ld + k];
-    __syncthreads();
+    if (r > 0) fetch(r - 1, c);
     if (own) {
+      const double y_r = y_next;
+      if (r > 0) y_next = T[(int64_t)(r - 1) * b + col];
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int idx = head;
       int d = 1;
@@ -467,11 +502,13 @@ __device__ void wg_band_solve(const double* __restrict__ band, int ld, int w, in
         idx = (idx + 1 == W) ? 0 : idx + 1;
         a0 += colbuf[d] * win[idx * b + col];
       }
-      const double x = (T[(int64_t)r * b + col] - ((a0 + a1) + (a2 + a3))) / colbuf[0];
+      const double x = (y_r - ((a0 + a1) + (a2 + a3))) / colbuf[0];
       T[(int64_t)r * b + col] = x;
       win[head * b + col] = x;
     }
     head = (head == 0) ? W - 1 : head - 1;
+    __syncthreads();
+    if (r > 0) stage(r - 1, c);
     __syncthreads();
   }
 }
