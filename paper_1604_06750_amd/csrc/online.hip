@@ -365,25 +365,34 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
     icol[i] = item / (4 * NCH);
     iok[i] = iq[i] < 4 * nch && 4 * iq[i] < ld && icol[i] < nsl;
   }
-  // X_j values of the thread's items (zero outside the cell or the tile)
-  auto load_layer = [&](V4 (&v)[CT], int j) {
+  // X_0 values of the thread's items, gathered from the piece dofs (zero
+  // outside the cell or the tile). All index loads are issued before any
+  // value load, at clamped in-bounds addresses, so the gather costs two
+  // memory round trips rather than one per element.
+  auto load_x0 = [&](V4 (&v)[CT]) {
+    int32_t gi[CT][4];
+#pragma unroll
+    for (int i = 0; i < CT; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) gi[i][e] = gat[min(4 * iq[i] + e, b - 1)];
 #pragma unroll
     for (int i = 0; i < CT; ++i) {
-      v[i] = mk4<V4, T>(0, 0, 0, 0);
-      if (iok[i]) {
-        if (j == 0) {
-          T x[4];
+      const int64_t sc = s0 + min(icol[i], nsl - 1);
+      T x[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int kk = 4 * iq[i] + e;
-            x[e] = (kk < b) ? ycur[(int64_t)gat[kk] * ns + s0 + icol[i]] : (T)0;
-          }
-          v[i] = mk4<V4, T>(x[0], x[1], x[2], x[3]);
-        } else {
-          v[i] = *reinterpret_cast<const V4*>(hrow(hcur, j) + (int64_t)icol[i] * ld + 4 * iq[i]);
-        }
+      for (int e = 0; e < 4; ++e) {
+        const T y = ycur[(int64_t)gi[i][e] * ns + sc];
+        x[e] = (iok[i] && 4 * iq[i] + e < b) ? y : (T)0;
       }
+      v[i] = mk4<V4, T>(x[0], x[1], x[2], x[3]);
     }
+  };
+  // X_j, j >= 1, of the thread's items (zero outside the cell or the tile)
+  auto load_hidden = [&](V4 (&v)[CT], int j) {
+    const T* src = hrow(hcur, j);
+#pragma unroll
+    for (int i = 0; i < CT; ++i)
+      v[i] = iok[i] ? *reinterpret_cast<const V4*>(src + (int64_t)icol[i] * ld + 4 * iq[i]) : mk4<V4, T>(0, 0, 0, 0);
   };
   auto store_layer = [&](const V4 (&v)[CT], int j) {
     T* tile = lds + (j % TS) * tsz;
@@ -405,11 +414,13 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
 
   V4 xn[CT];
   {
-    load_layer(xn, 0);
+    load_x0(xn);
     store_layer(xn, 0);
-    load_layer(xn, 1 < m ? 1 : 0);
-    if (m > 1) store_layer(xn, 1);
-    if (!(LEAN && TS == 2) && m > 2) load_layer(xn, 2);
+    if (m > 1) {
+      load_hidden(xn, 1);
+      store_layer(xn, 1);
+    }
+    if (!(LEAN && TS == 2) && m > 2) load_hidden(xn, 2);
   }
   // the ring: chunk stream positions q .. q+R-1
   AFrag<PM> ring[R];
@@ -455,11 +466,11 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
         if (TS == 2 && p.t == 0 && p.ch == nch - 1 && ly + 1 < m) {
           // two tiles: X_{ly+1} replaces X_{ly-1} once every wave is done
           // with C_{ly-1}^T X_{ly-1}
-          if (LEAN) load_layer(xn, ly + 1);
+          if (LEAN) load_hidden(xn, ly + 1);
           __syncthreads();
           store_layer(xn, ly + 1);
           __syncthreads();
-          if (!LEAN && ly + 2 < m) load_layer(xn, ly + 2);
+          if (!LEAN && ly + 2 < m) load_hidden(xn, ly + 2);
         }
         if (last_chunk_of_layer(p, m, nch)) {
           if (!HO && ly >= 1 && PM != 2) load_old(ho, ly);
@@ -515,7 +526,7 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
             __syncthreads();                     // every wave is done with X_{ly-1}
             store_layer(xn, ly + 2);
             __syncthreads();
-            if (ly + 3 < m) load_layer(xn, ly + 3);
+            if (ly + 3 < m) load_hidden(xn, ly + 3);
           }
         }
         more = stream_next(p, m, nch);
