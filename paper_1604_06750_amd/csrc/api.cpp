@@ -119,8 +119,18 @@ void free_fine(sfrom_t* h) {
   h->fine_prec = -1; h->fine_ns = -1; h->fine_io_dirty = true;
 }
 
+void free_stage(sfrom_t* h) {
+  auto& st = h->stage;
+  if (h->device >= 0) {
+    dfree(st.d_rowptr); dfree(st.d_col); dfree(st.d_a); dfree(st.d_bdiag);
+    dfree(st.d_wrow); dfree(st.d_wcol); dfree(st.d_wsoff); dfree(st.d_wbp); dfree(st.d_wkp); dfree(st.d_S);
+  }
+  st = sfrom::CellStage();
+}
+
 void free_all(sfrom_t* h) {
   if (h->device < 0) return;
+  free_stage(h);
   if (h->capture_stream) { hipStreamDestroy(h->capture_stream); h->capture_stream = nullptr; }
   for (int k = 0; k < 4; ++k)
     for (auto& pr : h->ev_pending[k]) { h->ev_pool.push_back(pr.first); h->ev_pool.push_back(pr.second); }
@@ -338,10 +348,66 @@ void make_columns(sfrom_t* h, Columns& out, int32_t count, const int64_t* colptr
 struct BuildCtx {
   std::vector<BuildCell> bcells;   // workspace offsets relative to the cell's own slice
   std::vector<int64_t> wsize;      // doubles of workspace per cell
-  std::vector<int64_t> soff;       // offset of each piece basis in d_S
-  double* d_S = nullptr;
   int max_m = 0, max_b = 0, max_n = 0;
 };
+
+// Uploads the build's inputs (cell operators A_i and B_i, the skeleton rows
+// of each W_i = P_i^T P^Gamma S and the piece bases S_p) once per partition.
+void stage_cells(sfrom_t* h) {
+  auto& st = h->stage;
+  if (st.ready) return;
+  free_stage(h);
+  const int nc = (int)h->cells.size(), np = (int)h->pieces.size();
+  st.soff.resize(np);
+  int64_t ns = 0;
+  for (int p = 0; p < np; ++p) { st.soff[p] = ns; ns += (int64_t)h->pieces[p].S.size(); }
+  std::vector<double> S((size_t)ns);
+  for (int p = 0; p < np; ++p) std::copy(h->pieces[p].S.begin(), h->pieces[p].S.end(), S.begin() + st.soff[p]);
+  int64_t nrp = 0, nnz = 0, nb = 0, nwr = 0;
+  st.rp_off.resize(nc); st.csr_off.resize(nc); st.b_off.resize(nc); st.w_off.resize(nc);
+  st.nw.assign(nc, 0); st.bw.assign(nc, 0);
+  for (int i = 0; i < nc; ++i) {
+    const CellDef& c = h->cells[i];
+    st.rp_off[i] = nrp; st.csr_off[i] = nnz; st.b_off[i] = nb; st.w_off[i] = nwr;
+    nrp += c.n + 1; nnz += (int64_t)c.col.size(); nb += c.n;
+    int nw = 0, w = 0;
+    for (int r = 0; r < c.n; ++r) {
+      if (h->piece_of_node[c.gnode[r]] >= 0) ++nw;
+      for (int k = c.rowptr[r]; k < c.rowptr[r + 1]; ++k) w = std::max(w, std::abs(r - c.col[k]));
+    }
+    st.nw[i] = nw; st.bw[i] = w;
+    nwr += nw;
+  }
+  std::vector<int32_t> rowptr((size_t)nrp), col((size_t)nnz), wrow((size_t)nwr), wcol((size_t)nwr), wbp((size_t)nwr),
+      wkp((size_t)nwr);
+  std::vector<double> av((size_t)nnz), bd((size_t)nb);
+  std::vector<int64_t> wsoff((size_t)nwr);
+  std::vector<int32_t> pcol(np, -1);
+  for (int i = 0; i < nc; ++i) {
+    const CellDef& c = h->cells[i];
+    std::copy(c.rowptr.begin(), c.rowptr.end(), rowptr.begin() + st.rp_off[i]);
+    std::copy(c.col.begin(), c.col.end(), col.begin() + st.csr_off[i]);
+    std::copy(c.a.begin(), c.a.end(), av.begin() + st.csr_off[i]);
+    std::copy(c.b.begin(), c.b.end(), bd.begin() + st.b_off[i]);
+    for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) pcol[h->cell_pieces[i][q]] = h->cell_piece_col[i][q];
+    int64_t t = st.w_off[i];
+    for (int r = 0; r < c.n; ++r) {
+      const int32_t p = h->piece_of_node[c.gnode[r]];
+      if (p < 0) continue;
+      wrow[t] = r;
+      wcol[t] = pcol[p];
+      wsoff[t] = st.soff[p] + h->pos_in_piece[c.gnode[r]];
+      wbp[t] = h->pieces[p].b;
+      wkp[t] = (int32_t)h->pieces[p].gnode.size();
+      ++t;
+    }
+    for (int32_t p : h->cell_pieces[i]) pcol[p] = -1;
+  }
+  st.d_rowptr = dupload(h, rowptr); st.d_col = dupload(h, col); st.d_a = dupload(h, av); st.d_bdiag = dupload(h, bd);
+  st.d_wrow = dupload(h, wrow); st.d_wcol = dupload(h, wcol); st.d_wsoff = dupload(h, wsoff);
+  st.d_wbp = dupload(h, wbp); st.d_wkp = dupload(h, wkp); st.d_S = dupload(h, S);
+  st.ready = true;
+}
 
 void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
   REQUIRE(o != nullptr, SFROM_EINVAL, "null build options");
@@ -426,15 +492,7 @@ void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
   h->d_minv = dalloc<unsigned char>(h, (size_t)moff * prec_bytes(h->prec));
   h->d_rom64 = dalloc<double>(h, (size_t)r64);
   h->d_rom64_off = dupload(h, h->rom64_off);
-  // ---- piece bases on the device --------------------------------------------
-  std::vector<double> S;
-  std::vector<int64_t> soff(np);
-  for (int p = 0; p < np; ++p) {
-    soff[p] = (int64_t)S.size();
-    S.insert(S.end(), h->pieces[p].S.begin(), h->pieces[p].S.end());
-  }
-  ctx.d_S = dupload(h, S);
-  ctx.soff = soff;
+  stage_cells(h);
   // ---- per-cell workspace sizes -----------------------------------------------
   std::vector<BuildCell>& bcells = ctx.bcells;
   std::vector<int64_t>& wsize = ctx.wsize;
@@ -444,9 +502,7 @@ void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
     const CellDef& c = h->cells[i];
     BuildCell& bc = bcells[i];
     bc.n = c.n; bc.b = h->cell_b[i]; bc.m = h->cell_m[i]; bc.nnz = (int32_t)c.a.size();
-    int w = 0;
-    for (int r = 0; r < c.n; ++r)
-      for (int k = c.rowptr[r]; k < c.rowptr[r + 1]; ++k) w = std::max(w, std::abs(r - c.col[k]));
+    const int w = h->stage.bw[i];
     bc.w = w;
     const int64_t n = c.n, b = bc.b, mb = (int64_t)bc.m * b;
     int64_t off = 0;
@@ -504,53 +560,24 @@ void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std
     for (size_t c0 = 0; c0 < list.size(); c0 += per_batch) {
       const int cnt = (int)std::min<size_t>(per_batch, list.size() - c0);
       std::vector<int32_t> ids(list.begin() + c0, list.begin() + c0 + cnt);
-      std::vector<int32_t> rowptr, col, wrow, wcol, wbp, wkp;
-      std::vector<double> av, bd;
-      std::vector<int64_t> wsoff;
+      const auto& st = h->stage;
       std::vector<BuildCell> bcb(cnt);
       int64_t woff = 0;
       for (int t = 0; t < cnt; ++t) {
         const int i = ids[t];
-        const CellDef& c = h->cells[i];
         BuildCell& bc = bcb[t];
         bc = ctx.bcells[i];
-        bc.rp_off = (int64_t)rowptr.size();
-        bc.csr_off = (int64_t)col.size();
-        bc.b_off = (int64_t)bd.size();
-        rowptr.insert(rowptr.end(), c.rowptr.begin(), c.rowptr.end());
-        col.insert(col.end(), c.col.begin(), c.col.end());
-        av.insert(av.end(), c.a.begin(), c.a.end());
-        bd.insert(bd.end(), c.b.begin(), c.b.end());
-        bc.w_off = (int64_t)wrow.size();
-        std::map<int32_t, int32_t> pcol;
-        for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) pcol[h->cell_pieces[i][q]] = h->cell_piece_col[i][q];
-        int nw = 0;
-        for (int r = 0; r < c.n; ++r) {
-          const int32_t p = h->piece_of_node[c.gnode[r]];
-          if (p < 0) continue;
-          wrow.push_back(r);
-          wcol.push_back(pcol[p]);
-          wsoff.push_back(ctx.soff[p] + h->pos_in_piece[c.gnode[r]]);
-          wbp.push_back(h->pieces[p].b);
-          wkp.push_back((int32_t)h->pieces[p].gnode.size());
-          ++nw;
-        }
-        bc.nw = nw;
+        bc.rp_off = st.rp_off[i];
+        bc.csr_off = st.csr_off[i];
+        bc.b_off = st.b_off[i];
+        bc.w_off = st.w_off[i];
+        bc.nw = st.nw[i];
         // rebase workspace offsets into this batch's work array
         const int64_t base = woff;
         bc.band_off += base; bc.v_off += base; bc.x_off += base; bc.av_off += base;
         bc.am_off += base; bc.q_off += base; bc.s_off += base; bc.r_off += base; bc.out_off += base;
         woff += ctx.wsize[i];
       }
-      int32_t* d_rp = dupload(h, rowptr);
-      int32_t* d_col = dupload(h, col);
-      double* d_a = dupload(h, av);
-      double* d_bd = dupload(h, bd);
-      int32_t* d_wrow = dupload(h, wrow);
-      int32_t* d_wcol = dupload(h, wcol);
-      int64_t* d_wsoff = dupload(h, wsoff);
-      int32_t* d_wbp = dupload(h, wbp);
-      int32_t* d_wkp = dupload(h, wkp);
       HIPCHK(hipMemcpy(d_bc, bcb.data(), cnt * sizeof(BuildCell), hipMemcpyHostToDevice));
       BuildBatch bb;
       bb.ncell = cnt;
@@ -559,19 +586,11 @@ void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std
       for (const BuildCell& x : bcb) bb.max_w = std::max(bb.max_w, x.w);
       bb.shift = o->shift;
       bb.d_cells = d_bc;
-      bb.d_rowptr = d_rp; bb.d_col = d_col; bb.d_a = d_a; bb.d_bdiag = d_bd;
-      bb.d_wrow = d_wrow; bb.d_wcol = d_wcol; bb.d_wsoff = d_wsoff; bb.d_wbp = d_wbp; bb.d_wkp = d_wkp;
-      bb.d_S = ctx.d_S;
+      bb.d_rowptr = st.d_rowptr; bb.d_col = st.d_col; bb.d_a = st.d_a; bb.d_bdiag = st.d_bdiag;
+      bb.d_wrow = st.d_wrow; bb.d_wcol = st.d_wcol; bb.d_wsoff = st.d_wsoff; bb.d_wbp = st.d_wbp; bb.d_wkp = st.d_wkp;
+      bb.d_S = st.d_S;
       bb.d_work = d_work;
-      try {
-        body(bb, ids);
-      } catch (...) {
-        dfree(d_rp); dfree(d_col); dfree(d_a); dfree(d_bd);
-        dfree(d_wrow); dfree(d_wcol); dfree(d_wsoff); dfree(d_wbp); dfree(d_wkp);
-        throw;
-      }
-      dfree(d_rp); dfree(d_col); dfree(d_a); dfree(d_bd);
-      dfree(d_wrow); dfree(d_wcol); dfree(d_wsoff); dfree(d_wbp); dfree(d_wkp);
+      body(bb, ids);
     }
   } catch (...) {
     dfree(d_work); dfree(d_bc);
@@ -693,11 +712,9 @@ void build_learned(sfrom_t* h, const sfrom_build_opts* o, sfrom_surrogate* sur, 
     build_lanczos(h, o, ctx, rest);
   } catch (...) {
     dfree(d_y);
-    dfree(ctx.d_S);
     throw;
   }
   dfree(d_y);
-  dfree(ctx.d_S);
   for (int t = 0; t < n; ++t) {
     accepted[t] = acc[t];
     if (mismatch) mismatch[t] = mis[t];
@@ -744,13 +761,7 @@ void build(sfrom_t* h, const sfrom_build_opts* o) {
   build_layout(h, o, ctx);
   std::vector<int32_t> all(h->cells.size());
   for (size_t i = 0; i < all.size(); ++i) all[i] = (int32_t)i;
-  try {
-    build_lanczos(h, o, ctx, all);
-  } catch (...) {
-    dfree(ctx.d_S);
-    throw;
-  }
-  dfree(ctx.d_S);
+  build_lanczos(h, o, ctx, all);
   h->built = true;
   h->masses_dirty = true;
   h->src_dirty = h->rec_dirty = true;
@@ -1314,6 +1325,7 @@ int sfrom_set_pencil(sfrom_t* h, int64_t n, const int64_t* rowptr, const int32_t
   h->cells.clear();
   h->pieces.clear();
   h->part_ready = false;
+  free_stage(h);
   h->stencil.clear();
   h->grid_u[0] = h->grid_u[1] = h->grid_u[2] = 0;
   h->src = Columns();
@@ -1361,6 +1373,7 @@ int sfrom_add_cell(sfrom_t* h, int32_t cell, int32_t n_i, const int64_t* global_
   c.defined = true;
   h->cells[cell] = std::move(c);
   h->part_ready = false;
+  free_stage(h);
   free_rom(h);
   API_END(h)
 }
@@ -1387,6 +1400,7 @@ int sfrom_add_piece(sfrom_t* h, int32_t piece, int32_t k_p, const int64_t* globa
   p.defined = true;
   h->pieces[piece] = std::move(p);
   h->part_ready = false;
+  free_stage(h);
   free_rom(h);
   API_END(h)
 }

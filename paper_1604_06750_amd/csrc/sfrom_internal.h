@@ -257,6 +257,27 @@ struct sfrom {
   std::vector<std::vector<int32_t>> piece_cells;   // ascending cell ids
   std::vector<int64_t> piece_dof_off;              // n_pieces + 1
 
+  // Cell operators, skeleton maps and piece bases staged in HBM for the
+  // off-line build: uploaded once per partition and shared by every build,
+  // each cell addressed by its offsets into the concatenated arrays.
+  struct CellStage {
+    bool ready = false;
+    int32_t* d_rowptr = nullptr;   // per cell n_i + 1 local row starts
+    int32_t* d_col = nullptr;
+    double* d_a = nullptr;
+    double* d_bdiag = nullptr;
+    int32_t* d_wrow = nullptr;     // skeleton rows of W_i: local row, column, basis entry
+    int32_t* d_wcol = nullptr;
+    int64_t* d_wsoff = nullptr;
+    int32_t* d_wbp = nullptr;
+    int32_t* d_wkp = nullptr;
+    double* d_S = nullptr;         // piece bases, piece after piece
+    std::vector<int64_t> rp_off, csr_off, b_off, w_off;
+    std::vector<int32_t> nw, bw;   // skeleton rows and half bandwidth per cell
+    std::vector<int64_t> soff;     // offset of each piece basis in d_S
+  };
+  CellStage stage;
+
   // ROM
   bool built = false;
   int32_t prec = SFROM_F32;
