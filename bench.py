@@ -28,6 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "source-steps/s, ROM vs fine-grid leapfrog, at ≤1e-3 receiver rel-L2 error"
 HBM_PEAK_GBS = 8000.0
+# per-kernel HIP events on one step in PROFILE_EVERY of the timed runs: an
+# event pair costs a few microseconds of stream time, so timing every launch
+# would slow the job it measures by about 8%
+PROFILE_EVERY = 8
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 
@@ -198,7 +202,7 @@ def main():
         job()
         torch.cuda.synchronize()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
-    S.sfrom_profile(h, True)
+    S.sfrom_profile(h, PROFILE_EVERY)
     for k in range(4):
         S.sfrom_profile_read(h, k)
     build_ms = []
@@ -234,7 +238,7 @@ def main():
     fprec = S.SFROM_F64 if args.prec == "f64" else S.SFROM_F32
     S.sfrom_fine_run(h, min(nt, 200), dt, w, tf, fprec)   # warm-up
     S.sfrom_fine_reset(h)
-    S.sfrom_profile(h, True)
+    S.sfrom_profile(h, PROFILE_EVERY)
     S.sfrom_profile_read(h, S.KERNEL_FINE)
     e0.record(stream)
     S.sfrom_fine_run(h, nt, dt, w, tf, fprec)

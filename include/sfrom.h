@@ -229,10 +229,13 @@ int sfrom_set_graph(sfrom_t* h, int32_t enable);
 int sfrom_set_cell_variant(sfrom_t* h, int32_t variant);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around
- * every launch while enabled. Kernel ids: 0 on-line cell phase, 1 on-line
- * piece phase, 2 receivers, 3 fine-grid step. sfrom_profile_read
- * synchronises the stream, returns the summed kernel time and the number of
- * launches since the last read, and clears them. */
+ * the launches of timed steps. enable: 0 off; 1 every step; N > 1 one step
+ * in N (steps 0, N, 2N, ... of each run; an event pair costs a few
+ * microseconds of stream time, so sampling keeps the measurement out of the
+ * run's own time); negative values return SFROM_EINVAL. Kernel ids: 0 on-line
+ * cell phase, 1 on-line piece phase, 2 receivers, 3 fine-grid step.
+ * sfrom_profile_read synchronises the stream, returns the summed kernel time
+ * and the number of timed launches since the last read, and clears them. */
 int sfrom_profile(sfrom_t* h, int32_t enable);
 int sfrom_profile_read(sfrom_t* h, int32_t kernel, double* total_ms, int64_t* launches);
 

@@ -158,9 +158,11 @@ hipEvent_t take_event(sfrom_t* h) {
   return e;
 }
 
+// `sample` selects the steps whose launches are timed (one step in
+// h->prof_every while profiling)
 template <typename F>
-void timed(sfrom_t* h, int kid, F&& launch) {
-  if (!h->profiling) {
+void timed(sfrom_t* h, int kid, bool sample, F&& launch) {
+  if (!h->profiling || !sample) {
     HIPCHK(launch());
     return;
   }
@@ -1028,9 +1030,10 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
       a.y_cur = h->d_y[cur]; a.y_old = h->d_y[1 - cur];
       a.h_cur = h->d_h[cur]; a.h_old = h->d_h[1 - cur];
       a.step = s; a.trace_step = s;
-      timed(h, 0, [&] { return cell_phase(a, ls); });
-      timed(h, 1, [&] { return launch_piece_phase(a, ls); });
-      timed(h, 2, [&] { return launch_receivers(a, ls); });
+      const bool sample = s % h->prof_every == 0;
+      timed(h, 0, sample, [&] { return cell_phase(a, ls); });
+      timed(h, 1, sample, [&] { return launch_piece_phase(a, ls); });
+      timed(h, 2, sample, [&] { return launch_receivers(a, ls); });
       cur = 1 - cur;
       if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
     }
@@ -1163,7 +1166,7 @@ void fine_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_
   for (int64_t s = 0; s < n_steps; ++s) {
     a.u_cur = h->d_u[h->fcur]; a.u_old = h->d_u[1 - h->fcur];
     a.step = s; a.trace_step = s;
-    timed(h, 3, [&] { return launch_fine_step(a, h->stream); });
+    timed(h, 3, s % h->prof_every == 0, [&] { return launch_fine_step(a, h->stream); });
     h->fcur = 1 - h->fcur;
     if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
   }
@@ -1779,8 +1782,10 @@ int sfrom_set_cell_variant(sfrom_t* h, int32_t variant) {
 int sfrom_profile(sfrom_t* h, int32_t enable) {
   API_BEGIN(h)
   REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
+  REQUIRE(enable >= 0, SFROM_EINVAL, "profile interval must be >= 0");
   collect_events(h);
   h->profiling = enable != 0;
+  h->prof_every = enable > 1 ? enable : 1;
   API_END(h)
 }
 

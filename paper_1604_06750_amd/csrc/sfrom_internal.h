@@ -346,6 +346,7 @@ struct sfrom {
   // optional per-kernel timing with HIP events (kernel ids: 0 cell phase,
   // 1 piece phase, 2 receivers, 3 fine step)
   bool profiling = false;
+  int32_t prof_every = 1;          // while profiling, steps timed: one in prof_every
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[4];
   double prof_ms[4] = {0, 0, 0, 0};

@@ -318,6 +318,7 @@ def sfrom_set_cell_variant(h, variant=-1):
 
 
 def sfrom_profile(h, enable=True):
+    """enable: False/0 off, True/1 every step, N > 1 one step in N."""
     _check(h, _lib.sfrom_profile(h, int(enable)))
 
 

@@ -264,6 +264,41 @@ def test_zero_steps_and_repeated_runs(dev):
     assert np.array_equal(np.concatenate([a, b]), full)
 
 
+def test_rebuild_reuses_staged_inputs_and_sampled_profile(dev):
+    """A second build on the same handle (inputs staged in HBM by the first)
+    gives bitwise the same traces; profiling one step in 4 times steps 0, 4
+    and 8 of a 10-step run, every step at 1, and changes no result."""
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3, n_steps=10)
+    run = pipeline.setup(wl)
+    h = _handle(S)
+    try:
+        P.setup(h, wl)
+        info = None
+        outs = []
+        for every in (0, 4, 1):
+            S.sfrom_build(h, wl.m, wl.shift, S.SFROM_F64)
+            info = S.sfrom_get_info(h)
+            tr = np.zeros((10, info["n_receivers"], info["n_sources"]))
+            S.sfrom_reset(h)
+            S.sfrom_profile(h, every)
+            for k in range(4):
+                S.sfrom_profile_read(h, k)
+            S.sfrom_run(h, 10, run.dt, run.w, tr)
+            counts = [S.sfrom_profile_read(h, k)[1] for k in range(3)]
+            S.sfrom_profile(h, 0)
+            assert counts == {0: [0, 0, 0], 4: [3, 3, 3], 1: [10, 10, 10]}[every]
+            outs.append(tr)
+        with pytest.raises(S.SfromError) as e:
+            S.sfrom_profile(h, -1)
+        assert e.value.name == "EINVAL"
+    finally:
+        S.sfrom_destroy(h)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    ref = pipeline.rom_traces(pipeline.build_all(run))
+    assert rel(outs[0], ref) < 1e-10
+
+
 def test_breakdown_is_reported(dev):
     """A partition whose Krylov blocks lose rank (a corner node with no
     interior neighbour in a 2D slab, m = 2) must fail with EBREAKDOWN."""
