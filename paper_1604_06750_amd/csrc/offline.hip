@@ -513,6 +513,94 @@ __device__ void wg_band_solve(const double* __restrict__ band, int ld, int w, in
   }
 }
 
+// Register form of the same solve for a single wave and half bandwidth
+// w <= W: lane `col` keeps its right-hand side's window in registers (the
+// partial sums of the next W rows while sweeping forward, the last W
+// solved values while sweeping backward), updated in place with
+// compile-time indices, so a row costs W fused multiply-adds and no LDS
+// traffic beyond the broadcast band column. The column is double-buffered
+// in LDS (colbuf holds 2 (W + 1) doubles, entries beyond the band zero) and
+// fetched from HBM a row ahead, so each row needs one barrier.
+template <int W>
+__device__ void reg_band_solve(const double* __restrict__ band, int ld, int w, int n, int b, double* T,
+                               double* colbuf) {
+  constexpr int NB = W + 1;
+  constexpr int KF = (NB + 63) / 64;    // column entries per lane
+  const int col = threadIdx.x;
+  const bool own = col < b;
+  auto fetch = [&](int r, double (&c)[KF]) {
+    const int lim = min(w, n - 1 - r);
+#pragma unroll
+    for (int i = 0; i < KF; ++i) {
+      const int k = col + 64 * i;
+      c[i] = (k <= lim) ? band[(int64_t)r * ld + k] : 0.0;
+    }
+  };
+  auto stage = [&](double* dst, const double (&c)[KF]) {
+#pragma unroll
+    for (int i = 0; i < KF; ++i)
+      if (col + 64 * i < NB) dst[col + 64 * i] = c[i];
+  };
+  double c[KF];
+  fetch(0, c);
+  stage(colbuf, c);
+  double acc[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) acc[j] = 0.0;
+  double t_next = own ? T[col] : 0.0;
+  __syncthreads();
+  for (int r = 0; r < n; ++r) {
+    const double* cur = colbuf + (r & 1) * NB;
+    if (r + 1 < n) fetch(r + 1, c);
+    if (own) {
+      const double t_r = t_next;
+      if (r + 1 < n) t_next = T[(int64_t)(r + 1) * b + col];
+      const double y = (t_r + acc[0]) / cur[0];
+      T[(int64_t)r * b + col] = y;
+      // acc[j] now collects row r + 1 + j
+#pragma unroll
+      for (int j = 0; j + 1 < W; ++j) acc[j] = fma(-cur[j + 1], y, acc[j + 1]);
+      acc[W - 1] = -cur[W] * y;
+    }
+    if (r + 1 < n) stage(colbuf + ((r + 1) & 1) * NB, c);
+    __syncthreads();
+  }
+  // backward sweep: xw[j] holds x[r + 1 + j]
+  double xw[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) xw[j] = 0.0;
+  fetch(n - 1, c);
+  stage(colbuf + ((n - 1) & 1) * NB, c);
+  double y_next = own ? T[(int64_t)(n - 1) * b + col] : 0.0;
+  __syncthreads();
+  for (int r = n - 1; r >= 0; --r) {
+    const double* cur = colbuf + (r & 1) * NB;
+    if (r > 0) fetch(r - 1, c);
+    if (own) {
+      const double y_r = y_next;
+      if (r > 0) y_next = T[(int64_t)(r - 1) * b + col];
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+      for (int j = 0; j < W; j += 4) {
+        s0 = fma(cur[j + 1], xw[j], s0);
+        if (j + 1 < W) s1 = fma(cur[j + 2], xw[j + 1], s1);
+        if (j + 2 < W) s2 = fma(cur[j + 3], xw[j + 2], s2);
+        if (j + 3 < W) s3 = fma(cur[j + 4], xw[j + 3], s3);
+      }
+      const double x = (y_r - ((s0 + s1) + (s2 + s3))) / cur[0];
+      T[(int64_t)r * b + col] = x;
+#pragma unroll
+      for (int j = W - 1; j > 0; --j) xw[j] = xw[j - 1];
+      xw[0] = x;
+    }
+    if (r > 0) stage(colbuf + ((r - 1) & 1) * NB, c);
+    __syncthreads();
+  }
+}
+
+// Half bandwidths served by the register solve (one instantiation each).
+constexpr int REG_SOLVE_W[] = {32, 64, 88};
+
 // LDS bytes of the solve's window and band column for a batch (0: the
 // per-lane solve from T)
 inline size_t solve_window_bytes(const BuildBatch& bb) {
@@ -541,6 +629,26 @@ __global__ __launch_bounds__(NT) void k_shift_solve(BuildBatch bb, int j, int us
     for (int col = threadIdx.x; col < b; col += blockDim.x) lane_band_solve(band, ld, w, n, b, T, col, nullptr);
   }
   for (int col = threadIdx.x; col < b; col += blockDim.x)
+    for (int r = 0; r < n; ++r) X[r + (int64_t)col * n] = -T[(int64_t)r * b + col];
+}
+
+// The same solve with the register window (one wave, b <= 64, w <= W).
+template <int W>
+__global__ __launch_bounds__(64) void k_shift_solve_reg(BuildBatch bb, int j) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c) || j + 1 >= c.m) return;
+  const int n = c.n, b = c.b, w = c.w, ld = w + 1;
+  const double* band = bb.d_work + c.band_off;
+  double* X = bb.d_work + c.x_off;
+  double* T = bb.d_work + c.av_off;
+  const double* q = bb.d_work + c.v_off + (int64_t)j * b * n;
+  const double* bd = bb.d_bdiag + c.b_off;
+  __shared__ double colbuf[2 * (W + 1)];
+  const int col = threadIdx.x;
+  if (col < b)
+    for (int r = 0; r < n; ++r) T[(int64_t)r * b + col] = bd[r] * q[r + (int64_t)col * n];
+  reg_band_solve<W>(band, ld, w, n, b, T, colbuf);
+  if (col < b)
     for (int r = 0; r < n; ++r) X[r + (int64_t)col * n] = -T[(int64_t)r * b + col];
 }
 
@@ -702,11 +810,26 @@ hipError_t launch_build(const BuildBatch& bb, hipStream_t st) {
   for (int j = 0; j < bb.max_m; ++j) {
     hipLaunchKernelGGL(k_cgs2, grid, block, 0, st, bb, j);
     hipLaunchKernelGGL(k_normalize, grid, block, 0, st, bb, j);
-    // one lane per right-hand side, neighbours from an LDS window
-    const size_t wb = solve_window_bytes(bb);
-    if (j + 1 < bb.max_m)
-      hipLaunchKernelGGL(k_shift_solve, grid, dim3(std::min(NT, (bb.max_b + 63) / 64 * 64)), wb, st, bb, j,
-                         wb > 0 ? 1 : 0);
+    // one lane per right-hand side: the window in registers when one wave
+    // holds every right-hand side and the band fits a register window, else
+    // in LDS
+    if (j + 1 < bb.max_m) {
+      int regw = 0;
+      if (bb.max_b <= 64)
+        for (int W : REG_SOLVE_W)
+          if (!regw && bb.max_w <= W) regw = W;
+      if (regw == REG_SOLVE_W[0]) {
+        hipLaunchKernelGGL(k_shift_solve_reg<REG_SOLVE_W[0]>, grid, dim3(64), 0, st, bb, j);
+      } else if (regw == REG_SOLVE_W[1]) {
+        hipLaunchKernelGGL(k_shift_solve_reg<REG_SOLVE_W[1]>, grid, dim3(64), 0, st, bb, j);
+      } else if (regw == REG_SOLVE_W[2]) {
+        hipLaunchKernelGGL(k_shift_solve_reg<REG_SOLVE_W[2]>, grid, dim3(64), 0, st, bb, j);
+      } else {
+        const size_t wb = solve_window_bytes(bb);
+        hipLaunchKernelGGL(k_shift_solve, grid, dim3(std::min(NT, (bb.max_b + 63) / 64 * 64)), wb, st, bb, j,
+                           wb > 0 ? 1 : 0);
+      }
+    }
   }
   hipLaunchKernelGGL(k_project, grid, block, 0, st, bb);
   hipLaunchKernelGGL(k_lanczos, grid, block, 0, st, bb);
