@@ -609,33 +609,46 @@ __device__ inline void piece_body(const StepArgs& a, const OnlinePiece& pc, int 
   int64_t base[NC];
 #pragma unroll
   for (int e = 0; e < NC; ++e) base[e] = a.d_inc[pc.inc_off + e] * ns + s;
+  // Every load of the piece is issued before any value is used: rows
+  // j >= b_p read row b_p - 1 (in bounds) and are dropped afterwards, so the
+  // loads need no branches and share one memory round trip.
+  T f[MAXB][NC], yc[MAXB], yo[MAXB];
+#pragma unroll
+  for (int j = 0; j < MAXB; ++j) {
+    const int jr = min(j, bp - 1);
+#pragma unroll
+    for (int e = 0; e < NC; ++e) f[j][e] = phi[base[e] + (int64_t)jr * ns];
+    const int64_t q = (pc.dof_off + jr) * ns + s;
+    yc[j] = ycur[q];
+    yo[j] = yold[q];
+  }
   TA r[MAXB];
 #pragma unroll
   for (int j = 0; j < MAXB; ++j) {
     TA acc = 0;
-    if (j < bp) {
 #pragma unroll
-      for (int e = 0; e < NC; ++e) acc += (TA)phi[base[e] + (int64_t)j * ns];
-    }
-    r[j] = acc;
+    for (int e = 0; e < NC; ++e) acc += (TA)f[j][e];
+    r[j] = (j < bp) ? acc : (TA)0;
   }
   if (pc.src_off >= 0) {
     const T* src = reinterpret_cast<const T*>(a.d_src) + pc.src_off * ns + s;
     const TA wn = (TA)a.w[a.step];
+    T g[MAXB];
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) g[j] = src[(int64_t)min(j, bp - 1) * ns];
 #pragma unroll
     for (int j = 0; j < MAXB; ++j)
-      if (j < bp) r[j] += wn * (TA)src[(int64_t)j * ns];
+      if (j < bp) r[j] += wn * (TA)g[j];
   }
   const TA dt2 = (TA)a.dt2;
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    if (i < bp) {
-      TA acc = 0;
+    TA acc = 0;
 #pragma unroll
-      for (int j = 0; j < MAXB; ++j)
-        if (j < bp) acc += minv[i + j * bp] * r[j];
+    for (int j = 0; j < MAXB; ++j) acc += minv[min(i, bp - 1) + min(j, bp - 1) * bp] * r[j];
+    if (i < bp) {
       const int64_t q = (pc.dof_off + i) * ns + s;
-      yold[q] = (T)((TA)2 * (TA)ycur[q] - (TA)yold[q] + dt2 * acc);
+      yold[q] = (T)((TA)2 * (TA)yc[i] - (TA)yo[i] + dt2 * acc);
     }
   }
 }
