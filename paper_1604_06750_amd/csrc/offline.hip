@@ -803,9 +803,75 @@ __global__ __launch_bounds__(NT) void k_sfraction(BuildBatch bb) {
   if (threadIdx.x == 0 && s_nf) c.status = ST_NONFINITE;
 }
 
+// The same factorisation with the active part of the band in LDS: the
+// w + 1 columns j .. j + w that step j reads or updates sit in a ring of
+// slots (column c in slot c mod (w + 1), band offsets contiguous), so the
+// rank-1 update is LDS arithmetic (one wave per updated column, lanes along
+// it) and HBM sees each column once in each direction: column j leaves for
+// the factor after its step and column j + w + 1, fetched into registers
+// during the step, takes its slot. Every thread computes the pivot itself,
+// so a step needs three barriers. Dynamic LDS: (w + 1)^2 doubles.
+__global__ __launch_bounds__(NT) void k_band_chol_win(BuildBatch bb) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  const int n = c.n, w = c.w, W1 = w + 1, ld = w + 1;
+  double* band = bb.d_work + c.band_off;
+  const int32_t* rp = bb.d_rowptr + c.rp_off;
+  const int32_t* col = bb.d_col + c.csr_off;
+  const double* a = bb.d_a + c.csr_off;
+  const double* bd = bb.d_bdiag + c.b_off;
+  extern __shared__ double win[];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  for (int64_t idx = tid; idx < (int64_t)n * ld; idx += NT) band[idx] = 0.0;
+  __syncthreads();
+  for (int r = tid; r < n; r += NT) {
+    for (int k = rp[r]; k < rp[r + 1]; ++k) {
+      const int cc = col[k];
+      if (r >= cc) band[(int64_t)cc * ld + (r - cc)] = -(a[k] + (r == cc ? bb.shift * bd[r] : 0.0));
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < min(W1, n) * W1; idx += NT) win[idx] = band[idx];
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double* cj = win + (j % W1) * W1;
+    const bool refill = j + W1 < n;
+    const double pre = (refill && tid < W1) ? band[(int64_t)(j + W1) * ld + tid] : 0.0;
+    const double d = cj[0];
+    const bool ok = d > 0.0 && isfinite(d);
+    const double piv = ok ? sqrt(d) : 1.0;
+    const double inv = 1.0 / piv;
+    const int lim = min(w, n - 1 - j);
+    if (tid >= 1 && tid <= lim) cj[tid] *= inv;
+    if (tid == 0 && !ok) s_bad = 1;
+    __syncthreads();
+    for (int d1 = 1 + wv; d1 <= lim; d1 += NT / 64) {
+      double* cd = win + ((j + d1) % W1) * W1;
+      const double v1 = cj[d1];
+      for (int e = lane; e <= lim - d1; e += 64) cd[e] -= cj[d1 + e] * v1;
+    }
+    __syncthreads();
+    if (tid < W1) {
+      band[(int64_t)j * ld + tid] = tid == 0 ? piv : cj[tid];
+      if (refill) cj[tid] = pre;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && s_bad) c.status = ST_NOTNSD;
+}
+
+// LDS bytes of the windowed factorisation for a batch (0: use k_band_chol)
+inline size_t chol_window_bytes(const BuildBatch& bb) {
+  const size_t bytes = (size_t)(bb.max_w + 1) * (bb.max_w + 1) * sizeof(double);
+  return (bb.max_w + 1 <= NT && bytes <= 64 * 1024) ? bytes : 0;
+}
+
 hipError_t launch_build(const BuildBatch& bb, hipStream_t st) {
   const dim3 grid(bb.ncell), block(NT);
-  hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bb);
+  const size_t cw = chol_window_bytes(bb);
+  if (cw) hipLaunchKernelGGL(k_band_chol_win, grid, block, cw, st, bb);
+  else hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bb);
   hipLaunchKernelGGL(k_krylov_start, grid, block, 0, st, bb);
   for (int j = 0; j < bb.max_m; ++j) {
     hipLaunchKernelGGL(k_cgs2, grid, block, 0, st, bb, j);
@@ -1324,7 +1390,9 @@ hipError_t launch_learned_check(const BuildBatch& bb, const float* y, int P, con
   for (int j = 0; j < nz; ++j) {
     BuildBatch bz = bb;
     bz.shift = z[j];
-    hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bz);
+    const size_t cw = chol_window_bytes(bz);
+    if (cw) hipLaunchKernelGGL(k_band_chol_win, grid, block, cw, st, bz);
+    else hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bz);
     const size_t wb = solve_window_bytes(bz);
     hipLaunchKernelGGL(k_tf_exact, grid, block, wb, st, bz, wb > 0 ? 1 : 0);
     hipLaunchKernelGGL(k_tf_rom, grid, block, 0, st, bz, z[j], mis);
