@@ -46,7 +46,9 @@ enum {
 
 // C = alpha op(A) op(B) + beta C, M x N, inner K. op(A)(i,k) = TA ? A[k+i*lda]
 // : A[i+k*lda]; op(B)(k,j) = TB ? B[j+k*ldb] : B[k+j*ldb]. 64x64 output tiles,
-// 4x4 per thread, K staged through LDS in chunks of 16. C must not alias A, B.
+// 4x4 per thread, K staged through LDS in chunks of 16; the next chunk's
+// HBM loads are issued into registers before the current chunk's products,
+// so their latency overlaps the arithmetic. C must not alias A, B.
 template <bool TA, bool TB>
 __device__ void wg_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
                         const double* __restrict__ B, int ldb, double beta, double* C, int ldc) {
@@ -54,39 +56,48 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* __restr
   __shared__ double Bs[16][65];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
+  // element q of this thread's share of a chunk: A(ii, kk) and B(kb, jj)
+  int ii[4], kk[4], jj[4], kb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + NT * q;
+    if (!TA) { ii[q] = e & 63; kk[q] = e >> 6; } else { kk[q] = e & 15; ii[q] = e >> 4; }
+    if (!TB) { kb[q] = e & 15; jj[q] = e >> 4; } else { jj[q] = e & 63; kb[q] = e >> 6; }
+  }
   for (int i0 = 0; i0 < M; i0 += 64) {
     for (int j0 = 0; j0 < N; j0 += 64) {
+      double pa[4], pb[4];
+      auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + ii[q], k = k0 + kk[q];
+          pa[q] = (i < M && k < K) ? (TA ? A[k + (int64_t)i * lda] : A[i + (int64_t)k * lda]) : 0.0;
+          const int j = j0 + jj[q], k2 = k0 + kb[q];
+          pb[q] = (j < N && k2 < K) ? (TB ? B[j + (int64_t)k2 * ldb] : B[k2 + (int64_t)j * ldb]) : 0.0;
+        }
+      };
       double acc[4][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+      gload(0);
       for (int k0 = 0; k0 < K; k0 += 16) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int e = tid + NT * q;
-          int ii, kk;
-          if (!TA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
-          const int i = i0 + ii, k = k0 + kk;
-          double v = 0.0;
-          if (i < M && k < K) v = TA ? A[k + (int64_t)i * lda] : A[i + (int64_t)k * lda];
-          As[kk][ii] = v;
-          int jj, kb;
-          if (!TB) { kb = e & 15; jj = e >> 4; } else { jj = e & 63; kb = e >> 6; }
-          const int j = j0 + jj, k2 = k0 + kb;
-          double u = 0.0;
-          if (j < N && k2 < K) u = TB ? B[j + (int64_t)k2 * ldb] : B[k2 + (int64_t)j * ldb];
-          Bs[kb][jj] = u;
+          As[kk[q]][ii[q]] = pa[q];
+          Bs[kb[q]][jj[q]] = pb[q];
         }
         __syncthreads();
+        if (k0 + 16 < K) gload(k0 + 16);
 #pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
+        for (int k = 0; k < 16; ++k) {
           double a[4], b[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) a[r] = As[kk][tx + 16 * r];
+          for (int r = 0; r < 4; ++r) a[r] = As[k][tx + 16 * r];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) b[c] = Bs[kk][ty + 16 * c];
+          for (int c = 0; c < 4; ++c) b[c] = Bs[k][ty + 16 * c];
 #pragma unroll
           for (int r = 0; r < 4; ++r)
 #pragma unroll
