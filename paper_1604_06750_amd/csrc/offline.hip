@@ -49,11 +49,15 @@ enum {
 // 4x4 per thread, K staged through LDS in chunks of 16; the next chunk's
 // HBM loads are issued into registers before the current chunk's products,
 // so their latency overlaps the arithmetic. C must not alias A, B.
+// K-chunk tiles of wg_gemm, one pair shared by all its instantiations
+__shared__ double g_gemm_as[16][65];
+__shared__ double g_gemm_bs[16][65];
+
 template <bool TA, bool TB>
 __device__ void wg_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
                         const double* __restrict__ B, int ldb, double beta, double* C, int ldc) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  auto& As = g_gemm_as;
+  auto& Bs = g_gemm_bs;
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   // element q of this thread's share of a chunk: A(ii, kk) and B(kb, jj)
@@ -124,7 +128,7 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* __restr
 // In-place lower Cholesky of an n x n SPD matrix (global memory). Returns the
 // ratio min/max of the pivots' square roots, or -1 if a pivot is not
 // positive and finite.
-__device__ double wg_potrf(int n, double* A, int lda) {
+__device__ double wg_potrf_global(int n, double* A, int lda) {
   __shared__ double s_piv;
   __shared__ double s_min, s_max;
   __shared__ int s_bad;
@@ -160,7 +164,7 @@ __device__ double wg_potrf(int n, double* A, int lda) {
 }
 
 // X (rows x n) <- X L^{-T} for lower L (n x n): solves q L^T = x row-wise.
-__device__ void wg_trsm_right_lt(int rows, int n, const double* L, int ldl, double* X, int ldx) {
+__device__ void wg_trsm_right_lt_global(int rows, int n, const double* L, int ldl, double* X, int ldx) {
   for (int r = threadIdx.x; r < rows; r += NT) {
     for (int j = 0; j < n; ++j) {
       double s = X[r + (int64_t)j * ldx];
@@ -169,6 +173,100 @@ __device__ void wg_trsm_right_lt(int rows, int n, const double* L, int ldl, doub
     }
   }
   __syncthreads();
+}
+
+// Small factors (n <= SMALL_N) are factored and applied from LDS. One
+// file-scope matrix buffer is shared by both helpers, so a kernel that uses
+// them holds it once.
+constexpr int SMALL_N = 64;
+constexpr int SMALL_LD = SMALL_N + 1;
+__shared__ double g_small[SMALL_N * SMALL_LD];
+
+// wg_potrf for n <= SMALL_N: A copied to LDS (column-major), the same
+// right-looking steps with one wave per updated column, the factor written
+// back. Same return value.
+__device__ double wg_potrf_lds(int n, double* A, int lda) {
+  __shared__ double s_min, s_max;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  double* S = g_small;
+  for (int idx = tid; idx < n * n; idx += NT) {
+    const int i = idx % n, k = idx / n;
+    S[i + k * SMALL_LD] = A[i + (int64_t)k * lda];
+  }
+  if (tid == 0) { s_bad = 0; s_min = 1e300; s_max = 0.0; }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double d = S[j + j * SMALL_LD];
+    const bool ok = d > 0.0 && isfinite(d);
+    const double piv = ok ? sqrt(d) : 1.0;
+    const double inv = 1.0 / piv;
+    if (tid > j && tid < n) S[tid + j * SMALL_LD] *= inv;
+    if (tid == 0) {
+      if (!ok) s_bad = 1;
+      else { s_min = fmin(s_min, piv); s_max = fmax(s_max, piv); }
+    }
+    __syncthreads();
+    for (int k = j + 1 + wv; k < n; k += NT / 64) {
+      const double lk = S[k + j * SMALL_LD];
+      for (int i = k + lane; i < n; i += 64) S[i + k * SMALL_LD] -= S[i + j * SMALL_LD] * lk;
+    }
+    if (tid == 0) S[j + j * SMALL_LD] = piv;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n * n; idx += NT) {
+    const int i = idx % n, k = idx / n;
+    A[i + (int64_t)k * lda] = S[i + k * SMALL_LD];
+  }
+  const double r = s_bad ? -1.0 : s_min / s_max;
+  __syncthreads();
+  return r;
+}
+
+// wg_trsm_right_lt for n <= SMALL_N: L staged in LDS (column-major), each
+// row of X solved in blocks of 16 unknowns held in registers; earlier
+// blocks' solved values are read back once per block.
+__device__ void wg_trsm_right_lt_lds(int rows, int n, const double* L, int ldl, double* X, int ldx) {
+  constexpr int NBK = 16;
+  double* S = g_small;
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+    const int j = idx % n, l = idx / n;
+    S[j + l * SMALL_LD] = (l <= j) ? L[j + (int64_t)l * ldl] : 0.0;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < rows; r += NT) {
+    for (int j0 = 0; j0 < n; j0 += NBK) {
+      double x[NBK];
+#pragma unroll
+      for (int q = 0; q < NBK; ++q) x[q] = (j0 + q < n) ? X[r + (int64_t)(j0 + q) * ldx] : 0.0;
+      for (int l = 0; l < j0; ++l) {
+        const double xl = X[r + (int64_t)l * ldx];
+#pragma unroll
+        for (int q = 0; q < NBK; ++q) x[q] -= xl * S[j0 + q + l * SMALL_LD];
+      }
+#pragma unroll
+      for (int q = 0; q < NBK; ++q) {
+        if (j0 + q < n) {
+          double s = x[q];
+#pragma unroll
+          for (int p = 0; p < q; ++p) s -= x[p] * S[j0 + q + (j0 + p) * SMALL_LD];
+          x[q] = s / S[j0 + q + (j0 + q) * SMALL_LD];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NBK; ++q)
+        if (j0 + q < n) X[r + (int64_t)(j0 + q) * ldx] = x[q];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ double wg_potrf(int n, double* A, int lda) {
+  return n <= SMALL_N ? wg_potrf_lds(n, A, lda) : wg_potrf_global(n, A, lda);
+}
+__device__ void wg_trsm_right_lt(int rows, int n, const double* L, int ldl, double* X, int ldx) {
+  if (n <= SMALL_N) wg_trsm_right_lt_lds(rows, n, L, ldl, X, ldx);
+  else wg_trsm_right_lt_global(rows, n, L, ldl, X, ldx);
 }
 
 // Ainv = A^{-1} (n x n) by Gauss-Jordan with partial pivoting; W is n x n
