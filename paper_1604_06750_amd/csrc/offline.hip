@@ -283,16 +283,27 @@ __device__ int wg_inverse(int n, const double* A, int lda, double* Ainv, int ldi
   }
   if (tid == 0) s_ok = 1;
   __syncthreads();
+  const int wv = tid >> 6, lane = tid & 63;
   for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
+    if (wv == 0) {
+      // pivot: the largest magnitude in column j at or below row j, the
+      // lowest row among equal magnitudes (one wave, shuffle reduction)
       int p = j;
-      double best = fabs(W[j + (int64_t)j * n]);
-      for (int i = j + 1; i < n; ++i) {
+      double best = -1.0;
+      for (int i = j + lane; i < n; i += 64) {
         const double v = fabs(W[i + (int64_t)j * n]);
         if (v > best) { best = v; p = i; }
       }
-      if (!(best > 0.0)) s_ok = 0;
-      s_p = p;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int op = __shfl_xor(p, o);
+        if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+      }
+      if (lane == 0) {
+        if (!(best > 0.0)) s_ok = 0;
+        s_p = p;
+      }
     }
     __syncthreads();
     const int p = s_p;
@@ -312,12 +323,16 @@ __device__ int wg_inverse(int n, const double* A, int lda, double* Ainv, int ldi
     __syncthreads();
     for (int i = tid; i < n; i += NT) fac[i] = (i == j) ? 0.0 : W[i + (int64_t)j * n];
     __syncthreads();
-    for (int idx = tid; idx < n * n; idx += NT) {
-      const int i = idx % n, c = idx / n;
-      const double f = fac[i];
-      if (f != 0.0) {
-        W[i + (int64_t)c * n] -= f * W[j + (int64_t)c * n];
-        Ainv[i + (int64_t)c * ldi] -= f * Ainv[j + (int64_t)c * ldi];
+    // eliminate column j from every other row: one wave per column c,
+    // lanes along the rows
+    for (int c = wv; c < n; c += NT / 64) {
+      const double wj = W[j + (int64_t)c * n], aj = Ainv[j + (int64_t)c * ldi];
+      for (int i = lane; i < n; i += 64) {
+        const double f = fac[i];
+        if (f != 0.0) {
+          W[i + (int64_t)c * n] -= f * wj;
+          Ainv[i + (int64_t)c * ldi] -= f * aj;
+        }
       }
     }
     __syncthreads();
