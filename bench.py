@@ -320,7 +320,8 @@ def main():
         "speedup_job_vs_fine": round(value / fine_ssps, 3),
         "speedup_online_vs_fine": round(online_ssps / fine_ssps, 3),
         "kernel_avg_ms": {"cell_phase": round(avg_ms, 4), "piece_phase": round(piece_ms / max(piece_n, 1), 4),
-                          "receivers": round(rec_ms / max(rec_n, 1), 4),
+                          # receivers that each read one piece are computed by the piece phase
+                          "receivers": round(rec_ms / rec_n, 4) if rec_n else "in piece phase",
                           "fine_step": round(fine_kms / max(fine_kn, 1), 4)},
     }
     S.sfrom_destroy(h)

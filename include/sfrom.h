@@ -233,7 +233,9 @@ int sfrom_set_cell_variant(sfrom_t* h, int32_t variant);
  * in N (steps 0, N, 2N, ... of each run; an event pair costs a few
  * microseconds of stream time, so sampling keeps the measurement out of the
  * run's own time); negative values return SFROM_EINVAL. Kernel ids: 0 on-line
- * cell phase, 1 on-line piece phase, 2 receivers, 3 fine-grid step.
+ * cell phase, 1 on-line piece phase, 2 receivers (no launches when every
+ * receiver reads a single piece: the piece phase then writes the traces),
+ * 3 fine-grid step.
  * sfrom_profile_read synchronises the stream, returns the summed kernel time
  * and the number of timed launches since the last read, and clears them. */
 int sfrom_profile(sfrom_t* h, int32_t enable);

@@ -102,6 +102,8 @@ void free_rom(sfrom_t* h) {
   dfree(h->d_ocells); dfree(h->d_opieces); dfree(h->d_gather); dfree(h->d_inc);
   dfree(h->d_inc_cell); dfree(h->d_inc_col);
   dfree(h->d_src); dfree(h->d_rptr); dfree(h->d_rrow); dfree(h->d_rval);
+  dfree(h->d_prec_ptr); dfree(h->d_prec_list);
+  h->rec_fused = false;
   dfree(h->d_y[0]); dfree(h->d_y[1]); dfree(h->d_h[0]); dfree(h->d_h[1]); dfree(h->d_phi); dfree(h->d_flag);
   for (auto& bk : h->buckets) dfree(bk.d_list);
   h->buckets.clear();
@@ -847,6 +849,21 @@ void prepare_online(sfrom_t* h) {
     h->d_rptr = dupload(h, rptr);
     h->d_rrow = dupload(h, rrow);
     h->d_rval = dupload(h, rval);
+    // receivers that each read exactly one piece are computed by the piece
+    // phase (per-piece receiver lists); otherwise the receivers kernel runs
+    dfree(h->d_prec_ptr); dfree(h->d_prec_list);
+    h->rec_fused = h->rec.count > 0;
+    for (int r = 0; r < h->rec.count && h->rec_fused; ++r) h->rec_fused = h->rec.rptr[r + 1] - h->rec.rptr[r] == 1;
+    if (h->rec_fused) {
+      const int np = (int)h->pieces.size();
+      std::vector<int32_t> pptr(np + 1, 0), plist(h->rec.count);
+      for (int r = 0; r < h->rec.count; ++r) pptr[h->rec.rpiece[h->rec.rptr[r]] + 1]++;
+      for (int p = 0; p < np; ++p) pptr[p + 1] += pptr[p];
+      std::vector<int32_t> fill(pptr.begin(), pptr.end() - 1);
+      for (int r = 0; r < h->rec.count; ++r) plist[fill[h->rec.rpiece[h->rec.rptr[r]]]++] = r;
+      h->d_prec_ptr = dupload(h, pptr);
+      h->d_prec_list = dupload(h, plist);
+    }
     h->rec_dirty = false;
   }
   if (h->state_ns != ns) {
@@ -963,6 +980,8 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   a.d_blocks = h->d_blocks; a.d_minv = h->d_minv; a.d_src = h->d_src;
   a.phi = h->d_phi; a.w = d_w;
   a.d_rptr = h->d_rptr; a.d_rrow = h->d_rrow; a.d_rval = h->d_rval;
+  a.d_prec_ptr = h->rec_fused ? h->d_prec_ptr : nullptr;
+  a.d_prec_list = h->rec_fused ? h->d_prec_list : nullptr;
   a.traces = d_tr;
   a.d_cell_list = nullptr;
   a.nlist = a.ncell;
@@ -1033,7 +1052,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
       const bool sample = s % h->prof_every == 0;
       timed(h, 0, sample, [&] { return cell_phase(a, ls); });
       timed(h, 1, sample, [&] { return launch_piece_phase(a, ls); });
-      timed(h, 2, sample, [&] { return launch_receivers(a, ls); });
+      if (!h->rec_fused) timed(h, 2, sample, [&] { return launch_receivers(a, ls); });
       cur = 1 - cur;
       if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
     }

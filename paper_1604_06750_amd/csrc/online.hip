@@ -653,6 +653,21 @@ __device__ inline void piece_body(const StepArgs& a, const OnlinePiece& pc, int 
   }
 }
 
+// Traces of the receivers that read piece p, for source s, from the piece's
+// new state that this thread has just stored (same sum order as
+// k_receivers, so the traces are the same).
+template <typename T, typename TA>
+__device__ inline void piece_receivers(const StepArgs& a, int p, int s) {
+  const T* y = reinterpret_cast<const T*>(a.y_old);   // holds level n+1 now
+  const int e0 = a.d_prec_ptr[p], e1 = a.d_prec_ptr[p + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int r = a.d_prec_list[e];
+    TA acc = 0;
+    for (int64_t k = a.d_rptr[r]; k < a.d_rptr[r + 1]; ++k) acc += (TA)a.d_rval[k] * (TA)y[a.d_rrow[k] * a.ns + s];
+    reinterpret_cast<T*>(a.traces)[(a.trace_step * a.nrec + r) * a.ns + s] = (T)acc;
+  }
+}
+
 template <typename T, typename TA, int MAXB, bool UNI>
 __global__ __launch_bounds__(256) void k_piece_phase(StepArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -697,6 +712,7 @@ __global__ __launch_bounds__(256) void k_piece_phase(StepArgs a) {
       }
     }
   }
+  if (a.d_prec_ptr) piece_receivers<T, TA>(a, p, s);
 }
 
 // Receivers: one thread per (receiver, source) over the new piece state.

@@ -182,6 +182,11 @@ struct StepArgs {
   const double* d_rval;
   void* traces;                  // n_steps x n_rec x ns
   int64_t trace_step;            // which slice to write
+  // receivers computed by the piece phase (each receiver reads one piece):
+  // receivers d_prec_list[d_prec_ptr[p] .. d_prec_ptr[p+1]) belong to piece
+  // p; null when the receivers kernel runs instead
+  const int32_t* d_prec_ptr;
+  const int32_t* d_prec_list;
   int32_t cell_variant;          // kernel variant of the cell phase (autotuned)
   // cell phase over a subset: cells d_cell_list[0..nlist) (all cells, in
   // order, when d_cell_list is null and nlist == ncell)
@@ -293,6 +298,9 @@ struct sfrom {
 
   // device: on-line structures
   void* d_blocks = nullptr;
+  int32_t* d_prec_ptr = nullptr;   // per-piece receiver lists (receivers fused into the piece phase)
+  int32_t* d_prec_list = nullptr;
+  bool rec_fused = false;
   void* d_minv = nullptr;
   double* d_rom64 = nullptr;
   int64_t* d_rom64_off = nullptr;
