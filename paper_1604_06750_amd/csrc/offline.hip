@@ -125,6 +125,49 @@ __device__ void wg_gemm(int M, int N, int K, double alpha, const double* __restr
   __syncthreads();
 }
 
+// Y = A X for a cell's CSR operator A (n x n, local row starts) and n x ncol
+// column-major X, Y (leading dimension n). One thread per row: a row of at
+// most SPMM_NZ nonzeros is held in registers while the columns are swept
+// (padding entries add exactly zero), longer rows use the plain loop.
+constexpr int SPMM_NZ = 8;
+__device__ void wg_spmm_csr(int n, int ncol, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ a, const double* __restrict__ X, double* __restrict__ Y) {
+  for (int r = threadIdx.x; r < n; r += NT) {
+    const int k0 = rp[r], nk = rp[r + 1] - k0;
+    if (nk <= SPMM_NZ) {
+      int ci[SPMM_NZ];
+      double av[SPMM_NZ];
+#pragma unroll
+      for (int k = 0; k < SPMM_NZ; ++k) {
+        ci[k] = k < nk ? col[k0 + k] : r;
+        av[k] = k < nk ? a[k0 + k] : 0.0;
+      }
+      for (int cc = 0; cc < ncol; ++cc) {
+        const double* Xc = X + (int64_t)cc * n;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < SPMM_NZ; ++k) s += av[k] * Xc[ci[k]];
+        Y[r + (int64_t)cc * n] = s;
+      }
+    } else {
+      for (int cc = 0; cc < ncol; ++cc) {
+        double s = 0.0;
+        for (int k = k0; k < k0 + nk; ++k) s += a[k] * X[col[k] + (int64_t)cc * n];
+        Y[r + (int64_t)cc * n] = s;
+      }
+    }
+  }
+}
+
+// Y = diag(d) X for n x ncol column-major X, Y (leading dimension n).
+__device__ void wg_scale_rows(int n, int ncol, const double* __restrict__ d, const double* __restrict__ X,
+                              double* __restrict__ Y) {
+  for (int r = threadIdx.x; r < n; r += NT) {
+    const double dr = d[r];
+    for (int cc = 0; cc < ncol; ++cc) Y[r + (int64_t)cc * n] = dr * X[r + (int64_t)cc * n];
+  }
+}
+
 // In-place lower Cholesky of an n x n SPD matrix (global memory). Returns the
 // ratio min/max of the pivots' square roots, or -1 if a pivot is not
 // positive and finite.
@@ -444,7 +487,7 @@ __global__ __launch_bounds__(NT) void k_cgs2(BuildBatch bb, int j) {
   double* coef = bb.d_work + c.s_off;           // jb x b scratch
   const double* bd = bb.d_bdiag + c.b_off;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) BX[idx] = bd[idx % n] * X[idx];
+    wg_scale_rows(n, b, bd, X, BX);
     __syncthreads();
     wg_gemm<true, false>(jb, b, n, 1.0, V, n, BX, n, 0.0, coef, jb);
     wg_gemm<false, false>(n, b, jb, -1.0, V, n, coef, jb, 1.0, X, n);
@@ -461,7 +504,7 @@ __global__ __launch_bounds__(NT) void k_normalize(BuildBatch bb, int j) {
   double* BX = bb.d_work + c.av_off;
   double* gram = bb.d_work + c.s_off;
   const double* bd = bb.d_bdiag + c.b_off;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)n * b; idx += NT) BX[idx] = bd[idx % n] * X[idx];
+  wg_scale_rows(n, b, bd, X, BX);
   __syncthreads();
   wg_gemm<true, false>(b, b, n, 1.0, X, n, BX, n, 0.0, gram, b);
   wg_symmetrize(b, gram, b);
@@ -787,13 +830,7 @@ __global__ __launch_bounds__(NT) void k_project(BuildBatch bb) {
   const int32_t* rp = bb.d_rowptr + c.rp_off;
   const int32_t* col = bb.d_col + c.csr_off;
   const double* a = bb.d_a + c.csr_off;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)n * mb; idx += NT) {
-    const int r = idx % n;
-    const int64_t cc = idx / n;
-    double s = 0.0;
-    for (int k = rp[r]; k < rp[r + 1]; ++k) s += a[k] * V[col[k] + cc * n];
-    AV[idx] = s;
-  }
+  wg_spmm_csr(n, mb, rp, col, a, V, AV);
   __syncthreads();
   wg_gemm<true, false>(mb, mb, n, 1.0, V, n, AV, n, 0.0, Am, mb);
   wg_symmetrize(mb, Am, mb);
