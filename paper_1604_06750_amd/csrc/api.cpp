@@ -94,10 +94,16 @@ T* dupload(sfrom_t* h, const std::vector<T>& v) {
 size_t prec_bytes(int prec) { return prec == SFROM_F64 ? 8 : 4; }        // state / masses
 size_t block_bytes(int prec) { return prec == SFROM_F64 ? 8 : (prec == SFROM_F32 ? 4 : 2); }
 
-void free_rom(sfrom_t* h) {
-  if (h->device < 0) { h->built = false; return; }
+// Forgets the captured run: its kernels hold device pointers that the
+// caller's next set-up may free.
+void drop_graph(sfrom_t* h) {
   if (h->graph_exec) { hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
   h->graph_key.clear();
+}
+
+void free_rom(sfrom_t* h) {
+  if (h->device < 0) { h->built = false; return; }
+  drop_graph(h);
   dfree(h->d_blocks); dfree(h->d_minv); dfree(h->d_rom64); dfree(h->d_rom64_off);
   dfree(h->d_ocells); dfree(h->d_opieces); dfree(h->d_gather); dfree(h->d_inc);
   dfree(h->d_inc_cell); dfree(h->d_inc_col);
@@ -808,6 +814,7 @@ void prepare_online(sfrom_t* h) {
   REQUIRE(ns > 0, SFROM_ESTATE, "no sources: call sfrom_set_sources");
   const size_t eb = prec_bytes(h->prec);
   if (h->src_dirty) {
+    drop_graph(h);   // the captured run reads the source arrays replaced here
     // dense reduced sources for pieces that carry a source
     std::vector<int64_t> srow(h->pieces.size(), -1);
     int64_t rows = 0;
@@ -833,6 +840,7 @@ void prepare_online(sfrom_t* h) {
     h->src_dirty = false;
   }
   if (h->rec_dirty) {
+    drop_graph(h);   // and the receiver arrays replaced here
     std::vector<int64_t> rptr(1, 0), rrow;
     std::vector<double> rval;
     for (int r = 0; r < h->rec.count; ++r) {

@@ -448,6 +448,40 @@ def test_uneven_cells_layered_medium(dev):
     assert e32 <= 1e-4
 
 
+def test_graph_is_recaptured_after_new_receivers(dev):
+    """With graph replay on, replacing the receivers by the same number of
+    different columns (here: their order reversed) takes effect at the next
+    run: the captured run is dropped, not replayed with the old arrays."""
+    S, P = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3, n_steps=60)
+    run = pipeline.setup(wl)
+    w = torch.tensor(run.w, dtype=torch.float64, device="cuda")
+    h = _handle(S)
+    try:
+        P.setup(h, wl)
+        S.sfrom_build(h, wl.m, wl.shift, S.SFROM_F32)
+        S.sfrom_set_graph(h, True)
+        info = S.sfrom_get_info(h)
+        nr = info["n_receivers"]
+        tr = torch.zeros((60, nr, info["n_sources"]), dtype=torch.float32, device="cuda")
+        S.sfrom_run(h, 60, run.dt, w, tr)
+        torch.cuda.synchronize()
+        t1 = tr.cpu().numpy().copy()
+        cp, rw, vl = S.sfrom_point_columns(h, P.node_ids(wl.nvox, wl.receivers), P.max_piece_nodes(wl))
+        cols = [(rw[cp[r]:cp[r + 1]], vl[cp[r]:cp[r + 1]]) for r in range(nr)][::-1]
+        cp2 = np.concatenate([[0], np.cumsum([len(c[0]) for c in cols])]).astype(np.int64)
+        S.sfrom_set_receivers(h, cp2, np.concatenate([c[0] for c in cols]), np.concatenate([c[1] for c in cols]),
+                              project=False)
+        S.sfrom_reset(h)
+        S.sfrom_run(h, 60, run.dt, w, tr)
+        torch.cuda.synchronize()
+        t2 = tr.cpu().numpy().copy()
+    finally:
+        S.sfrom_destroy(h)
+    assert np.abs(t1).max() > 0
+    assert np.array_equal(t2, t1[:, ::-1, :])
+
+
 def test_graph_replay_matches_eager(dev):
     """sfrom_run captured into a hipGraph and replayed: every replay, with
     eager work and synchronisation in between, equals the eager run bitwise."""
