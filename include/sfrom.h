@@ -135,8 +135,12 @@ typedef struct {
  * the S-fraction change of variables (eq. GammaTrans), piece masses
  * M_p = sum_{i owns p} [(Ghat_i^1)^{-1}]_pp (eq. bdrytstep) and packing in
  * the on-line precision. On failure no ROM is kept and the message names the
- * first failing cell. Errors: ESTATE, ESPLIT, ENOTNSD, EBREAKDOWN, ENOTSPD,
- * ENOMEM, EDEVICE. */
+ * first failing cell. The first build after the partition is defined copies
+ * the build's inputs (cell operators, skeleton rows of each W_i, piece bases)
+ * to device memory that the handle keeps for later builds until the pencil,
+ * a cell or a piece changes or the handle is destroyed (about 300 MB for
+ * 4096 cells of 8^3 voxels). Errors: ESTATE, ESPLIT, ENOTNSD, EBREAKDOWN,
+ * ENOTSPD, ENOMEM, EDEVICE. */
 int sfrom_build(sfrom_t* h, const sfrom_build_opts* opts);
 
 /* Replace cell `cell`'s S-fraction by m blocks Ghat^k and G^k (each b x b
