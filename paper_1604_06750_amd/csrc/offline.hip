@@ -839,7 +839,9 @@ __global__ __launch_bounds__(NT) void k_project(BuildBatch bb) {
 // K4: block Lanczos on (A^m, I) from S^m = E_1 R_1.
 // Work layout in the av region (free after K3): AQ (mb x b), Z (mb x b),
 // coef (mb x b), gram (b x b); alphas/betas at s_off: alpha_k then beta_k.
-__global__ __launch_bounds__(NT) void k_lanczos(BuildBatch bb) {
+// 3 waves per SIMD: a few spilled registers buy a third resident workgroup
+// per CU for this chain of small dependent products
+__global__ __launch_bounds__(NT, 3) void k_lanczos(BuildBatch bb) {
   BuildCell& c = bb.d_cells[blockIdx.x];
   if (cell_failed(c)) return;
   const int b = c.b, m = c.m, mb = m * b;
@@ -902,7 +904,9 @@ __global__ __launch_bounds__(NT) void k_lanczos(BuildBatch bb) {
 
 // K5: S-fraction blocks from (alpha_k, beta_k) (eq. GammaTrans, corrected).
 // Output at out_off: Ghat^1..Ghat^m then G^1..G^m.
-__global__ __launch_bounds__(NT) void k_sfraction(BuildBatch bb) {
+// 3 waves per SIMD: a few spilled registers buy a third resident workgroup
+// per CU for this chain of small dependent products
+__global__ __launch_bounds__(NT, 3) void k_sfraction(BuildBatch bb) {
   BuildCell& c = bb.d_cells[blockIdx.x];
   if (cell_failed(c)) return;
   const int b = c.b, m = c.m;
