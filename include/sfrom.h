@@ -182,7 +182,8 @@ int sfrom_point_columns(sfrom_t* h, int32_t count, const int64_t* node, int64_t*
  * On-line stage (Alg. alg1red stage 2) and the fine-grid comparator
  * ------------------------------------------------------------------------ */
 
-/* Zero the ROM state (eq. initial: U = 0 for t <= 0). */
+/* Zero the ROM state (eq. initial: U = 0 for t <= 0) in place and the step
+ * counter. Errors: ESTATE (no ROM). */
 int sfrom_reset(sfrom_t* h);
 /* Advance the ROM n_steps leapfrog steps of size dt from its current state:
  * Y^{n+1} = 2Y^n - Y^{n-1} + dt^2 D^{-1} (L Y^n + w^n F), piece dofs by
@@ -196,13 +197,37 @@ int sfrom_reset(sfrom_t* h);
  * wavelet samples for these steps, host memory unless w_on_device.
  * traces receives n_steps x n_r x n_s values (source fastest) of the
  * receiver output at levels n+1, as double for F64 and float otherwise,
- * host memory unless traces_on_device. dt must satisfy the stability limit
- * of the ROM when known (ECFL). After the steps the state is checked: a
+ * host memory unless traces_on_device. dt must satisfy the leapfrog
+ * stability limit dt^2 lambda_max < 4 of the ROM pencil (Remark MFEM),
+ * else ECFL and nothing is stepped: the limit is tested first against a
+ * bound valid for built blocks (the largest Gershgorin bound of the cells'
+ * pencils B_i^{-1}(-A_i), which bounds every cell's Galerkin-projected
+ * pencil and hence the assembled ROM), and only when that test fails, or
+ * some blocks were imported, against the ROM's own lambda_max (computed
+ * once per ROM on the host, as sfrom_rom_lambda_max). After the steps the state is checked: a
  * NaN or infinity (the scheme diverged) returns ENONFINITE; the traces are
  * written either way. Errors: ESTATE, EINVAL, ECFL, EDEVICE,
  * ENONFINITE. */
 int sfrom_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int32_t w_on_device,
               void* traces, int32_t traces_on_device);
+
+/* Checkpoint of the on-line stage (the ROM is built "just once" for all
+ * sources and time windows, Sec. 4.2 and Alg. alg1red stage 1): writes to
+ * the file `path` a versioned binary record of the partition's cell and
+ * piece sizes, the piece nodes and bases, the FP64 S-fraction of every
+ * cell, the on-line blocks and inverse piece masses in the on-line
+ * precision, and, when a run has allocated it, both levels of the ROM
+ * state with the step counter. Errors: ESTATE (no ROM), EINVAL (file). */
+int sfrom_save(sfrom_t* h, const char* path);
+/* Restores a checkpoint into a handle whose problem (pencil, cells, pieces)
+ * is the one saved: cell and piece sizes, piece nodes and bases must match
+ * exactly (EINVAL otherwise, and the current ROM is kept). Replaces any ROM
+ * of the handle without building; the saved state continues at the next
+ * sfrom_run when the handle has as many sources as were saved, so that n
+ * steps, save, load and n more steps equal 2n steps bitwise. Sources and
+ * receivers are not part of the checkpoint. A failure after the file has
+ * been validated leaves no ROM. Errors: EINVAL, EDEVICE, ENOMEM. */
+int sfrom_load(sfrom_t* h, const char* path);
 
 /* Zero the fine-grid state. */
 int sfrom_fine_reset(sfrom_t* h);
@@ -266,6 +291,7 @@ typedef struct {
   double build_ms;         /* last sfrom_build wall time          */
   int32_t cell_variant;    /* autotuned on-line cell-phase kernel variant of the last
                               run (0-3 matrix-core tilings, 4 scalar; -1 before)    */
+  int64_t steps_done;      /* on-line steps since the last reset (or as loaded)     */
 } sfrom_info;
 
 int sfrom_get_info(const sfrom_t* h, sfrom_info* info);

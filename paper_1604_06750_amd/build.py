@@ -32,8 +32,19 @@ def _hipcc():
             return c
 
 
-def _compile(src: str) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """Object older than its source or any header of the library."""
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src), os.path.join(CSRC, "sfrom_internal.h"),
+            os.path.join(os.path.dirname(HERE), "include", "sfrom.h"), __file__]
+    return os.path.getmtime(obj) < max(os.path.getmtime(d) for d in deps)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    if incremental and not _stale(src, obj):
+        return obj
     lang = ["-x", "hip"] if src.endswith((".hip", ".cpp")) else []
     cmd = [_hipcc(), *lang, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -42,11 +53,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every source (or, with ``incremental``, only those whose
+    object is older than the source or the headers) and link libsfrom.so."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     tmp = OUT + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -59,5 +72,5 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -114,7 +114,10 @@ void free_rom(sfrom_t* h) {
   for (auto& bk : h->buckets) dfree(bk.d_list);
   h->buckets.clear();
   h->built = false;
+  h->rom_imported = false;
+  h->lam_rom = -1.0;
   h->state_ns = -1;
+  h->steps_done = 0;
   h->src_dirty = h->rec_dirty = true;
 }
 
@@ -292,6 +295,17 @@ void finalize_partition(sfrom_t* h) {
     REQUIRE(std::fabs(asum[k] - h->a[k]) <= 1e-12 * amax, SFROM_ESPLIT, "sum of cell operators differs from A at entry " + std::to_string(k));
   for (int64_t g = 0; g < n; ++g)
     REQUIRE(std::fabs(bsum[g] - h->b[g]) <= 1e-12 * bmax, SFROM_ESPLIT, "sum of cell masses differs from B at node " + std::to_string(g));
+  // Gershgorin bound of each cell's pencil: every eigenvalue of
+  // B_i^{-1}(-A_i) lies in a disc around a diagonal entry of radius the
+  // row's off-diagonal absolute sum
+  double lam = 0.0;
+  for (const auto& c : h->cells)
+    for (int r = 0; r < c.n; ++r) {
+      double s = 0.0;
+      for (int k = c.rowptr[r]; k < c.rowptr[r + 1]; ++k) s += std::fabs(c.a[k]);
+      lam = std::max(lam, s / c.b[r]);
+    }
+  h->lam_cells = lam;
   h->part_ready = true;
 }
 
@@ -808,6 +822,42 @@ void update_masses(sfrom_t* h) {
   h->masses_dirty = false;
 }
 
+// Bytes of one level of the piece state and of the hidden state for the
+// current state width.
+size_t ystate_bytes(const sfrom_t* h, int ns) { return (size_t)h->piece_dof_off.back() * ns * prec_bytes(h->prec); }
+size_t hstate_bytes(const sfrom_t* h, int ns) {
+  return (size_t)std::max<int64_t>(h->n_hidden_rows, 1) * ns * prec_bytes(h->prec);
+}
+
+// Zeroes both levels of the ROM state (eq. initial: u = 0 for t <= 0).
+void zero_state(sfrom_t* h) {
+  h->steps_done = 0;
+  h->cur = 0;
+  if (h->state_ns < 0) return;
+  for (int k = 0; k < 2; ++k) {
+    HIPCHK(hipMemsetAsync(h->d_y[k], 0, ystate_bytes(h, h->state_ns), h->stream));
+    HIPCHK(hipMemsetAsync(h->d_h[k], 0, hstate_bytes(h, h->state_ns), h->stream));
+  }
+}
+
+// (Re)allocates the ROM state and the Phi^1 exchange buffer for n_s sources
+// and zeroes the state. A captured run refers to the old buffers, so it is
+// dropped first.
+void alloc_state(sfrom_t* h, int ns) {
+  drop_graph(h);
+  int64_t nu1 = 0;
+  for (auto& oc : h->ocells) nu1 += oc.b;
+  for (int k = 0; k < 2; ++k) {
+    dfree(h->d_y[k]); dfree(h->d_h[k]);
+    h->d_y[k] = dalloc<unsigned char>(h, ystate_bytes(h, ns));
+    h->d_h[k] = dalloc<unsigned char>(h, hstate_bytes(h, ns));
+  }
+  dfree(h->d_phi);
+  h->d_phi = dalloc<unsigned char>(h, (size_t)nu1 * ns * prec_bytes(h->prec));
+  h->state_ns = ns;
+  zero_state(h);
+}
+
 // ROM-side device inputs/outputs and state for n_s sources
 void prepare_online(sfrom_t* h) {
   const int ns = h->src.count;
@@ -874,24 +924,7 @@ void prepare_online(sfrom_t* h) {
     }
     h->rec_dirty = false;
   }
-  if (h->state_ns != ns) {
-    const int64_t npd = h->piece_dof_off.back();
-    int64_t nu1 = 0;
-    for (auto& oc : h->ocells) nu1 += oc.b;
-    for (int k = 0; k < 2; ++k) {
-      dfree(h->d_y[k]); dfree(h->d_h[k]);
-      h->d_y[k] = dalloc<unsigned char>(h, (size_t)npd * ns * eb);
-      h->d_h[k] = dalloc<unsigned char>(h, (size_t)std::max<int64_t>(h->n_hidden_rows, 1) * ns * eb);
-    }
-    dfree(h->d_phi);
-    h->d_phi = dalloc<unsigned char>(h, (size_t)nu1 * ns * eb);
-    h->state_ns = ns;
-    for (int k = 0; k < 2; ++k) {
-      HIPCHK(hipMemsetAsync(h->d_y[k], 0, (size_t)npd * ns * eb, h->stream));
-      HIPCHK(hipMemsetAsync(h->d_h[k], 0, (size_t)std::max<int64_t>(h->n_hidden_rows, 1) * ns * eb, h->stream));
-    }
-    h->cur = 0;
-  }
+  if (h->state_ns != ns) alloc_state(h, ns);
 }
 
 // Autotuner of the cell phase: on the first run for a given (precision,
@@ -960,13 +993,33 @@ const double* stage_w(sfrom_t* h, int64_t n_steps, const double* w, int w_on_dev
   return h->d_w;
 }
 
+double rom_lambda_exact(sfrom_t* h);
+
+// Leapfrog stability (Remark MFEM: the explicit scheme is stable for
+// dt^2 lambda_max < 4). The cheap sufficient test uses the cells' Gershgorin
+// bound (valid for blocks built from the cells' pencils); only when it fails,
+// or for imported blocks, is the ROM's own largest eigenvalue computed.
+void check_cfl(sfrom_t* h, double dt) {
+  const double d2 = dt * dt;
+  if (!h->rom_imported && h->lam_cells > 0.0 && d2 * h->lam_cells < 4.0) return;
+  const double lam = rom_lambda_exact(h);
+  char msg[160];
+  std::snprintf(msg, sizeof msg, "dt = %.6g exceeds the leapfrog stability limit 2/sqrt(lambda_max) = %.6g of the ROM",
+                dt, 2.0 / std::sqrt(lam));
+  REQUIRE(d2 * lam < 4.0, SFROM_ECFL, msg);
+}
+
 void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_device, void* traces, int traces_on_device) {
   REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
   REQUIRE(h->built, SFROM_ESTATE, "no ROM: call sfrom_build first");
   REQUIRE(n_steps >= 0, SFROM_EINVAL, "n_steps < 0");
   REQUIRE(dt > 0.0 && std::isfinite(dt), SFROM_EINVAL, "dt must be positive");
   REQUIRE(w != nullptr || n_steps == 0, SFROM_EINVAL, "null wavelet");
+  if (!w_on_device)
+    for (int64_t k = 0; k < n_steps; ++k)
+      REQUIRE(std::isfinite(w[k]), SFROM_ENONFINITE, "wavelet sample " + std::to_string(k) + " is not finite");
   update_masses(h);
+  if (n_steps > 0) check_cfl(h, dt);
   prepare_online(h);
   const int ns = h->src.count, nr = h->rec.count;
   const size_t eb = prec_bytes(h->prec);
@@ -1032,7 +1085,9 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
     int64_t dbits;
     std::memcpy(&dbits, &dtv, 8);
     key = {n_steps, dbits, (int64_t)(intptr_t)d_w, (int64_t)(intptr_t)d_tr, (int64_t)h->cur,
-           (int64_t)(intptr_t)h->d_y[0], (int64_t)(intptr_t)h->d_h[0], (int64_t)(intptr_t)h->d_phi,
+           (int64_t)(intptr_t)h->d_y[0], (int64_t)(intptr_t)h->d_y[1], (int64_t)(intptr_t)h->d_h[0],
+           (int64_t)(intptr_t)h->d_h[1], (int64_t)(intptr_t)h->d_phi, (int64_t)(intptr_t)h->d_minv,
+           (int64_t)(intptr_t)h->d_src, (int64_t)(intptr_t)h->d_rval,
            (int64_t)ns, (int64_t)nr, (int64_t)a.cell_variant, (int64_t)(intptr_t)h->d_blocks};
     for (const StepArgs& ab : ba) key.push_back(ab.cell_variant);
     if (h->graph_exec && key == h->graph_key) {
@@ -1080,6 +1135,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   }
   }
 done:
+  h->steps_done += n_steps;
   if (own) {
     HIPCHK(hipMemcpyAsync(traces, d_tr, tbytes, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1261,6 +1317,313 @@ double lanczos_max(int64_t n, MV matvec, int maxit = 300) {
     beta = bn;
   }
   return lam;
+}
+
+
+// Largest eigenvalue of the global ROM pencil (-L, D) by Lanczos on the
+// host (FP64 blocks as built or imported), cached until the ROM changes.
+double rom_lambda_exact(sfrom_t* h) {
+  if (h->lam_rom >= 0.0) return h->lam_rom;
+  const int nc = (int)h->ocells.size();
+  // host copy of the double blocks; operator D^{-1/2}(-L)D^{-1/2} applied in
+  // cell-blocked flux form with D = blkdiag(M_p, (Ghat_i^k)^{-1}).
+  std::vector<double> r64;
+  int64_t tot = 0;
+  for (int i = 0; i < nc; ++i) tot += 2LL * h->ocells[i].m * h->ocells[i].b * h->ocells[i].b;
+  r64.resize(tot);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(r64.data(), h->d_rom64, tot * 8, hipMemcpyDeviceToHost));
+  const int64_t npd = h->piece_dof_off.back();
+  const int64_t ndof = npd + h->n_hidden_dofs;
+  std::vector<int64_t> hoff(nc + 1, 0);   // hidden dofs of the cells, unpadded
+  for (int i = 0; i < nc; ++i) hoff[i + 1] = hoff[i] + (int64_t)(h->ocells[i].m - 1) * h->ocells[i].b;
+  // symmetric square roots of the mass blocks: piece masses M_p and hidden (Ghat^k)^{-1}
+  auto symsqrt = [](int n, const double* A, double* out, bool inverse) {
+    // Jacobi eigen-decomposition (small n)
+    std::vector<double> a(A, A + n * n), v(n * n, 0.0);
+    for (int i = 0; i < n; ++i) v[i + i * n] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+      double off = 0.0;
+      for (int p = 0; p < n; ++p) for (int q = p + 1; q < n; ++q) off += a[p + q * n] * a[p + q * n];
+      if (off < 1e-30) break;
+      for (int p = 0; p < n; ++p)
+        for (int q = p + 1; q < n; ++q) {
+          const double apq = a[p + q * n];
+          if (std::fabs(apq) < 1e-300) continue;
+          const double th = 0.5 * (a[q + q * n] - a[p + p * n]) / apq;
+          const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+          const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+          for (int k = 0; k < n; ++k) {
+            const double akp = a[k + p * n], akq = a[k + q * n];
+            a[k + p * n] = c * akp - s * akq; a[k + q * n] = s * akp + c * akq;
+          }
+          for (int k = 0; k < n; ++k) {
+            const double apk = a[p + k * n], aqk = a[q + k * n];
+            a[p + k * n] = c * apk - s * aqk; a[q + k * n] = s * apk + c * aqk;
+          }
+          for (int k = 0; k < n; ++k) {
+            const double vkp = v[k + p * n], vkq = v[k + q * n];
+            v[k + p * n] = c * vkp - s * vkq; v[k + q * n] = s * vkp + c * vkq;
+          }
+        }
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double ev = std::max(a[k + k * n], 1e-300);
+          s += v[i + k * n] * v[j + k * n] * (inverse ? 1.0 / std::sqrt(ev) : std::sqrt(ev));
+        }
+        out[i + j * n] = s;
+      }
+  };
+  // piece masses M_p = sum_c ([Ghat_c^1]_pp)^{-1}  -> M_p^{-1/2}
+  std::vector<std::vector<double>> pm(h->pieces.size());
+  for (size_t p = 0; p < h->pieces.size(); ++p) {
+    const int bp = h->pieces[p].b;
+    std::vector<double> M(bp * bp, 0.0);
+    for (int32_t c : h->piece_cells[p]) {
+      const auto& cp = h->cell_pieces[c];
+      const size_t q = std::lower_bound(cp.begin(), cp.end(), (int32_t)p) - cp.begin();
+      const int col0 = h->cell_piece_col[c][q], b = h->ocells[c].b;
+      const double* G1 = r64.data() + h->rom64_off[c];
+      std::vector<double> blk(bp * bp), inv(bp * bp), tmp(bp * bp);
+      for (int j = 0; j < bp; ++j) for (int i = 0; i < bp; ++i) blk[i + j * bp] = G1[(col0 + i) + (int64_t)(col0 + j) * b];
+      // inverse via inverse square root squared
+      symsqrt(bp, blk.data(), tmp.data(), true);
+      for (int i = 0; i < bp; ++i) for (int j = 0; j < bp; ++j) {
+        double s = 0.0; for (int k = 0; k < bp; ++k) s += tmp[i + k * bp] * tmp[k + j * bp];
+        M[i + j * bp] += s;
+      }
+    }
+    pm[p].resize(bp * bp);
+    symsqrt(bp, M.data(), pm[p].data(), true);
+  }
+  // hidden mass (Ghat^k)^{-1} -> its inverse square root is Ghat^{1/2}
+  std::vector<std::vector<double>> hsq(nc);
+  for (int i = 0; i < nc; ++i) {
+    const int m = h->ocells[i].m, b = h->ocells[i].b;
+    hsq[i].resize((size_t)std::max(m - 1, 0) * b * b);
+    for (int k = 1; k < m; ++k) symsqrt(b, r64.data() + h->rom64_off[i] + (int64_t)k * b * b, hsq[i].data() + (int64_t)(k - 1) * b * b, false);
+  }
+  auto apply_msq = [&](const double* x, double* y) {   // y = D^{-1/2} x
+    for (size_t p = 0; p < h->pieces.size(); ++p) {
+      const int bp = h->pieces[p].b; const int64_t o = h->piece_dof_off[p];
+      for (int i = 0; i < bp; ++i) { double s = 0.0; for (int j = 0; j < bp; ++j) s += pm[p][i + j * bp] * x[o + j]; y[o + i] = s; }
+    }
+    for (int i = 0; i < nc; ++i) {
+      const int m = h->ocells[i].m, b = h->ocells[i].b;
+      for (int k = 1; k < m; ++k) {
+        const int64_t o = npd + hoff[i] + (int64_t)(k - 1) * b;
+        const double* S = hsq[i].data() + (int64_t)(k - 1) * b * b;
+        for (int r = 0; r < b; ++r) { double s = 0.0; for (int c = 0; c < b; ++c) s += S[r + c * b] * x[o + c]; y[o + r] = s; }
+      }
+    }
+  };
+  std::vector<double> t1(ndof), t2(ndof);
+  auto mv = [&](const double* x, double* y) {
+    apply_msq(x, t1.data());
+    std::fill(t2.begin(), t2.end(), 0.0);
+    for (int i = 0; i < nc; ++i) {
+      const int m = h->ocells[i].m, b = h->ocells[i].b;
+      const double* G = r64.data() + h->rom64_off[i] + (int64_t)m * b * b;
+      std::vector<int64_t> rows((size_t)m * b);
+      int r0 = 0;
+      for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) {
+        const int32_t p = h->cell_pieces[i][q];
+        for (int l = 0; l < h->pieces[p].b; ++l) rows[r0++] = h->piece_dof_off[p] + l;
+      }
+      for (int k = 1; k < m; ++k) for (int r = 0; r < b; ++r) rows[(size_t)k * b + r] = npd + hoff[i] + (int64_t)(k - 1) * b + r;
+      // (-L U)^k = -(Phi^k - Phi^{k-1}), Phi^k = G^k (U^{k+1} - U^k)
+      std::vector<double> phi((size_t)m * b);
+      for (int k = 0; k < m; ++k)
+        for (int r = 0; r < b; ++r) {
+          double s = 0.0;
+          for (int c = 0; c < b; ++c) {
+            const double up = (k + 1 < m) ? t1[rows[(size_t)(k + 1) * b + c]] : 0.0;
+            s += G[(int64_t)k * b * b + r + (int64_t)c * b] * (up - t1[rows[(size_t)k * b + c]]);
+          }
+          phi[(size_t)k * b + r] = s;
+        }
+      for (int k = 0; k < m; ++k)
+        for (int r = 0; r < b; ++r) t2[rows[(size_t)k * b + r]] -= phi[(size_t)k * b + r] - (k > 0 ? phi[(size_t)(k - 1) * b + r] : 0.0);
+    }
+    apply_msq(t2.data(), y);
+  };
+  h->lam_rom = lanczos_max(ndof, mv);
+  return h->lam_rom;
+}
+
+
+// ---------------------------------------------------------------------------
+// ROM and state checkpoint (sfrom_save / sfrom_load)
+// ---------------------------------------------------------------------------
+
+constexpr char kMagic[8] = {'S', 'F', 'R', 'O', 'M', 'C', 'K', 'P'};
+constexpr int32_t kVersion = 1;
+
+struct File {
+  std::FILE* f = nullptr;
+  ~File() { if (f) std::fclose(f); }
+};
+
+void put(sfrom_t* h, File& F, const void* p, size_t n) {
+  REQUIRE(n == 0 || std::fwrite(p, 1, n, F.f) == n, SFROM_EINVAL, "write to the checkpoint file failed");
+}
+void get(sfrom_t* h, File& F, void* p, size_t n) {
+  REQUIRE(n == 0 || std::fread(p, 1, n, F.f) == n, SFROM_EINVAL, "checkpoint file is truncated");
+}
+template <typename T>
+void put_v(sfrom_t* h, File& F, T v) { put(h, F, &v, sizeof v); }
+template <typename T>
+T get_v(sfrom_t* h, File& F) { T v; get(h, F, &v, sizeof v); return v; }
+
+// device -> file in chunks
+void put_dev(sfrom_t* h, File& F, const void* d, size_t n) {
+  std::vector<unsigned char> buf(std::min<size_t>(n, (size_t)64 << 20));
+  for (size_t o = 0; o < n; o += buf.size()) {
+    const size_t k = std::min(buf.size(), n - o);
+    HIPCHK(hipMemcpy(buf.data(), (const unsigned char*)d + o, k, hipMemcpyDeviceToHost));
+    put(h, F, buf.data(), k);
+  }
+}
+void get_dev(sfrom_t* h, File& F, void* d, size_t n) {
+  std::vector<unsigned char> buf(std::min<size_t>(n, (size_t)64 << 20));
+  for (size_t o = 0; o < n; o += buf.size()) {
+    const size_t k = std::min(buf.size(), n - o);
+    get(h, F, buf.data(), k);
+    HIPCHK(hipMemcpy((unsigned char*)d + o, buf.data(), k, hipMemcpyHostToDevice));
+  }
+}
+
+int64_t minv_elems(const sfrom_t* h) {
+  int64_t moff = 0;
+  for (auto& op : h->opieces) moff += (int64_t)op.b * op.b;
+  return moff;
+}
+int64_t rom64_elems(const sfrom_t* h) {
+  int64_t r = 0;
+  for (auto& oc : h->ocells) r += 2LL * oc.m * oc.b * oc.b;
+  return r;
+}
+
+void save_checkpoint(sfrom_t* h, const char* path) {
+  REQUIRE(path != nullptr, SFROM_EINVAL, "null path");
+  REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
+  REQUIRE(h->built, SFROM_ESTATE, "no ROM: build or load first");
+  update_masses(h);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  File F;
+  F.f = std::fopen(path, "wb");
+  REQUIRE(F.f != nullptr, SFROM_EINVAL, std::string("cannot open ") + path + " for writing");
+  const int nc = (int)h->cells.size(), np = (int)h->pieces.size();
+  put(h, F, kMagic, 8);
+  put_v<int32_t>(h, F, kVersion);
+  put_v<int32_t>(h, F, nc);
+  put_v<int32_t>(h, F, np);
+  put_v<int32_t>(h, F, h->prec);
+  put_v<double>(h, F, h->shift);
+  put_v<int32_t>(h, F, h->rom_imported ? 1 : 0);
+  for (int i = 0; i < nc; ++i) { put_v<int32_t>(h, F, h->ocells[i].m); put_v<int32_t>(h, F, h->ocells[i].b); }
+  for (int p = 0; p < np; ++p) {
+    const auto& pc = h->pieces[p];
+    put_v<int32_t>(h, F, pc.b);
+    put_v<int64_t>(h, F, (int64_t)pc.gnode.size());
+    put(h, F, pc.gnode.data(), pc.gnode.size() * 8);
+    put(h, F, pc.S.data(), pc.S.size() * 8);
+  }
+  put_dev(h, F, h->d_rom64, (size_t)rom64_elems(h) * 8);
+  put_dev(h, F, h->d_blocks, (size_t)h->block_elems * block_bytes(h->prec));
+  put_dev(h, F, h->d_minv, (size_t)minv_elems(h) * prec_bytes(h->prec));
+  put_v<int32_t>(h, F, h->state_ns);
+  put_v<int32_t>(h, F, h->cur);
+  put_v<int64_t>(h, F, h->steps_done);
+  if (h->state_ns > 0)
+    for (int k = 0; k < 2; ++k) {
+      put_dev(h, F, h->d_y[k], ystate_bytes(h, h->state_ns));
+      put_dev(h, F, h->d_h[k], hstate_bytes(h, h->state_ns));
+    }
+  REQUIRE(std::fflush(F.f) == 0, SFROM_EINVAL, "write to the checkpoint file failed");
+}
+
+void load_arrays(sfrom_t* h, File& F);
+
+void load_checkpoint(sfrom_t* h, const char* path) {
+  REQUIRE(path != nullptr, SFROM_EINVAL, "null path");
+  REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
+  finalize_partition(h);
+  File F;
+  F.f = std::fopen(path, "rb");
+  REQUIRE(F.f != nullptr, SFROM_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  get(h, F, magic, 8);
+  REQUIRE(std::memcmp(magic, kMagic, 8) == 0, SFROM_EINVAL, "not an sfrom checkpoint file");
+  const int32_t ver = get_v<int32_t>(h, F);
+  REQUIRE(ver == kVersion, SFROM_EINVAL, "unsupported checkpoint version " + std::to_string(ver));
+  const int nc = (int)h->cells.size(), np = (int)h->pieces.size();
+  REQUIRE(get_v<int32_t>(h, F) == nc && get_v<int32_t>(h, F) == np, SFROM_EINVAL,
+          "checkpoint partition differs: cell or piece count");
+  const int32_t prec = get_v<int32_t>(h, F);
+  REQUIRE(prec >= SFROM_F64 && prec <= SFROM_BF16, SFROM_EINVAL, "bad on-line precision in checkpoint");
+  const double shift = get_v<double>(h, F);
+  const int32_t imported = get_v<int32_t>(h, F);
+  std::vector<int32_t> mpc(nc);
+  for (int i = 0; i < nc; ++i) {
+    mpc[i] = get_v<int32_t>(h, F);
+    const int32_t b = get_v<int32_t>(h, F);
+    REQUIRE(b == h->cell_b[i] && mpc[i] >= 1, SFROM_EINVAL,
+            "checkpoint partition differs: boundary dimension of cell " + std::to_string(i));
+  }
+  for (int p = 0; p < np; ++p) {
+    const auto& pc = h->pieces[p];
+    const int32_t bp = get_v<int32_t>(h, F);
+    const int64_t kp = get_v<int64_t>(h, F);
+    REQUIRE(bp == pc.b && kp == (int64_t)pc.gnode.size(), SFROM_EINVAL,
+            "checkpoint partition differs: piece " + std::to_string(p));
+    std::vector<int64_t> g((size_t)kp);
+    std::vector<double> S((size_t)kp * bp);
+    get(h, F, g.data(), g.size() * 8);
+    get(h, F, S.data(), S.size() * 8);
+    REQUIRE(g == pc.gnode && S == pc.S, SFROM_EINVAL,
+            "checkpoint partition differs: nodes or basis of piece " + std::to_string(p));
+  }
+  sfrom_build_opts o{};
+  o.m = mpc[0];
+  o.m_per_cell = mpc.data();
+  o.shift = shift;
+  o.online_prec = prec;
+  BuildCtx ctx;
+  build_layout(h, &o, ctx);   // on-line layout and device arrays, no build
+  // from here on the previous ROM is gone: a failure leaves no ROM
+  h->rom_imported = imported != 0;
+  try {
+    load_arrays(h, F);
+  } catch (const Fail&) {
+    free_rom(h);
+    throw;
+  }
+}
+
+void load_arrays(sfrom_t* h, File& F) {
+  get_dev(h, F, h->d_rom64, (size_t)rom64_elems(h) * 8);
+  get_dev(h, F, h->d_blocks, (size_t)h->block_elems * block_bytes(h->prec));
+  get_dev(h, F, h->d_minv, (size_t)minv_elems(h) * prec_bytes(h->prec));
+  const int32_t sns = get_v<int32_t>(h, F);
+  const int32_t cur = get_v<int32_t>(h, F);
+  const int64_t done = get_v<int64_t>(h, F);
+  REQUIRE(cur == 0 || cur == 1, SFROM_EINVAL, "bad state level in checkpoint");
+  if (sns > 0) {
+    alloc_state(h, sns);
+    for (int k = 0; k < 2; ++k) {
+      get_dev(h, F, h->d_y[k], ystate_bytes(h, sns));
+      get_dev(h, F, h->d_h[k], hstate_bytes(h, sns));
+    }
+  }
+  h->cur = cur;
+  h->steps_done = done;
+  h->masses_dirty = false;
+  h->lam_rom = -1.0;
+  h->built = true;
 }
 
 }  // namespace
@@ -1542,6 +1905,20 @@ int sfrom_import_rom(sfrom_t* h, int32_t cell, int32_t m, int32_t b, const doubl
     HIPCHK(hipMemcpy(dst, bf.data(), bf.size() * 2, hipMemcpyHostToDevice));
   }
   h->masses_dirty = true;
+  h->rom_imported = true;   // the cells' Gershgorin bound no longer covers these blocks
+  h->lam_rom = -1.0;
+  API_END(h)
+}
+
+int sfrom_save(sfrom_t* h, const char* path) {
+  API_BEGIN(h)
+  save_checkpoint(h, path);
+  API_END(h)
+}
+
+int sfrom_load(sfrom_t* h, const char* path) {
+  API_BEGIN(h)
+  load_checkpoint(h, path);
   API_END(h)
 }
 
@@ -1617,7 +1994,7 @@ int sfrom_point_columns(sfrom_t* h, int32_t count, const int64_t* node, int64_t*
 int sfrom_reset(sfrom_t* h) {
   API_BEGIN(h)
   REQUIRE(h->built, SFROM_ESTATE, "no ROM: build first");
-  h->state_ns = -1;   // reallocated and zeroed at the next run
+  zero_state(h);
   API_END(h)
 }
 
@@ -1661,133 +2038,7 @@ int sfrom_fine_lambda_max(sfrom_t* h, double* lambda) {
 int sfrom_rom_lambda_max(sfrom_t* h, double* lambda) {
   API_BEGIN(h)
   REQUIRE(h->built && lambda, SFROM_ESTATE, "no ROM: build first");
-  const int nc = (int)h->ocells.size();
-  // host copy of the double blocks; operator D^{-1/2}(-L)D^{-1/2} applied in
-  // cell-blocked flux form with D = blkdiag(M_p, (Ghat_i^k)^{-1}).
-  std::vector<double> r64;
-  int64_t tot = 0;
-  for (int i = 0; i < nc; ++i) tot += 2LL * h->ocells[i].m * h->ocells[i].b * h->ocells[i].b;
-  r64.resize(tot);
-  HIPCHK(hipStreamSynchronize(h->stream));
-  HIPCHK(hipMemcpy(r64.data(), h->d_rom64, tot * 8, hipMemcpyDeviceToHost));
-  const int64_t npd = h->piece_dof_off.back();
-  const int64_t ndof = npd + h->n_hidden_dofs;
-  std::vector<int64_t> hoff(nc + 1, 0);   // hidden dofs of the cells, unpadded
-  for (int i = 0; i < nc; ++i) hoff[i + 1] = hoff[i] + (int64_t)(h->ocells[i].m - 1) * h->ocells[i].b;
-  // symmetric square roots of the mass blocks: piece masses M_p and hidden (Ghat^k)^{-1}
-  auto symsqrt = [](int n, const double* A, double* out, bool inverse) {
-    // Jacobi eigen-decomposition (small n)
-    std::vector<double> a(A, A + n * n), v(n * n, 0.0);
-    for (int i = 0; i < n; ++i) v[i + i * n] = 1.0;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-      double off = 0.0;
-      for (int p = 0; p < n; ++p) for (int q = p + 1; q < n; ++q) off += a[p + q * n] * a[p + q * n];
-      if (off < 1e-30) break;
-      for (int p = 0; p < n; ++p)
-        for (int q = p + 1; q < n; ++q) {
-          const double apq = a[p + q * n];
-          if (std::fabs(apq) < 1e-300) continue;
-          const double th = 0.5 * (a[q + q * n] - a[p + p * n]) / apq;
-          const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-          const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-          for (int k = 0; k < n; ++k) {
-            const double akp = a[k + p * n], akq = a[k + q * n];
-            a[k + p * n] = c * akp - s * akq; a[k + q * n] = s * akp + c * akq;
-          }
-          for (int k = 0; k < n; ++k) {
-            const double apk = a[p + k * n], aqk = a[q + k * n];
-            a[p + k * n] = c * apk - s * aqk; a[q + k * n] = s * apk + c * aqk;
-          }
-          for (int k = 0; k < n; ++k) {
-            const double vkp = v[k + p * n], vkq = v[k + q * n];
-            v[k + p * n] = c * vkp - s * vkq; v[k + q * n] = s * vkp + c * vkq;
-          }
-        }
-    }
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) {
-          const double ev = std::max(a[k + k * n], 1e-300);
-          s += v[i + k * n] * v[j + k * n] * (inverse ? 1.0 / std::sqrt(ev) : std::sqrt(ev));
-        }
-        out[i + j * n] = s;
-      }
-  };
-  // piece masses M_p = sum_c ([Ghat_c^1]_pp)^{-1}  -> M_p^{-1/2}
-  std::vector<std::vector<double>> pm(h->pieces.size());
-  for (size_t p = 0; p < h->pieces.size(); ++p) {
-    const int bp = h->pieces[p].b;
-    std::vector<double> M(bp * bp, 0.0);
-    for (int32_t c : h->piece_cells[p]) {
-      const auto& cp = h->cell_pieces[c];
-      const size_t q = std::lower_bound(cp.begin(), cp.end(), (int32_t)p) - cp.begin();
-      const int col0 = h->cell_piece_col[c][q], b = h->ocells[c].b;
-      const double* G1 = r64.data() + h->rom64_off[c];
-      std::vector<double> blk(bp * bp), inv(bp * bp), tmp(bp * bp);
-      for (int j = 0; j < bp; ++j) for (int i = 0; i < bp; ++i) blk[i + j * bp] = G1[(col0 + i) + (int64_t)(col0 + j) * b];
-      // inverse via inverse square root squared
-      symsqrt(bp, blk.data(), tmp.data(), true);
-      for (int i = 0; i < bp; ++i) for (int j = 0; j < bp; ++j) {
-        double s = 0.0; for (int k = 0; k < bp; ++k) s += tmp[i + k * bp] * tmp[k + j * bp];
-        M[i + j * bp] += s;
-      }
-    }
-    pm[p].resize(bp * bp);
-    symsqrt(bp, M.data(), pm[p].data(), true);
-  }
-  // hidden mass (Ghat^k)^{-1} -> its inverse square root is Ghat^{1/2}
-  std::vector<std::vector<double>> hsq(nc);
-  for (int i = 0; i < nc; ++i) {
-    const int m = h->ocells[i].m, b = h->ocells[i].b;
-    hsq[i].resize((size_t)std::max(m - 1, 0) * b * b);
-    for (int k = 1; k < m; ++k) symsqrt(b, r64.data() + h->rom64_off[i] + (int64_t)k * b * b, hsq[i].data() + (int64_t)(k - 1) * b * b, false);
-  }
-  auto apply_msq = [&](const double* x, double* y) {   // y = D^{-1/2} x
-    for (size_t p = 0; p < h->pieces.size(); ++p) {
-      const int bp = h->pieces[p].b; const int64_t o = h->piece_dof_off[p];
-      for (int i = 0; i < bp; ++i) { double s = 0.0; for (int j = 0; j < bp; ++j) s += pm[p][i + j * bp] * x[o + j]; y[o + i] = s; }
-    }
-    for (int i = 0; i < nc; ++i) {
-      const int m = h->ocells[i].m, b = h->ocells[i].b;
-      for (int k = 1; k < m; ++k) {
-        const int64_t o = npd + hoff[i] + (int64_t)(k - 1) * b;
-        const double* S = hsq[i].data() + (int64_t)(k - 1) * b * b;
-        for (int r = 0; r < b; ++r) { double s = 0.0; for (int c = 0; c < b; ++c) s += S[r + c * b] * x[o + c]; y[o + r] = s; }
-      }
-    }
-  };
-  std::vector<double> t1(ndof), t2(ndof);
-  auto mv = [&](const double* x, double* y) {
-    apply_msq(x, t1.data());
-    std::fill(t2.begin(), t2.end(), 0.0);
-    for (int i = 0; i < nc; ++i) {
-      const int m = h->ocells[i].m, b = h->ocells[i].b;
-      const double* G = r64.data() + h->rom64_off[i] + (int64_t)m * b * b;
-      std::vector<int64_t> rows((size_t)m * b);
-      int r0 = 0;
-      for (size_t q = 0; q < h->cell_pieces[i].size(); ++q) {
-        const int32_t p = h->cell_pieces[i][q];
-        for (int l = 0; l < h->pieces[p].b; ++l) rows[r0++] = h->piece_dof_off[p] + l;
-      }
-      for (int k = 1; k < m; ++k) for (int r = 0; r < b; ++r) rows[(size_t)k * b + r] = npd + hoff[i] + (int64_t)(k - 1) * b + r;
-      // (-L U)^k = -(Phi^k - Phi^{k-1}), Phi^k = G^k (U^{k+1} - U^k)
-      std::vector<double> phi((size_t)m * b);
-      for (int k = 0; k < m; ++k)
-        for (int r = 0; r < b; ++r) {
-          double s = 0.0;
-          for (int c = 0; c < b; ++c) {
-            const double up = (k + 1 < m) ? t1[rows[(size_t)(k + 1) * b + c]] : 0.0;
-            s += G[(int64_t)k * b * b + r + (int64_t)c * b] * (up - t1[rows[(size_t)k * b + c]]);
-          }
-          phi[(size_t)k * b + r] = s;
-        }
-      for (int k = 0; k < m; ++k)
-        for (int r = 0; r < b; ++r) t2[rows[(size_t)k * b + r]] -= phi[(size_t)k * b + r] - (k > 0 ? phi[(size_t)(k - 1) * b + r] : 0.0);
-    }
-    apply_msq(t2.data(), y);
-  };
-  *lambda = lanczos_max(ndof, mv);
+  *lambda = rom_lambda_exact(h);
   API_END(h)
 }
 
@@ -1846,6 +2097,7 @@ int sfrom_get_info(const sfrom_t* hc, sfrom_info* info) {
   info->block_bytes = h->built ? h->block_elems * (int64_t)block_bytes(h->prec) : 0;
   info->build_ms = h->build_ms;
   info->cell_variant = h->tuned_variant;
+  info->steps_done = h->steps_done;
   return SFROM_OK;
 }
 

@@ -678,10 +678,15 @@ __global__ __launch_bounds__(256) void k_piece_phase(StepArgs a) {
   // incidence list and inverse mass are read through the scalar cache
   if constexpr (UNI) p = __builtin_amdgcn_readfirstlane(p);
   const OnlinePiece pc = a.d_pieces[p];
-  switch (pc.ncell) {
+  // the unrolled bodies hold NC x rows flux values in registers: edge lines
+  // (4 cells) up to 9 rows, corner points (8 cells) up to 4; wider pieces of
+  // those kinds take the generic loop below
+  constexpr int CAP4 = MAXB < 9 ? MAXB : 9, CAP8 = MAXB < 4 ? MAXB : 4;
+  const int kind = (pc.ncell == 2) ? 2 : (pc.ncell == 4 && pc.b <= CAP4) ? 4 : (pc.ncell == 8 && pc.b <= CAP8) ? 8 : 0;
+  switch (kind) {
     case 2: piece_body<T, TA, MAXB, 2>(a, pc, s); break;
-    case 4: piece_body<T, TA, (MAXB < 9 ? MAXB : 9), 4>(a, pc, s); break;
-    case 8: piece_body<T, TA, (MAXB < 4 ? MAXB : 4), 8>(a, pc, s); break;
+    case 4: piece_body<T, TA, CAP4, 4>(a, pc, s); break;
+    case 8: piece_body<T, TA, CAP8, 8>(a, pc, s); break;
     default: {
       // generic incidence count (partitions that are not Cartesian)
       const int bp = pc.b, ns = a.ns;

@@ -282,9 +282,18 @@ struct sfrom {
     std::vector<int64_t> soff;     // offset of each piece basis in d_S
   };
   CellStage stage;
+  // Upper bound of the largest eigenvalue of every cell's local pencil
+  // (Gershgorin discs of B_i^{-1}(-A_i)); -1 until computed for the current
+  // partition. Each cell's S-fraction is a Galerkin projection of that
+  // pencil and the global ROM an assembly of the cells' ROMs, so the bound
+  // also bounds the ROM's largest eigenvalue (used by the CFL check).
+  double lam_cells = -1.0;
 
   // ROM
   bool built = false;
+  bool rom_imported = false;   // some cell's blocks came from sfrom_import_rom
+  double lam_rom = -1.0;       // largest eigenvalue of the ROM pencil, once computed
+  int64_t steps_done = 0;      // on-line steps since the last reset
   int32_t prec = SFROM_F32;
   std::vector<int32_t> cell_m;
   double shift = 0.0;

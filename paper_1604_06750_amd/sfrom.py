@@ -45,7 +45,7 @@ class sfrom_info(C.Structure):
                 ("n_piece_dofs", C.c_int64), ("n_hidden_dofs", C.c_int64), ("max_b", C.c_int32),
                 ("max_m", C.c_int32), ("n_sources", C.c_int32), ("n_receivers", C.c_int32),
                 ("built", C.c_int32), ("online_prec", C.c_int32), ("block_bytes", C.c_int64),
-                ("build_ms", C.c_double), ("cell_variant", C.c_int32)]
+                ("build_ms", C.c_double), ("cell_variant", C.c_int32), ("steps_done", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -67,6 +67,8 @@ _SIGS = {
     "sfrom_set_receivers": [_P, C.c_int32, _P, _P, _P, C.c_int32],
     "sfrom_point_columns": [_P, C.c_int32, _P, _P, _P, _P],
     "sfrom_reset": [_P],
+    "sfrom_save": [_P, C.c_char_p],
+    "sfrom_load": [_P, C.c_char_p],
     "sfrom_run": [_P, C.c_int64, C.c_double, _P, C.c_int32, _P, C.c_int32],
     "sfrom_fine_reset": [_P],
     "sfrom_fine_run": [_P, C.c_int64, C.c_double, _P, C.c_int32, _P, C.c_int32, C.c_int32],
@@ -241,16 +243,39 @@ def sfrom_reset(h):
     _check(h, _lib.sfrom_reset(h))
 
 
+def sfrom_save(h, path):
+    _check(h, _lib.sfrom_save(h, os.fsencode(path)))
+
+
+def sfrom_load(h, path):
+    _check(h, _lib.sfrom_load(h, os.fsencode(path)))
+
+
+def _device_tensor(t, what):
+    """A torch tensor handed to the library as a device pointer: it must live
+    in GPU memory (the kernels dereference it) and be contiguous."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what}: a torch tensor must be on the GPU (got device {t.device}); "
+                         "pass a numpy array for host memory")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return _dev(t)
+
+
 def _wave_arg(w):
     if hasattr(w, "data_ptr"):
-        return _dev(w), 1, None
+        return _device_tensor(w, "wavelet"), 1, None
     w = _host(w, np.float64)
     return _ptr(w), 0, w
 
 
 def _trace_arg(traces):
     if hasattr(traces, "data_ptr"):
-        return _dev(traces), 1
+        return _device_tensor(traces, "traces"), 1
+    if not isinstance(traces, np.ndarray):
+        raise ValueError("traces must be a numpy array or a GPU torch tensor")
+    if not (traces.flags.c_contiguous and traces.flags.writeable):
+        raise ValueError("traces must be a C-contiguous, writeable numpy array")
     return _ptr(traces), 0
 
 

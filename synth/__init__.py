@@ -178,6 +178,8 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
     """Build a named workload.
 
     ``tiny``   : 16^3 voxels, 2^3 cells of 8^3 (fast CPU tests)
+    ``cube3``  : 24^3 voxels, 3^3 cells of 8^3 (one interior cell), seeded
+                 face-interior sources and receivers
     ``small``  : 32^3 voxels, 4^3 cells of 8^3, one source, 64 receivers,
                  1500 steps (the FP64 case)
     ``medium`` : 64^3 voxels, 8^3 cells, 16 sources (parity case that spans
@@ -207,6 +209,23 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
         rec = rec_all[np.sort(rng.choice(len(rec_all), size=nr, replace=False))]
         return Workload(name, nvox, sigma, rho, cuts, m or 3, mf, me, src, rec,
                         n_steps or 400, f_p, omega_max, shift, seed=seed)
+    if name == "cube3":
+        # 24^3 voxels, 3^3 cells of 8^3: the centre cell is interior (the
+        # boundary dimension of the 128^3 workload's interior cells) while
+        # the oracle stays within seconds; sources and receivers are seeded
+        # picks among face-interior nodes
+        nvox = (24, 24, 24)
+        seed = 6001 + realisation
+        sigma, rho = acoustic_medium(nvox, seed)
+        cuts = tuple(np.array([8, 16]) for _ in range(3))
+        fi = face_interior_nodes(nvox, cuts)
+        rng = np.random.Generator(np.random.PCG64(seed + 100))
+        ns = 64 if n_sources is None else n_sources
+        nr = 48 if n_receivers is None else n_receivers
+        src = fi[np.sort(rng.choice(len(fi), size=ns, replace=False))]
+        rec = fi[np.sort(rng.choice(len(fi), size=nr, replace=False))]
+        return Workload(name, nvox, sigma, rho, cuts, m or 4, mf, me, src, rec,
+                        n_steps or 300, f_p, omega_max, shift, seed=seed)
     if name == "small":
         nvox = (32, 32, 32)
         seed = 1001 + realisation

@@ -178,3 +178,38 @@ def test_binding_refuses_undersized_or_mistyped_buffers(monkeypatch):
         S._check_buffers(None, 10, np.zeros(5), np.zeros((10, 3, 2), np.float32), S.SFROM_F32)
     S._check_buffers(None, 10, np.zeros(10), np.zeros((10, 3, 2), np.float64), S.SFROM_F64)
     S._check_buffers(None, 0, np.zeros(0), np.zeros((0, 3, 2), np.float32), S.SFROM_F64)
+
+
+def test_binding_refuses_host_tensors_and_bad_numpy_layouts():
+    """Device pointers come only from GPU tensors (a CPU tensor's address
+    would be dereferenced by the kernels); host trace buffers must be
+    C-contiguous and writeable, since the library copies into them as one
+    flat block."""
+    S = _lib()
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        S._wave_arg(torch.zeros(10, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        S._trace_arg(torch.zeros((4, 3, 2), dtype=torch.float32))
+    t = np.zeros((4, 3, 2), np.float32)
+    with pytest.raises(ValueError):
+        S._trace_arg(t[::-1])
+    with pytest.raises(ValueError):
+        S._trace_arg(np.asfortranarray(np.zeros((4, 3, 2), np.float32)))
+    ro = np.zeros((4, 3, 2), np.float32)
+    ro.flags.writeable = False
+    with pytest.raises(ValueError):
+        S._trace_arg(ro)
+    with pytest.raises(ValueError):
+        S._trace_arg([[0.0]])
+    p, dev = S._trace_arg(t)
+    assert dev == 0 and p.value == t.ctypes.data
+
+
+def test_checkpoint_calls_need_a_device(host, tmp_path):
+    S, h = host
+    _small_split(S, h)
+    for f in (S.sfrom_save, S.sfrom_load):
+        with pytest.raises(S.SfromError) as e:
+            f(h, str(tmp_path / "x.ckp"))
+        assert e.value.name == "EDEVICE"

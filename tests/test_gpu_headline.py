@@ -1,0 +1,170 @@
+"""GPU parity at the benchmark's cell shape, element by element.
+
+The benchmark's on-line step runs cells of boundary dimension b = 56 (4 face
++ 2 edge + 1 corner modes per piece) with m = 4 layers and full tiles of 64
+sources. Here the same shapes run on a 24^3-voxel medium (3^3 cells of 8^3,
+the centre cell interior with b = 56, the wall cells in the same strip
+bucket) with 64 sources (one full tile) and 128 (two tiles), through every
+cell-phase kernel variant, against the FP64 oracle ROM on the same seeded
+inputs. The wavelet is seeded white noise, which excites the whole spectrum
+of the ROM (the recurrence is linear, so any wavelet is a valid parity
+input). Besides the relative L2 over all samples, every receiver is checked
+on its own: max |GPU - oracle| over (step, source) against the receiver's
+own peak, and against the global peak.
+
+Also here: the configuration of the FP64 case as configured (32^3 voxels,
+4^3 cells, m = 4, 4 face + 2 edge + 1 corner modes, one source, 64
+receivers, 1500 steps) and cells of 6..8 layers.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pipeline
+from oracle.rom_cell import build_cell
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+NSTEPS = 150
+
+
+def _lib():
+    from paper_1604_06750_amd import sfrom, problem
+    return sfrom, problem
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def per_receiver(tr, ref):
+    """(worst error of a receiver relative to its own peak, worst error of a
+    receiver relative to the global peak); traces are [step][receiver][source]."""
+    d = np.abs(np.asarray(tr, np.float64) - ref).max(axis=(0, 2))
+    own = np.abs(ref).max(axis=(0, 2))
+    assert own.min() > 0, "a receiver sees no signal: the test would not check it"
+    return float((d / own).max()), float(d.max() / np.abs(ref).max())
+
+
+def _gpu(wl, prec, dt, w, ns, variant=None, m_per_cell=None):
+    S, P = _lib()
+    h = S.sfrom_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        sub = synth.Workload(**{**wl.__dict__, "sources": wl.sources[:ns]})
+        P.setup(h, sub)
+        if variant is not None:
+            S.sfrom_set_cell_variant(h, variant)
+        S.sfrom_build(h, sub.m, sub.shift, prec, m_per_cell=m_per_cell)
+        info = S.sfrom_get_info(h)
+        tr = np.zeros((len(w), info["n_receivers"], ns), np.float64 if prec == S.SFROM_F64 else np.float32)
+        S.sfrom_run(h, len(w), dt, w, tr)
+        return tr, S.sfrom_get_info(h)
+    finally:
+        S.sfrom_destroy(h)
+
+
+@pytest.fixture(scope="module")
+def headline(dev):
+    wl = synth.workload("cube3", modes_face=4, modes_edge=2, m=4, n_sources=128, n_steps=NSTEPS)
+    run = pipeline.setup(wl)
+    run.w = np.random.default_rng(2024).standard_normal(NSTEPS)
+    pipeline.build_all(run)
+    ref = pipeline.rom_traces(run)
+    return wl, run, ref
+
+
+@pytest.mark.parametrize("ns", [64, 128])
+def test_headline_shape_every_variant_fp32(headline, ns):
+    """FP32 blocks and state, b = 56 interior cell, m = 4: global rel L2
+    <= 1e-4 (the FP32 bound), every sample within 1e-4 of the global peak,
+    every receiver within 1e-3 of its own peak."""
+    S, _ = _lib()
+    wl, run, ref = headline
+    ref = ref[:, :, :ns]
+    for v in range(5):
+        tr, info = _gpu(wl, S.SFROM_F32, run.dt, run.w, ns, variant=v)
+        assert info["cell_variant"] == v and info["max_b"] == 56 and info["max_m"] == 4
+        e = rel(tr, ref)
+        own, glob = per_receiver(tr, ref)
+        print(f"n_s {ns} FP32 variant {v}: rel L2 {e:.2e}, worst receiver {own:.2e} of its peak, "
+              f"{glob:.2e} of the global peak")
+        assert e <= 1e-4 and glob <= 1e-4 and own <= 1e-3
+
+
+@pytest.mark.parametrize("ns", [64, 128])
+def test_headline_shape_every_variant_fp64(headline, ns):
+    """FP64 on-line step (FP64 matrix instructions and the scalar kernel):
+    1e-10 globally and per receiver against its own peak."""
+    S, _ = _lib()
+    wl, run, ref = headline
+    ref = ref[:, :, :ns]
+    for v in range(5):
+        tr, info = _gpu(wl, S.SFROM_F64, run.dt, run.w, ns, variant=v)
+        assert info["cell_variant"] == v
+        e = rel(tr, ref)
+        own, glob = per_receiver(tr, ref)
+        print(f"n_s {ns} FP64 variant {v}: rel L2 {e:.2e}, worst receiver {own:.2e} of its peak")
+        assert e <= 1e-10 and own <= 1e-10
+
+
+def test_headline_shape_autotuned_equals_a_variant(headline):
+    """The autotuner's pick is one of the variants above, and its traces are
+    bitwise those of that variant pinned."""
+    S, _ = _lib()
+    wl, run, ref = headline
+    tr, info = _gpu(wl, S.SFROM_F32, run.dt, run.w, 64)
+    v = info["cell_variant"]
+    assert 0 <= v <= 4
+    pinned, _ = _gpu(wl, S.SFROM_F32, run.dt, run.w, 64, variant=v)
+    assert np.array_equal(tr, pinned)
+
+
+def test_fp64_case_as_configured(dev):
+    """32^3 voxels, 4^3 cells of 8^3, m = 4, 4 face + 2 edge + 1 corner
+    modes (b = 56 interior), one source at (20, 20, 16), 64 receivers, 1500
+    steps at half the fine CFL: FP64 end to end (GPU build and run) against
+    the oracle at 1e-10, globally and per receiver."""
+    S, _ = _lib()
+    wl = synth.workload("small", modes_face=4, modes_edge=2, m=4)
+    run = pipeline.setup(wl)
+    pipeline.build_all(run)
+    ref = pipeline.rom_traces(run)
+    tr, info = _gpu(wl, S.SFROM_F64, run.dt, run.w, 1)
+    e = rel(tr, ref)
+    own, _ = per_receiver(tr, ref)
+    print(f"FP64 config: {info['n_cells']} cells, max b {info['max_b']}: rel L2 {e:.2e}, worst receiver {own:.2e}")
+    assert info["max_b"] == 56 and len(run.w) == 1500
+    assert e <= 1e-10 and own <= 1e-9
+
+
+def test_deep_cells_six_to_eight_layers(dev):
+    """Cells of 6, 7 and 8 layers in one launch with 40 sources (a ragged
+    source tile): FP64 at 1e-10 and FP32 at 1e-4 against the oracle, every
+    cell-phase variant."""
+    S, _ = _lib()
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=8, n_steps=200)
+    fi = synth.face_interior_nodes(wl.nvox, wl.cuts)
+    wl.sources = fi[np.sort(np.random.default_rng(5).choice(len(fi), 40, replace=False))]
+    run = pipeline.setup(wl)
+    run.w = np.random.default_rng(6).standard_normal(len(run.w))
+    mpc = np.array([6, 7, 8, 8, 7, 6, 8, 6], np.int32)
+    for i in range(len(run.part.cells)):
+        Ai, bi = run.part.cell_operator(i, wl.sigma, wl.rho)
+        run.blocks[i] = build_cell(Ai, bi, run.part.cell_W(i), wl.shift, int(mpc[i]))
+    ref = pipeline.rom_traces(run)
+    for prec, tol in ((S.SFROM_F64, 1e-10), (S.SFROM_F32, 1e-4)):
+        for v in range(5):
+            tr, info = _gpu(wl, prec, run.dt, run.w, 40, variant=v, m_per_cell=mpc)
+            e = rel(tr, ref)
+            print(f"layers 6..8, prec {prec}, variant {v}: rel L2 {e:.2e}")
+            assert info["max_m"] == 8
+            assert e <= tol
