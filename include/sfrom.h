@@ -211,6 +211,26 @@ int sfrom_reset(sfrom_t* h);
 int sfrom_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int32_t w_on_device,
               void* traces, int32_t traces_on_device);
 
+/* sfrom_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same steps, kernels and results as sfrom_run, with no hipMalloc,
+ * hipFree or other allocating call. w[n_steps] (double) and traces
+ * (n_steps x n_r x n_s, as in sfrom_run) must be device pointers. The
+ * handle must already be prepared by a sfrom_run (any n_steps, also 0)
+ * since the last build, load, import, or change of sources or receivers,
+ * and, for a dt beyond the cells' Gershgorin bound, the ROM's largest
+ * eigenvalue must be known (sfrom_rom_lambda_max): ESTATE otherwise. The
+ * Phi^1 exchange buffer (sum of the cells' b_i times n_s values of the
+ * on-line precision) and the non-finite flag live in a static device array
+ * of 256 MiB per GPU, held until the process ends; a run that needs more
+ * returns EINVAL and steps nothing. Calls on one GPU share that array, so
+ * runs that overlap on one GPU (other streams, other handles, other
+ * threads) race: order them. The run is enqueued eagerly, is not timed by
+ * sfrom_profile, and synchronises the stream at its end for the non-finite
+ * check as sfrom_run does. Errors: as sfrom_run, plus ESTATE and EINVAL
+ * as above. */
+int sfrom_run_noalloc(sfrom_t* h, int64_t n_steps, double dt, const double* w, void* traces);
+
 /* Checkpoint of the on-line stage (the ROM is built "just once" for all
  * sources and time windows, Sec. 4.2 and Alg. alg1red stage 1): writes to
  * the file `path` a versioned binary record of the partition's cell and

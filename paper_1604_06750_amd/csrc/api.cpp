@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,7 +20,33 @@
 
 using namespace sfrom_impl;
 
+// Device memory of sfrom_run_noalloc, for callers that cannot allocate: the
+// non-finite flag (first 256 bytes) and the Phi^1 exchange buffer of the
+// on-line step. A file-scope array, so each GPU the library runs on holds
+// one copy until the process ends; all calls on one GPU share it.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
+constexpr size_t NOALLOC_FLAG_BYTES = 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// Device address of `scratch` on each GPU (host code must not use the
+// array's name, which is a host-side stand-in). Set once per device by
+// sfrom_create with that device current.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+hipError_t init_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
 
 struct Fail {
   int code;
@@ -931,7 +958,7 @@ void prepare_online(sfrom_t* h) {
 // max b, max m, n_s), every kernel variant is timed over a few launches on
 // scratch copies of the state (the real state is not touched) and the
 // fastest is kept for the life of the handle.
-int autotune_cell(sfrom_t* h, StepArgs a) {
+int autotune_cell(sfrom_t* h, StepArgs a, bool noalloc = false) {
   if (h->pinned_variant >= 0) {
     h->tuned_variant = std::min(h->pinned_variant, cell_variants(a) - 1);
     return h->tuned_variant;
@@ -939,6 +966,7 @@ int autotune_cell(sfrom_t* h, StepArgs a) {
   const auto key = std::make_tuple(a.prec, a.max_b, a.max_m, a.ns);
   auto it = h->tuned.find(key);
   if (it != h->tuned.end()) return it->second;
+  REQUIRE(!noalloc, SFROM_ESTATE, "the cell-phase kernel is not tuned for these sizes: call sfrom_run once first");
   const int nv = cell_variants(a);
   if (nv <= 1) { h->tuned[key] = 0; return 0; }
   const size_t eb = prec_bytes(h->prec);
@@ -999,9 +1027,11 @@ double rom_lambda_exact(sfrom_t* h);
 // dt^2 lambda_max < 4). The cheap sufficient test uses the cells' Gershgorin
 // bound (valid for blocks built from the cells' pencils); only when it fails,
 // or for imported blocks, is the ROM's own largest eigenvalue computed.
-void check_cfl(sfrom_t* h, double dt) {
+void check_cfl(sfrom_t* h, double dt, bool noalloc = false) {
   const double d2 = dt * dt;
   if (!h->rom_imported && h->lam_cells > 0.0 && d2 * h->lam_cells < 4.0) return;
+  REQUIRE(!noalloc || h->lam_rom >= 0.0, SFROM_ESTATE,
+          "the ROM's largest eigenvalue is needed for this dt: call sfrom_rom_lambda_max or sfrom_run first");
   const double lam = rom_lambda_exact(h);
   char msg[160];
   std::snprintf(msg, sizeof msg, "dt = %.6g exceeds the leapfrog stability limit 2/sqrt(lambda_max) = %.6g of the ROM",
@@ -1009,7 +1039,13 @@ void check_cfl(sfrom_t* h, double dt) {
   REQUIRE(d2 * lam < 4.0, SFROM_ECFL, msg);
 }
 
-void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_device, void* traces, int traces_on_device) {
+// With `noalloc` (sfrom_run_noalloc) the run allocates no device memory:
+// w and traces are device pointers, the handle must already be prepared
+// for its sources, receivers and ROM (a previous sfrom_run), and the Phi^1
+// exchange buffer and the non-finite flag live in `scratch`; the run is
+// enqueued eagerly (no graph capture) and without profiling events.
+void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_device, void* traces, int traces_on_device,
+         bool noalloc = false) {
   REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
   REQUIRE(h->built, SFROM_ESTATE, "no ROM: call sfrom_build first");
   REQUIRE(n_steps >= 0, SFROM_EINVAL, "n_steps < 0");
@@ -1018,8 +1054,23 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   if (!w_on_device)
     for (int64_t k = 0; k < n_steps; ++k)
       REQUIRE(std::isfinite(w[k]), SFROM_ENONFINITE, "wavelet sample " + std::to_string(k) + " is not finite");
+  void* noalloc_base = nullptr;
+  if (noalloc) {
+    REQUIRE(w_on_device && traces_on_device, SFROM_EINVAL, "sfrom_run_noalloc takes device pointers only");
+    REQUIRE(!h->masses_dirty && !h->src_dirty && !h->rec_dirty && h->state_ns == h->src.count && h->src.count > 0,
+            SFROM_ESTATE,
+            "the on-line stage is not prepared for the current ROM, sources and receivers: call sfrom_run once first");
+    int64_t nu1 = 0;
+    for (auto& oc : h->ocells) nu1 += oc.b;
+    const size_t need = NOALLOC_FLAG_BYTES + (size_t)nu1 * h->src.count * prec_bytes(h->prec);
+    REQUIRE(need <= NOALLOC_SCRATCH_BYTES, SFROM_EINVAL,
+            "sfrom_run_noalloc needs " + std::to_string(need) + " bytes of scratch, more than its maximum of " +
+                std::to_string(NOALLOC_SCRATCH_BYTES) + " (use sfrom_run, or fewer sources)");
+    REQUIRE(h->device < MAX_DEVICES && g_scratch_ptr[h->device], SFROM_EDEVICE, "no scratch address for this device");
+    noalloc_base = g_scratch_ptr[h->device];
+  }
   update_masses(h);
-  if (n_steps > 0) check_cfl(h, dt);
+  if (n_steps > 0) check_cfl(h, dt, noalloc);
   prepare_online(h);
   const int ns = h->src.count, nr = h->rec.count;
   const size_t eb = prec_bytes(h->prec);
@@ -1028,6 +1079,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   bool own = false;
   if (!traces_on_device && tbytes > 0) { d_tr = dalloc<unsigned char>(h, tbytes); own = true; }
   const double* d_w = stage_w(h, n_steps, w, w_on_device);
+  const bool profiling = h->profiling && !noalloc;
   StepArgs a;
   a.ncell = (int32_t)h->ocells.size();
   a.npiece = (int32_t)h->opieces.size();
@@ -1039,7 +1091,8 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   a.dt2 = dt * dt;
   a.d_cells = h->d_ocells; a.d_pieces = h->d_opieces; a.d_gather = h->d_gather; a.d_inc = h->d_inc;
   a.d_blocks = h->d_blocks; a.d_minv = h->d_minv; a.d_src = h->d_src;
-  a.phi = h->d_phi; a.w = d_w;
+  a.phi = noalloc ? static_cast<unsigned char*>(noalloc_base) + NOALLOC_FLAG_BYTES : h->d_phi;
+  a.w = d_w;
   a.d_rptr = h->d_rptr; a.d_rrow = h->d_rrow; a.d_rval = h->d_rval;
   a.d_prec_ptr = h->rec_fused ? h->d_prec_ptr : nullptr;
   a.d_prec_list = h->rec_fused ? h->d_prec_list : nullptr;
@@ -1059,14 +1112,14 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
       ab.nlist = bk.count;
       ab.max_b = bk.max_b;
       ab.max_m = bk.max_m;
-      bk.variant = ab.cell_variant = autotune_cell(h, ab);
+      bk.variant = ab.cell_variant = autotune_cell(h, ab, noalloc);
       ba.push_back(ab);
       if (bk.count > h->buckets[largest].count) largest = (int)k;
     }
     h->tuned_variant = h->buckets[largest].variant;
     a.cell_variant = h->tuned_variant;
   } else {
-    a.cell_variant = autotune_cell(h, a);
+    a.cell_variant = autotune_cell(h, a, noalloc);
   }
   auto cell_phase = [&](const StepArgs& x, hipStream_t st) -> hipError_t {
     if (!use_buckets) return launch_cell_phase(x, st);
@@ -1078,7 +1131,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
     }
     return hipSuccess;
   };
-  const bool graph = h->use_graph && !h->profiling && n_steps > 0;
+  const bool graph = h->use_graph && !h->profiling && n_steps > 0 && !noalloc;
   std::vector<int64_t> key;
   if (graph) {
     double dtv = dt;
@@ -1112,12 +1165,12 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
       a.y_cur = h->d_y[cur]; a.y_old = h->d_y[1 - cur];
       a.h_cur = h->d_h[cur]; a.h_old = h->d_h[1 - cur];
       a.step = s; a.trace_step = s;
-      const bool sample = s % h->prof_every == 0;
+      const bool sample = profiling && s % h->prof_every == 0;
       timed(h, 0, sample, [&] { return cell_phase(a, ls); });
       timed(h, 1, sample, [&] { return launch_piece_phase(a, ls); });
       if (!h->rec_fused) timed(h, 2, sample, [&] { return launch_receivers(a, ls); });
       cur = 1 - cur;
-      if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
+      if (profiling && ((s + 1) % 1024) == 0) collect_events(h);
     }
     if (graph) {
       hipGraph_t g = nullptr;
@@ -1145,13 +1198,17 @@ done:
     // a reduced-precision ROM can lose the stability of the leap-frog scheme
     // (rounded blocks of a deep layer need not stay definite); report it
     // instead of returning garbage
-    if (!h->d_flag) h->d_flag = dalloc<int32_t>(h, 1);
-    HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), h->stream));
+    int32_t* d_flag = static_cast<int32_t*>(noalloc_base);
+    if (!noalloc) {
+      if (!h->d_flag) h->d_flag = dalloc<int32_t>(h, 1);
+      d_flag = h->d_flag;
+    }
+    HIPCHK(launch_zero_flag(d_flag, h->stream));
     const int64_t npd = h->piece_dof_off.back();
-    HIPCHK(launch_nonfinite(h->d_y[h->cur], npd * ns, h->prec, h->d_flag, h->stream));
-    HIPCHK(launch_nonfinite(h->d_h[h->cur], h->n_hidden_rows * ns, h->prec, h->d_flag, h->stream));
+    HIPCHK(launch_nonfinite(h->d_y[h->cur], npd * ns, h->prec, d_flag, h->stream));
+    HIPCHK(launch_nonfinite(h->d_h[h->cur], h->n_hidden_rows * ns, h->prec, d_flag, h->stream));
     int32_t flag = 0;
-    HIPCHK(hipMemcpyAsync(&flag, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&flag, d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     REQUIRE(flag == 0, SFROM_ENONFINITE,
             "the ROM state became non-finite: the scheme is unstable for this dt in this storage precision");
@@ -1669,6 +1726,7 @@ int sfrom_create(sfrom_t** out, int device, void* hip_stream) {
   h->device = device;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess) { delete h; return SFROM_EDEVICE; }
+  if (init_scratch(device) != hipSuccess) { delete h; return SFROM_EDEVICE; }
   *out = h;
   return SFROM_OK;
 }
@@ -2002,6 +2060,12 @@ int sfrom_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int32_t w
               int32_t traces_on_device) {
   API_BEGIN(h)
   run(h, n_steps, dt, w, w_on_device, traces, traces_on_device);
+  API_END(h)
+}
+
+int sfrom_run_noalloc(sfrom_t* h, int64_t n_steps, double dt, const double* w, void* traces) {
+  API_BEGIN(h)
+  run(h, n_steps, dt, w, 1, traces, 1, true);
   API_END(h)
 }
 

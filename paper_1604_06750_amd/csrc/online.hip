@@ -820,6 +820,15 @@ __global__ __launch_bounds__(256) void k_nonfinite(const T* __restrict__ x, int6
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+// Writes zero to one int32 (a kernel, not a memset, so that callers which
+// capture the run into a graph record no memset node).
+__global__ void k_zero_flag(int32_t* flag) { *flag = 0; }
+
+hipError_t launch_zero_flag(int32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, st, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_nonfinite(const void* x, int64_t n, int prec, int32_t* flag, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>(2048, (n + 255) / 256);

@@ -205,6 +205,7 @@ hipError_t surrogate_predict(sfrom_surrogate* s, const float* x, int n, float* o
 // ORs 1 into *flag if any of n state values (double for F64, else float) is
 // not finite
 hipError_t launch_nonfinite(const void* x, int64_t n, int prec, int32_t* flag, hipStream_t st);
+hipError_t launch_zero_flag(int32_t* flag, hipStream_t st);
 int cell_variants(const StepArgs& a);
 
 // Fine-grid leapfrog step (CSR).

@@ -70,6 +70,7 @@ _SIGS = {
     "sfrom_save": [_P, C.c_char_p],
     "sfrom_load": [_P, C.c_char_p],
     "sfrom_run": [_P, C.c_int64, C.c_double, _P, C.c_int32, _P, C.c_int32],
+    "sfrom_run_noalloc": [_P, C.c_int64, C.c_double, _P, _P],
     "sfrom_fine_reset": [_P],
     "sfrom_fine_run": [_P, C.c_int64, C.c_double, _P, C.c_int32, _P, C.c_int32, C.c_int32],
     "sfrom_fine_lambda_max": [_P, C.POINTER(C.c_double)],
@@ -309,6 +310,15 @@ def sfrom_run(h, n_steps, dt, w, traces):
     wp, wdev, keep = _wave_arg(w)
     tp, tdev = _trace_arg(traces)
     _check(h, _lib.sfrom_run(h, n_steps, dt, wp, wdev, tp, tdev))
+
+
+def sfrom_run_noalloc(h, n_steps, dt, w, traces):
+    """sfrom_run without device allocation: w (float64) and traces (on-line
+    precision, n_steps x n_r x n_s) must be contiguous GPU torch tensors."""
+    _check_buffers(h, n_steps, w, traces, sfrom_get_info(h)["online_prec"])
+    wp = _device_tensor(w, "wavelet")
+    tp = _device_tensor(traces, "traces")
+    _check(h, _lib.sfrom_run_noalloc(h, n_steps, dt, wp, tp))
 
 
 def sfrom_fine_reset(h):
