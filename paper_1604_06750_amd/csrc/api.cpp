@@ -153,6 +153,7 @@ void free_fine(sfrom_t* h) {
   dfree(h->d_frowptr); dfree(h->d_fcol); dfree(h->d_fa); dfree(h->d_fbinv);
   dfree(h->d_u[0]); dfree(h->d_u[1]);
   dfree(h->d_fsrc_row); dfree(h->d_fsrc_col); dfree(h->d_fsrc_val);
+  dfree(h->d_fsrc_idx); dfree(h->d_fsrc_dense); h->fsrc_dense_prec = -1;
   dfree(h->d_frec_ptr); dfree(h->d_frec_row); dfree(h->d_frec_val);
   h->fine_prec = -1; h->fine_ns = -1; h->fine_io_dirty = true;
 }
@@ -1242,10 +1243,14 @@ void prepare_fine(sfrom_t* h, int prec) {
     }
     dfree(h->d_stencil);
     if (!h->stencil.empty()) {
+      // padded by FINE_PAD nodes of zero coefficients (unconditional row loads)
       if (prec == SFROM_F64) {
-        h->d_stencil = dupload(h, h->stencil);
+        std::vector<double> sd(h->stencil);
+        sd.resize(sd.size() + (size_t)FINE_PAD * 8, 0.0);
+        h->d_stencil = dupload(h, sd);
       } else {
         std::vector<float> sf(h->stencil.begin(), h->stencil.end());
+        sf.resize(sf.size() + (size_t)FINE_PAD * 8, 0.0f);
         h->d_stencil = dupload(h, sf);
       }
     }
@@ -1270,12 +1275,36 @@ void prepare_fine(sfrom_t* h, int prec) {
     h->d_frec_row = dupload(h, h->rec.row);
     h->d_frec_val = dupload(h, h->rec.val);
     h->fine_io_dirty = false;
+    dfree(h->d_fsrc_idx); dfree(h->d_fsrc_dense); h->fsrc_dense_prec = -1;
+  }
+  if (!h->stencil.empty() && h->fsrc_dense_prec != prec) {
+    // point sources of the Cartesian kernel: a dense row of n_s values per
+    // node that carries a source entry
+    std::vector<int32_t> idx(h->n + FINE_PAD, -1);
+    int32_t rows = 0;
+    for (int j = 0; j < ns; ++j)
+      for (int64_t k = h->src.colptr[j]; k < h->src.colptr[j + 1]; ++k)
+        if (idx[h->src.row[k]] < 0) idx[h->src.row[k]] = rows++;
+    std::vector<double> dense((size_t)std::max(rows, 1) * ns, 0.0);
+    for (int j = 0; j < ns; ++j)
+      for (int64_t k = h->src.colptr[j]; k < h->src.colptr[j + 1]; ++k)
+        dense[(size_t)idx[h->src.row[k]] * ns + j] += h->src.val[k];
+    dfree(h->d_fsrc_idx); dfree(h->d_fsrc_dense);
+    h->d_fsrc_idx = dupload(h, idx);
+    if (prec == SFROM_F64) {
+      h->d_fsrc_dense = dupload(h, dense);
+    } else {
+      std::vector<float> f(dense.begin(), dense.end());
+      h->d_fsrc_dense = dupload(h, f);
+    }
+    h->fsrc_dense_prec = prec;
   }
   if (h->fine_ns != ns) {
     for (int k = 0; k < 2; ++k) {
       dfree(h->d_u[k]);
-      h->d_u[k] = dalloc<unsigned char>(h, (size_t)h->n * ns * eb);
-      HIPCHK(hipMemsetAsync(h->d_u[k], 0, (size_t)h->n * ns * eb, h->stream));
+      // FINE_PAD nodes of padding for the Cartesian kernel's row loads
+      h->d_u[k] = dalloc<unsigned char>(h, (size_t)(h->n + FINE_PAD) * ns * eb);
+      HIPCHK(hipMemsetAsync(h->d_u[k], 0, (size_t)(h->n + FINE_PAD) * ns * eb, h->stream));
     }
     h->fine_ns = ns;
     h->fcur = 0;
@@ -1303,12 +1332,21 @@ void fine_run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_
   a.nsrc_entries = h->fsrc_n; a.src_row = h->d_fsrc_row; a.src_col = h->d_fsrc_col; a.src_val = h->d_fsrc_val;
   a.rec_ptr = h->d_frec_ptr; a.rec_row = h->d_frec_row; a.rec_val = h->d_frec_val;
   a.traces = d_tr;
+  a.src_idx = h->d_fsrc_idx;
+  a.src_dense = h->d_fsrc_dense;
+  a.src_dense_ok = (h->d_fsrc_idx != nullptr && h->fsrc_dense_prec == prec) ? 1 : 0;
   for (int64_t s = 0; s < n_steps; ++s) {
     a.u_cur = h->d_u[h->fcur]; a.u_old = h->d_u[1 - h->fcur];
     a.step = s; a.trace_step = s;
     timed(h, 3, s % h->prof_every == 0, [&] { return launch_fine_step(a, h->stream); });
     h->fcur = 1 - h->fcur;
     if (h->profiling && ((s + 1) % 1024) == 0) collect_events(h);
+  }
+  if (n_steps > 0 && fine_uses_25d(a)) {
+    // each step wrote the traces of the level it read; the last level's
+    a.u_cur = h->d_u[h->fcur];
+    a.trace_step = n_steps - 1;
+    HIPCHK(launch_fine_rec_level(a, h->stream));
   }
   if (own) {
     HIPCHK(hipMemcpyAsync(traces, d_tr, tbytes, hipMemcpyDeviceToHost, h->stream));

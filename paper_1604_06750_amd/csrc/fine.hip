@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sfrom_internal.h"
 
 namespace sfrom_impl {
@@ -150,6 +152,181 @@ __global__ __launch_bounds__(FNT) void k_fine_stencil(FineArgs a, int64_t nblk) 
   }
 }
 
+// Traces of level `lv` (a state array) for trace step ts, one thread per
+// (receiver, source), r_gid counting from 0.
+template <typename T>
+__device__ inline void fine_receiver(const FineArgs& a, const T* __restrict__ lv, int64_t ts, int64_t r_gid) {
+  if (r_gid >= (int64_t)a.nrec * a.ns) return;
+  const int r = (int)(r_gid / a.ns), s = (int)(r_gid % a.ns);
+  T acc = 0;
+  for (int64_t k = a.rec_ptr[r]; k < a.rec_ptr[r + 1]; ++k) acc += (T)a.rec_val[k] * lv[a.rec_row[k] * a.ns + s];
+  reinterpret_cast<T*>(a.traces)[(ts * a.nrec + r) * a.ns + s] = acc;
+}
+
+// Cartesian 7-point step with 2.5D blocking, for n_s a multiple of 64. A
+// workgroup owns a TX x TY tile of (x, y) columns and one group of 64
+// sources (lane = source), and marches a segment of z planes; wave w owns
+// tile row w (TX consecutive columns). The values of its columns at planes
+// z - 1, z and z + 1 stay in registers, so along z every state value is
+// read from HBM once; the +-y neighbours and the row ends come from an LDS
+// copy of plane z (the tile plus its one-node ring, which the waves load
+// from the neighbouring tiles). Loads of plane z + 2, of the ring of plane
+// z + 1 and of the next plane's old values, coefficients and source
+// indices are issued one plane ahead. A row's coefficients (8 per node)
+// are one coalesced load, broadcast to the lanes through LDS. A point
+// source at a node adds w^n g to its flux (source rows of dense values,
+// index per node). The old level is streamed with non-temporal loads and
+// stores, so that the current level's planes, which neighbouring tiles
+// re-read as their rings, stay in L2. The state, coefficient and
+// source-index arrays are
+// padded by FINE_PAD nodes, so a row's loads are issued unconditionally
+// and the values of columns beyond the grid are dropped. The workgroups
+// after the tiles compute the traces of the level that this launch reads
+// (the previous step's output), so the step is one launch.
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(64 * TY) void k_fine_25d(FineArgs a, int ntx, int nty, int zseg, int nzs,
+                                                      int64_t ntile, int64_t tile_grid) {
+  if ((int64_t)blockIdx.x >= tile_grid) {
+    if (a.trace_step > 0)
+      fine_receiver<T>(a, reinterpret_cast<const T*>(a.u_cur), a.trace_step - 1,
+                       ((int64_t)blockIdx.x - tile_grid) * blockDim.x + threadIdx.x);
+    return;
+  }
+  // workgroups are dealt to the 8 XCDs round-robin: each XCD gets a
+  // contiguous range of tiles, so neighbouring tiles (whose rows form each
+  // other's rings) share that XCD's L2
+  const int64_t per = tile_grid / 8;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= ntile) return;
+  extern __shared__ __align__(16) unsigned char f25_raw[];
+  T* pl = reinterpret_cast<T*>(f25_raw);
+  constexpr int PX = TX + 2, PY = TY + 2, NPL = PX * PY * 64, PLANE = NPL + TY * TX * 8;
+  constexpr int NH = 2 * (TX + TY), NHW = NH / TY;   // ring nodes, per wave
+  static_assert(NH % TY == 0 && TX * 8 == 64, "8 columns per row, ring split evenly over the waves");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tx = (int)(t % ntx);
+  int64_t rr = t / ntx;
+  const int ty = (int)(rr % nty);
+  rr /= nty;
+  const int zs = (int)(rr % nzs);
+  const int sg = (int)(rr / nzs);
+  const int ux = a.ux, uy = a.uy, uz = a.uz, ns = a.ns;
+  const int x0 = tx * TX, y0 = ty * TY, y = y0 + w;
+  const int zb = zs * zseg, ze = min(zb + zseg, uz);
+  // lane's source column in every state array
+  const T* __restrict__ u = reinterpret_cast<const T*>(a.u_cur) + sg * 64 + lane;
+  T* __restrict__ uo = reinterpret_cast<T*>(a.u_old) + sg * 64 + lane;
+  const T* __restrict__ cf = reinterpret_cast<const T*>(a.stencil);
+  const T* __restrict__ gs = reinterpret_cast<const T*>(a.src_dense) + sg * 64 + lane;
+  const T dt2 = (T)a.dt2;
+  const int ncol = min(TX, ux - x0);                 // columns of the tile inside the grid
+  const bool rowok = y < uy;
+  const int yc = min(y, uy - 1);
+  // first node of this wave's row in plane z (z clamped into the grid)
+  auto row0 = [&](int z) -> int64_t { return x0 + (int64_t)ux * (yc + (int64_t)uy * min(max(z, 0), uz - 1)); };
+  // the row's TX values of plane z, zero off the grid
+  auto ld_cols = [&](int z, T (&v)[TX]) {
+    const T* p = u + row0(z) * ns;
+    const bool ok = rowok && z >= 0 && z < uz;
+#pragma unroll
+    for (int i = 0; i < TX; ++i) {
+      const T x = p[(int64_t)i * ns];
+      v[i] = (ok && i < ncol) ? x : (T)0;
+    }
+  };
+  // ring node j of this wave: left and right columns, then bottom and top
+  // rows (tile coordinates)
+  int hx[NHW], hy[NHW];
+#pragma unroll
+  for (int j = 0; j < NHW; ++j) {
+    const int q = w + j * TY;
+    if (q < TY) { hx[j] = -1; hy[j] = q; }
+    else if (q < 2 * TY) { hx[j] = TX; hy[j] = q - TY; }
+    else if (q < 2 * TY + TX) { hx[j] = q - 2 * TY; hy[j] = -1; }
+    else { hx[j] = q - 2 * TY - TX; hy[j] = TY; }
+  }
+  auto ld_ring = [&](int z, T (&v)[NHW]) {
+#pragma unroll
+    for (int j = 0; j < NHW; ++j) {
+      const int xx = x0 + hx[j], yy = y0 + hy[j];
+      const bool ok = xx >= 0 && xx < ux && yy >= 0 && yy < uy && z >= 0 && z < uz;
+      const int64_t nd = ok ? xx + (int64_t)ux * (yy + (int64_t)uy * z) : 0;
+      const T x = u[nd * ns];
+      v[j] = ok ? x : (T)0;
+    }
+  };
+  // per-row data of plane z: the row's 64 coefficients (one per lane), old
+  // values, source index (lanes < TX)
+  auto ld_row = [&](int z, T& c, T (&o)[TX], int& sidx) {
+    const int64_t r0 = row0(z);
+    c = cf[r0 * 8 + lane];
+    const T* p = uo + r0 * ns;
+#pragma unroll
+    for (int i = 0; i < TX; ++i) o[i] = __builtin_nontemporal_load(p + (int64_t)i * ns);
+    sidx = a.src_idx[r0 + (lane & (TX - 1))];
+  };
+  T zm[TX], zc[TX], zp[TX], zq[TX], hz[NHW], hn[NHW], oc[TX], on[TX];
+  T cc, cn;
+  int sc, sn;
+  ld_cols(zb - 1, zm);
+  ld_cols(zb, zc);
+  ld_cols(zb + 1, zp);
+  ld_ring(zb, hz);
+  ld_row(zb, cc, oc, sc);
+  const T wn = (T)a.w[a.step];
+  for (int z = zb; z < ze; ++z) {
+    // loads one plane ahead
+    ld_cols(z + 2, zq);
+    ld_ring(z + 1, hn);
+    ld_row(min(z + 1, ze - 1), cn, on, sn);
+    // plane z and the row's coefficients into LDS
+    T* P = pl + (z & 1) * PLANE;
+    T* C = P + NPL + w * TX * 8;
+#pragma unroll
+    for (int i = 0; i < TX; ++i) P[((w + 1) * PX + i + 1) * 64 + lane] = zc[i];
+#pragma unroll
+    for (int j = 0; j < NHW; ++j) P[((hy[j] + 1) * PX + hx[j] + 1) * 64 + lane] = hz[j];
+    C[lane] = cc;
+    __syncthreads();
+    if (rowok) {
+      T* po = uo + row0(z) * ns;
+#pragma unroll
+      for (int i = 0; i < TX; ++i) {
+        if (i >= ncol) break;
+        T c[8];   // same LDS address in every lane: a broadcast read
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = C[i * 8 + k];
+        const T xm = (i > 0) ? zc[i - 1] : P[((w + 1) * PX) * 64 + lane];
+        const T xp = (i < TX - 1) ? zc[i + 1] : P[((w + 1) * PX + TX + 1) * 64 + lane];
+        const T ym = P[(w * PX + i + 1) * 64 + lane];
+        const T yp = P[((w + 2) * PX + i + 1) * 64 + lane];
+        T acc = c[6] * zc[i];
+        acc += c[0] * xm;
+        acc += c[1] * xp;
+        acc += c[2] * ym;
+        acc += c[3] * yp;
+        acc += c[4] * zm[i];
+        acc += c[5] * zp[i];
+        const int si = __builtin_amdgcn_readlane(sc, i);
+        if (si >= 0) acc += wn * gs[(int64_t)si * ns];
+        __builtin_nontemporal_store((T)2 * zc[i] - oc[i] + dt2 * c[7] * acc, po + (int64_t)i * ns);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TX; ++i) { zm[i] = zc[i]; zc[i] = zp[i]; zp[i] = zq[i]; oc[i] = on[i]; }
+#pragma unroll
+    for (int j = 0; j < NHW; ++j) hz[j] = hn[j];
+    cc = cn;
+    sc = sn;
+  }
+}
+
+// Traces of the final level of a run of k_fine_25d launches.
+template <typename T>
+__global__ void k_fine_rec_level(FineArgs a) {
+  fine_receiver<T>(a, reinterpret_cast<const T*>(a.u_cur), a.trace_step, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 template <typename T>
 __global__ void k_fine_src(FineArgs a) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,8 +349,50 @@ __global__ void k_fine_rec(FineArgs a) {
   reinterpret_cast<T*>(a.traces)[(a.trace_step * a.nrec + r) * a.ns + s] = acc;
 }
 
+// 2.5D tiles of 8 x 8 columns: two LDS planes of (TX + 2)(TY + 2) nodes x
+// 64 sources plus the tile's coefficients (float: 3 workgroups per CU)
+template <typename T>
+struct Tile25 {
+  static constexpr int TX = 8, TY = 8;
+};
+
+template <typename T>
+static hipError_t fine_25d_impl(const FineArgs& a, hipStream_t st) {
+  constexpr int TX = Tile25<T>::TX, TY = Tile25<T>::TY;
+  const int ntx = (a.ux + TX - 1) / TX, nty = (a.uy + TY - 1) / TY, nsg = a.ns / 64;
+  const int64_t cols = (int64_t)ntx * nty * nsg;
+  // z segments: about 1024 workgroups in all, each segment at least 8 planes
+  int nzs = (int)std::min<int64_t>(std::max<int64_t>((1024 + cols - 1) / cols, 1), (a.uz + 7) / 8);
+  nzs = std::max(nzs, 1);
+  const int zseg = (a.uz + nzs - 1) / nzs;
+  nzs = (a.uz + zseg - 1) / zseg;
+  const int64_t ntile = cols * nzs;
+  const int64_t tile_grid = (ntile + 7) / 8 * 8;
+  const int64_t nrt = (a.trace_step > 0) ? (int64_t)a.nrec * a.ns : 0;
+  const int64_t rgrid = (nrt + 64 * TY - 1) / (64 * TY);
+  const size_t lds = (size_t)2 * ((TX + 2) * (TY + 2) * 64 + TY * TX * 8) * sizeof(T);
+  static_assert(TX <= FINE_PAD, "arrays are padded by FINE_PAD nodes");
+  hipLaunchKernelGGL((k_fine_25d<T, TX, TY>), dim3(tile_grid + rgrid), dim3(64 * TY), lds, st, a, ntx, nty, zseg, nzs,
+                     ntile, tile_grid);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t fine_rec_level_impl(const FineArgs& a, hipStream_t st) {
+  const int64_t nr = (int64_t)a.nrec * a.ns;
+  if (nr > 0) hipLaunchKernelGGL(k_fine_rec_level<T>, dim3((nr + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+bool fine_uses_25d(const FineArgs& a) { return a.stencil != nullptr && a.ns % 64 == 0 && a.src_dense_ok; }
+
+hipError_t launch_fine_rec_level(const FineArgs& a, hipStream_t st) {
+  return (a.prec == SFROM_F64) ? fine_rec_level_impl<double>(a, st) : fine_rec_level_impl<float>(a, st);
+}
+
 template <typename T>
 static hipError_t fine_impl(const FineArgs& a, hipStream_t st) {
+  if (fine_uses_25d(a)) return fine_25d_impl<T>(a, st);
   const int64_t tot = (a.n + FR - 1) / FR * a.ns;
   const int64_t nblk = (tot + FNT - 1) / FNT;
   const int64_t grid = (nblk + 7) / 8 * 8;

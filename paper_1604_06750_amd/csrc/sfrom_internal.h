@@ -234,8 +234,21 @@ struct FineArgs {
   // x fastest, 8 coefficients per node: A to x-, x+, y-, y+, z-, z+, diag, 1/b
   const void* stencil;
   int32_t ux, uy, uz;
+  // point sources of the Cartesian form: per node the row of src_dense
+  // (n_s values of precision prec) that its flux adds w^n times, or -1
+  const int32_t* src_idx;
+  const void* src_dense;
+  int32_t src_dense_ok;          // src_idx / src_dense are set (2.5D kernel usable)
 };
 hipError_t launch_fine_step(const FineArgs& a, hipStream_t st);
+// The Cartesian step of n_s a multiple of 64 is one launch that also writes
+// the traces of the level it reads (trace step - 1); the traces of a run's
+// last level then need this launch (u_cur = that level, trace_step).
+bool fine_uses_25d(const FineArgs& a);
+// Nodes of padding after the fine state (n_s values each), stencil (8
+// values each) and source-index (1 each) arrays of the Cartesian kernel.
+constexpr int FINE_PAD = 64;
+hipError_t launch_fine_rec_level(const FineArgs& a, hipStream_t st);
 
 }  // namespace sfrom_impl
 
@@ -352,6 +365,9 @@ struct sfrom {
   int32_t* d_fsrc_col = nullptr;
   double* d_fsrc_val = nullptr;
   int64_t fsrc_n = 0;
+  int32_t* d_fsrc_idx = nullptr;   // Cartesian form: source row per node (-1: none)
+  void* d_fsrc_dense = nullptr;    // and the rows, n_s values each (fine precision)
+  int32_t fsrc_dense_prec = -1;
   int64_t* d_frec_ptr = nullptr;
   int64_t* d_frec_row = nullptr;
   double* d_frec_val = nullptr;
