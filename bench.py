@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "source-steps/s, ROM vs fine-grid leapfrog, at ≤1e-3 receiver rel-L2 error"
+GATE = 1e-3   # receiver rel-L2 of the ROM against the FP64 fine grid
 HBM_PEAK_GBS = 8000.0
 # per-kernel HIP events on one step in PROFILE_EVERY of the timed runs: an
 # event pair costs a few microseconds of stream time, so timing every launch
@@ -69,10 +70,11 @@ def _cell_b(S, h, i):
     return bd.value
 
 
-def traffic_from_profiles(kernel_file, workload):
+def traffic_from_profiles(kernel_file, tag):
     """HBM bytes per launch measured by rocprofv3 PMC counters (committed
-    summary), valid only while the kernel source is unchanged."""
-    path = os.path.join(ROOT, "profiles", f"cell_phase_{workload}_pmc.md")
+    summary for this workload and setting), valid only while the kernel
+    source is unchanged."""
+    path = os.path.join(ROOT, "profiles", f"cell_phase_{tag}_pmc.md")
     if not os.path.exists(path):
         return None
     sha = hashlib.sha256(open(kernel_file, "rb").read()).hexdigest()
@@ -138,6 +140,53 @@ def cpu_baseline(args, ns_target, nsteps_target, ncells_target, budget_s):
     }
 
 
+def extra_setting(S, problem, synth, args, stream, dev, tdt, prec, nt, dt, w, fine_ssps):
+    """The same job at 4 face + 2 edge modes and m = 4 (b = 56 for interior
+    cells), which misses the gate: its rate, error and cell-phase time, for
+    comparison with the gated setting (one warm-up job, three timed)."""
+    import torch
+    import numpy as np
+    wl = synth.workload(args.workload, modes_face=4, modes_edge=2, m=4)
+    h = S.sfrom_create(0, stream.cuda_stream)
+    try:
+        problem.setup(h, wl)
+        info = S.sfrom_get_info(h)
+        ns, nr = info["n_sources"], info["n_receivers"]
+        tr = torch.zeros((nt, nr, ns), dtype=tdt, device=dev)
+
+        def job():
+            S.sfrom_build(h, 4, wl.shift, prec)
+            S.sfrom_reset(h)
+            S.sfrom_run(h, nt, dt, w, tr)
+        job()
+        torch.cuda.synchronize()
+        S.sfrom_profile(h, PROFILE_EVERY)
+        S.sfrom_profile_read(h, S.KERNEL_CELL)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            job()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / 3
+        cell_ms, cell_n = S.sfrom_profile_read(h, S.KERNEL_CELL)
+        S.sfrom_profile(h, False)
+        rom = tr.double().cpu().numpy()
+        S.sfrom_fine_reset(h)
+        t64 = torch.zeros((nt, nr, ns), dtype=torch.float64, device=dev)
+        S.sfrom_fine_run(h, nt, dt, w, t64, S.SFROM_F64)
+        torch.cuda.synchronize()
+        ref = t64.cpu().numpy()
+        err = float(np.linalg.norm(rom - ref) / np.linalg.norm(ref))
+        bytes_, flops = algorithmic_cost(S, h, ns, args.prec)
+        avg = cell_ms / max(cell_n, 1)
+        return {"modes": "4 face + 2 edge + 1 corner", "m": 4, "max_b": info["max_b"],
+                "job_source_steps_per_s": round(ns * nt / t, 1), "rel_l2_vs_fine_fp64": err,
+                "meets_gate": bool(err <= GATE), "speedup_job_vs_fine": round(ns * nt / t / fine_ssps, 3),
+                "cell_phase_avg_ms": round(avg, 4),
+                "cell_phase_hbm_frac_at_algorithmic_bytes": round(bytes_ / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    finally:
+        S.sfrom_destroy(h)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,9 +194,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large")
     ap.add_argument("--time-steps", type=int, default=None, help="leapfrog steps per job (default: workload)")
-    ap.add_argument("--m", type=int, default=4)
-    ap.add_argument("--modes-face", type=int, default=4)
-    ap.add_argument("--modes-edge", type=int, default=2)
+    # the cheapest setting of the 128^3 workload whose traces are within the
+    # gate of the FP64 fine grid (layers 3 and 4, 4/9/12/16 face and 2/3
+    # edge modes measured: only 16 + 3 modes per face and edge pass)
+    ap.add_argument("--m", type=int, default=3)
+    ap.add_argument("--modes-face", type=int, default=16)
+    ap.add_argument("--modes-edge", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra measurement at 4 face + 2 edge modes, m = 4 (b = 56)")
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
@@ -275,7 +329,8 @@ def main():
     peak_tf = MFMA_PEAK_TFLOPS[args.prec]
     intensity = flops / bytes_
     ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
-    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_1604_06750_amd", "csrc", "online.hip"), args.workload)
+    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_1604_06750_amd", "csrc", "online.hip"),
+                                    f"{args.workload}_m{args.m}_f{args.modes_face}_e{args.modes_edge}")
     if intensity < ridge:
         roofline = {"bound": "hbm", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(bw / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -288,9 +343,16 @@ def main():
 
     fine_ssps = ns * nt / (fine_ms / 1e3)
     online_ssps = ns * nt / (online_ms / 1e3)
+    meets_gate = bool(rel_l2 <= GATE)
+    extra = None
+    if not args.no_extra:
+        extra = extra_setting(S, problem, synth, args, stream, dev, tdt, prec, nt, dt, w, fine_ssps)
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        # the metric is defined at the gate: no value when the traces miss it
+        "value": round(value, 1) if meets_gate else None,
+        "meets_gate": meets_gate,
+        "value_ungated": round(value, 1),
         "unit": "source-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -312,6 +374,7 @@ def main():
         "roofline": roofline,
         "rel_l2_vs_rom_fp64": rel_l2_rom64,
         "rel_l2_vs_fine_fp64": rel_l2,
+        "gate": GATE,
         "build_ms": round(float(np.mean(build_ms)), 2),
         "online_ms": round(online_ms, 2),
         "online_source_steps_per_s": round(online_ssps, 1),
@@ -323,6 +386,7 @@ def main():
                           # receivers that each read one piece are computed by the piece phase
                           "receivers": round(rec_ms / rec_n, 4) if rec_n else "in piece phase",
                           "fine_step": round(fine_kms / max(fine_kn, 1), 4)},
+        "extra_b56_m4": extra,
     }
     S.sfrom_destroy(h)
     if not args.no_cpu:
