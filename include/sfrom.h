@@ -270,11 +270,19 @@ int sfrom_rom_lambda_max(sfrom_t* h, double* lambda);
  * outputs). Runs with host pointers are captured afresh each time. */
 int sfrom_set_graph(sfrom_t* h, int32_t enable);
 
+/* Band kernels of the off-line build (Sec. 4.2: one Cholesky factorisation
+ * of -(A_i + s B_i) per cell serves every shifted solve): mode 0 (default)
+ * uses the blocked kernels, spread over many workgroups per cell, for half
+ * bandwidths above 128 and the one-workgroup-per-cell kernels otherwise;
+ * 1 always the blocked kernels; 2 never. The results agree to rounding.
+ * Meant for tests and tuning studies. Errors: EINVAL. */
+int sfrom_set_build_path(sfrom_t* h, int32_t mode);
+
 /* Kernel variant of the on-line cell phase: -1 (default) lets the
  * autotuner time the variants on the first run and keep the fastest; 0..3
- * pin a matrix-core tiling (FP32, BF16 or FP64 matrix instructions by the
- * on-line precision), 4 the scalar kernel. Meant for tests and tuning
- * studies. */
+ * and 5 pin a matrix-core tiling (FP32, BF16 or FP64 matrix instructions by
+ * the on-line precision; 5 has 16-source tiles, for partitions with few
+ * cells), 4 the scalar kernel. Meant for tests and tuning studies. */
 int sfrom_set_cell_variant(sfrom_t* h, int32_t variant);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around

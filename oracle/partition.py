@@ -119,6 +119,11 @@ class CartesianPartition:
     def cell_operator(self, i, sigma, rho):
         """Split operators (A_i dense, b_i) of cell i: the voxel sums of the
         fine assembly restricted to the voxels of the cell (eq. splitN_c)."""
+        Ai, b = self.cell_operator_sparse(i, sigma, rho)
+        return Ai.toarray(), b
+
+    def cell_operator_sparse(self, i, sigma, rho):
+        """The same (A_i, b_i) with A_i as a scipy sparse matrix (large cells)."""
         c = self.cells[i]
         lo, hi = c.vox_lo, c.vox_hi
         sg = sigma[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
@@ -134,7 +139,7 @@ class CartesianPartition:
         ux, uy = okx.sum(), oky.sum()
         lidx[X, Y, Z] = (X - X.min()) + ux * ((Y - Y.min()) + uy * (Z - Z.min()))
         cx, cy, cz = fine.edge_conductances(sg)
-        Ai = fine._laplacian_from_edges(cx, cy, cz, lidx).toarray()
+        Ai = fine._laplacian_from_edges(cx, cy, cz, lidx)
         mass = fine.node_masses(rh)
         bi = mass[X, Y, Z].ravel()
         order = lidx[X, Y, Z].ravel()

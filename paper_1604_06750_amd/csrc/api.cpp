@@ -20,6 +20,9 @@
 
 using namespace sfrom_impl;
 
+// Receivers per piece up to which the piece phase computes the traces.
+constexpr int MAX_FUSED_RECEIVERS = 8;
+
 // Device memory of sfrom_run_noalloc, for callers that cannot allocate: the
 // non-finite flag (first 256 bytes) and the Phi^1 exchange buffer of the
 // on-line step. A file-scope array, so each GPU the library runs on holds
@@ -548,6 +551,11 @@ void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
   // ---- per-cell workspace sizes -----------------------------------------------
   std::vector<BuildCell>& bcells = ctx.bcells;
   std::vector<int64_t>& wsize = ctx.wsize;
+  // the blocked build (any cell wider than WIDE_MIN_W, or forced) needs a
+  // region for partial Gram products in every cell of a batch
+  int max_w = 0;
+  for (int i = 0; i < nc; ++i) max_w = std::max(max_w, h->stage.bw[i]);
+  const bool any_wide = h->wide_mode == 1 || (h->wide_mode == 0 && max_w > WIDE_MIN_W);
   bcells.assign(nc, BuildCell{});
   wsize.assign(nc, 0);
   for (int i = 0; i < nc; ++i) {
@@ -567,6 +575,8 @@ void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
     bc.s_off = off; off += std::max(2 * mb * b, mb * b);
     bc.r_off = off; off += mb * b;
     bc.out_off = off; off += 2 * mb * b;
+    bc.p_off = off;
+    if (any_wide) off += ts_partials(n, bc.m, b);
     bc.status = 0;
     wsize[i] = off;
   }
@@ -597,11 +607,12 @@ void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
 template <class F>
 void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std::vector<int32_t>& list, F&& body) {
   if (list.empty()) return;
-  // workspace budget: up to 32 GiB (HBM holds 288 GB), at most half of the
-  // memory that is free now
+  // workspace budget: up to 128 GiB (HBM holds 288 GB; large cells need
+  // about 0.6 GB each, and fewer batches mean fewer, fuller launches), at
+  // most half of the memory that is free now
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
-  const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)32 << 30, (int64_t)(free_b / 2)));
+  const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)128 << 30, (int64_t)(free_b / 2)));
   int64_t wmax = 0;
   for (int32_t i : list) wmax = std::max(wmax, ctx.wsize[i]);
   int per_batch = o->cells_per_batch > 0 ? o->cells_per_batch : (int)list.size();
@@ -628,6 +639,7 @@ void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std
         const int64_t base = woff;
         bc.band_off += base; bc.v_off += base; bc.x_off += base; bc.av_off += base;
         bc.am_off += base; bc.q_off += base; bc.s_off += base; bc.r_off += base; bc.out_off += base;
+        bc.p_off += base;
         woff += ctx.wsize[i];
       }
       HIPCHK(hipMemcpy(d_bc, bcb.data(), cnt * sizeof(BuildCell), hipMemcpyHostToDevice));
@@ -637,6 +649,7 @@ void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std
       bb.max_w = 0;
       for (const BuildCell& x : bcb) bb.max_w = std::max(bb.max_w, x.w);
       bb.shift = o->shift;
+      bb.wide_mode = h->wide_mode;
       bb.d_cells = d_bc;
       bb.d_rowptr = st.d_rowptr; bb.d_col = st.d_col; bb.d_a = st.d_a; bb.d_bdiag = st.d_bdiag;
       bb.d_wrow = st.d_wrow; bb.d_wcol = st.d_wcol; bb.d_wsoff = st.d_wsoff; bb.d_wbp = st.d_wbp; bb.d_wkp = st.d_wkp;
@@ -940,6 +953,15 @@ void prepare_online(sfrom_t* h) {
     dfree(h->d_prec_ptr); dfree(h->d_prec_list);
     h->rec_fused = h->rec.count > 0;
     for (int r = 0; r < h->rec.count && h->rec_fused; ++r) h->rec_fused = h->rec.rptr[r + 1] - h->rec.rptr[r] == 1;
+    if (h->rec_fused) {
+      const int np = (int)h->pieces.size();
+      std::vector<int32_t> pptr(np + 1, 0), plist(h->rec.count);
+      for (int r = 0; r < h->rec.count; ++r) pptr[h->rec.rpiece[h->rec.rptr[r]] + 1]++;
+      // a piece-phase thread computes its piece's receivers one after the
+      // other: with many receivers on one piece (few, large pieces) the
+      // separate receivers kernel, one thread per receiver, is faster
+      h->rec_fused = *std::max_element(pptr.begin(), pptr.end()) <= MAX_FUSED_RECEIVERS;
+    }
     if (h->rec_fused) {
       const int np = (int)h->pieces.size();
       std::vector<int32_t> pptr(np + 1, 0), plist(h->rec.count);
@@ -2152,9 +2174,16 @@ int sfrom_set_graph(sfrom_t* h, int32_t enable) {
   API_END(h)
 }
 
+int sfrom_set_build_path(sfrom_t* h, int32_t mode) {
+  API_BEGIN(h)
+  REQUIRE(mode >= 0 && mode <= 2, SFROM_EINVAL, "mode must be 0 (automatic), 1 (blocked wide-band) or 2 (per-cell)");
+  h->wide_mode = mode;
+  API_END(h)
+}
+
 int sfrom_set_cell_variant(sfrom_t* h, int32_t variant) {
   API_BEGIN(h)
-  REQUIRE(variant >= -1 && variant < 5, SFROM_EINVAL, "variant must be -1 (autotune) or 0..4");
+  REQUIRE(variant >= -1 && variant < 6, SFROM_EINVAL, "variant must be -1 (autotune) or 0..5");
   h->pinned_variant = variant;
   API_END(h)
 }

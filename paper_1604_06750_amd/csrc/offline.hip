@@ -524,6 +524,26 @@ __global__ __launch_bounds__(NT) void k_normalize(BuildBatch bb, int j) {
   wg_trsm_right_lt(n, b, gram, b, q, n);
 }
 
+// Blocked build, normalisation of block j after the Gram matrix X^T B X has
+// been reduced into the small workspace: Cholesky R^T R of it (rank check as
+// k_normalize) and R_j kept; q_j = X R^{-1} follows row-parallel.
+__global__ __launch_bounds__(NT) void k_ts_chol(BuildBatch bb, int j) {
+  BuildCell& c = bb.d_cells[blockIdx.x];
+  if (cell_failed(c) || j >= c.m) return;
+  const int b = c.b;
+  double* gram = bb.d_work + c.s_off;
+  const double ratio = wg_potrf(b, gram, b);          // gram <- L (lower)
+  if (!(ratio > 1e-10)) {
+    if (threadIdx.x == 0) c.status = ST_BREAKDOWN;
+    return;
+  }
+  double* R = bb.d_work + c.r_off + (int64_t)j * b * b;
+  for (int idx = threadIdx.x; idx < b * b; idx += NT) {
+    const int r = idx % b, cc = idx / b;
+    R[r + (int64_t)cc * b] = (r <= cc) ? gram[cc + (int64_t)r * b] : 0.0;
+  }
+}
+
 // X = (A + sB)^{-1} B q_j = -C^{-1} (B q_j) with the banded factor.
 // Solves (L L^T) x = t for one right-hand side per lane: L is the band
 // Cholesky factor (column-major band, column c holding L[c..c+w][c]) and t
@@ -1032,11 +1052,44 @@ inline size_t chol_window_bytes(const BuildBatch& bb) {
   return (bb.max_w + 1 <= NT && bytes <= 64 * 1024) ? bytes : 0;
 }
 
+// Blocked build of a batch with wide bands: the same steps as launch_build
+// with the band factorisation, the shifted solves and the tall-skinny
+// products of the Krylov basis and of the projection spread over many
+// workgroups per cell; block Lanczos and the S-fraction (m b x m b dense
+// work) stay one workgroup per cell.
+static hipError_t launch_build_wide(const BuildBatch& bb, hipStream_t st) {
+  const dim3 grid(bb.ncell), block(NT);
+  hipError_t e = launch_wide_chol(bb, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_krylov_start, grid, block, 0, st, bb);
+  for (int j = 0; j < bb.max_m; ++j) {
+    if (j > 0)
+      for (int pass = 0; pass < 2; ++pass) {
+        if ((e = launch_ts_gram(bb, TS_CGS, j, st)) != hipSuccess) return e;
+        if ((e = launch_ts_update(bb, j, st)) != hipSuccess) return e;
+      }
+    if ((e = launch_ts_gram(bb, TS_NORM, j, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ts_chol, grid, block, 0, st, bb, j);
+    if ((e = launch_ts_trsm_rows(bb, j, st)) != hipSuccess) return e;
+    if (j + 1 < bb.max_m && (e = launch_wide_solve(bb, j, st)) != hipSuccess) return e;
+  }
+  if ((e = launch_ts_spmm(bb, st)) != hipSuccess) return e;
+  if ((e = launch_ts_gram(bb, TS_PROJ, 0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lanczos, grid, block, 0, st, bb);
+  hipLaunchKernelGGL(k_sfraction, grid, block, 0, st, bb);
+  return hipGetLastError();
+}
+
 hipError_t launch_build(const BuildBatch& bb, hipStream_t st) {
   const dim3 grid(bb.ncell), block(NT);
+  const bool wide = build_is_wide(bb, bb.wide_mode);
+  if (wide) return launch_build_wide(bb, st);
   const size_t cw = chol_window_bytes(bb);
-  if (cw) hipLaunchKernelGGL(k_band_chol_win, grid, block, cw, st, bb);
-  else hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bb);
+  if (cw) {
+    hipLaunchKernelGGL(k_band_chol_win, grid, block, cw, st, bb);
+  } else {
+    hipLaunchKernelGGL(k_band_chol, grid, block, 0, st, bb);
+  }
   hipLaunchKernelGGL(k_krylov_start, grid, block, 0, st, bb);
   for (int j = 0; j < bb.max_m; ++j) {
     hipLaunchKernelGGL(k_cgs2, grid, block, 0, st, bb, j);

@@ -566,6 +566,11 @@ static void launch_variant(const StepArgs& a, int variant, hipStream_t st) {
   constexpr int TS32 = tile_bytes(NCH, 3, 32, ES) <= LDS_BYTES ? 3 : 2;
   if ((variant == 0 && B3 > LDS_BYTES) || ((variant == 1 || variant == 2) && B2 > LDS_BYTES)) variant = 3;
   switch (variant) {
+    case 5:
+      // 16-source tiles: four times the workgroups of variant 0, for
+      // partitions with few (large) cells
+      launch_mfma<NCH, 1, 4, PM != 2, 3, lds_waves(NCH, tile_bytes(NCH, 3, 16, ES)), false, PM>(a, st);
+      break;
     case 0:
       if constexpr (B3 <= LDS_BYTES) launch_mfma<NCH, 4, 4, false, 3, lds_waves(NCH, B3), false, PM>(a, st);
       break;
@@ -780,15 +785,15 @@ static hipError_t rec_impl(const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int cell_variants(const StepArgs& a) { return a.max_b > 256 ? 1 : 5; }
+int cell_variants(const StepArgs& a) { return a.max_b > 256 ? 1 : 6; }
 
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st) {
   // variants 0..3: matrix-core kernel (FP32, BF16 blocks or FP64) with 4
   // chunks in flight and the register budget of the waves the LDS admits
   // (source tile 64 with three layer tiles; two tiles; two tiles with
   // per-tile B reads and the next layer read at its store; source tile 32);
-  // 4: the scalar kernel
-  if (a.max_b > 256 || a.cell_variant >= 4) {
+  // 4: the scalar kernel; 5: matrix cores with 16-source tiles
+  if (a.max_b > 256 || a.cell_variant == 4) {
     if (a.prec == SFROM_F64) return cell_impl<double, double, double>(a, st);
     if (a.prec == SFROM_F32) return cell_impl<float, float, float>(a, st);
     return cell_impl<float, __hip_bfloat16, float>(a, st);

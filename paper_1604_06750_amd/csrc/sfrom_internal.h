@@ -69,6 +69,7 @@ struct BuildCell {
   int64_t out_off;  // S-fraction output: 2 m b^2 (Ghat^1..m then G^1..m)
   int32_t status;   // per-cell status (written by kernels)
   int32_t pad;
+  int64_t p_off;    // blocked build only: partial Gram products, ceil(n / TS_ROWS) x max((m b)^2, m b^2)
 };
 
 // Per-cell on-line descriptor.
@@ -116,8 +117,31 @@ struct BuildBatch {
   const int32_t* d_wkp;       // k_p (leading dimension of S_p)
   const double* d_S;
   double* d_work;
+  int32_t wide_mode;          // 0: blocked wide-band kernels when max_w > WIDE_MIN_W; 1: always; 2: never
 };
 hipError_t launch_build(const BuildBatch& bb, hipStream_t st);
+// Blocked band factorisation and shifted solves over many workgroups per
+// cell (wide.hip), used for bands wider than WIDE_MIN_W.
+constexpr int WIDE_MIN_W = 128;
+// Rows per partial Gram product of the blocked build (a cell's n rows are
+// split into ceil(n / TS_ROWS) chunks summed in a fixed order).
+constexpr int TS_ROWS = 4096;
+inline int64_t ts_partials(int64_t n, int64_t m, int64_t b) {
+  const int64_t mb = m * b;
+  return ((n + TS_ROWS - 1) / TS_ROWS) * (mb * mb > mb * b ? mb * mb : mb * b);
+}
+bool build_is_wide(const BuildBatch& bb, int force);
+hipError_t launch_wide_chol(const BuildBatch& bb, hipStream_t st);
+hipError_t launch_wide_solve(const BuildBatch& bb, int j, hipStream_t st);
+// Tall-skinny steps of the blocked build: Gram products A^T diag(d) B
+// (mode TS_CGS: V[:, 0:jb]^T B X into the CGS coefficients; TS_NORM: X^T B X
+// into the Gram matrix; TS_PROJ: V^T (A V) into A^m), the CGS update
+// X -= V coef, q_j = X L^{-T} and the sparse product A V.
+enum { TS_CGS = 0, TS_NORM = 1, TS_PROJ = 2 };
+hipError_t launch_ts_gram(const BuildBatch& bb, int mode, int j, hipStream_t st);
+hipError_t launch_ts_update(const BuildBatch& bb, int j, hipStream_t st);
+hipError_t launch_ts_trsm_rows(const BuildBatch& bb, int j, hipStream_t st);
+hipError_t launch_ts_spmm(const BuildBatch& bb, hipStream_t st);
 
 // Learned off-line stage (cells of one batch): S-fraction from the
 // predicted factors y (one row of P floats per cell), its on-line blocks in
@@ -401,6 +425,7 @@ struct sfrom {
   bool use_graph = false;
   hipStream_t capture_stream = nullptr;   // private stream used for capture
   int pinned_variant = -1;                 // >= 0: cell-phase variant fixed by the caller
+  int wide_mode = 0;                       // band kernels of the build: 0 automatic, 1 blocked, 2 per-cell
   hipGraphExec_t graph_exec = nullptr;
   std::vector<int64_t> graph_key;
   int64_t graph_launches = 0;

@@ -20,6 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 SFROM_F64, SFROM_F32, SFROM_BF16 = 0, 1, 2
+CELL_VARIANTS = 6          # cell-phase kernel variants 0..5 (4: the scalar kernel)
 
 STATUS = {
     0: "OK", -1: "EINVAL", -2: "ENOTSYM", -3: "ENOTNSD", -4: "EBPOS", -5: "ESUPPORT",
@@ -78,6 +79,7 @@ _SIGS = {
     "sfrom_get_info": [_P, C.POINTER(sfrom_info)],
     "sfrom_set_graph": [_P, C.c_int32],
     "sfrom_set_cell_variant": [_P, C.c_int32],
+    "sfrom_set_build_path": [_P, C.c_int32],
     "sfrom_profile": [_P, C.c_int32],
     "sfrom_profile_read": [_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "sfrom_export_pencil": [_P, _P, _P, _P, _P],
@@ -346,6 +348,11 @@ def sfrom_rom_lambda_max(h) -> float:
 
 def sfrom_set_graph(h, enable=True):
     _check(h, _lib.sfrom_set_graph(h, int(enable)))
+
+
+def sfrom_set_build_path(h, mode=0):
+    """0 automatic, 1 blocked wide-band kernels, 2 one workgroup per cell."""
+    _check(h, _lib.sfrom_set_build_path(h, mode))
 
 
 def sfrom_set_cell_variant(h, variant=-1):

@@ -174,7 +174,8 @@ def _band(c_min: float, ppw: float = 10.0):
 def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optional[int] = None,
              m: Optional[int] = None, n_steps: Optional[int] = None,
              n_sources: Optional[int] = None, n_receivers: Optional[int] = None,
-             realisation: int = 0, ppw: float = 10.0) -> Workload:
+             realisation: int = 0, ppw: float = 10.0, cell: Optional[int] = None,
+             ncell: Optional[int] = None) -> Workload:
     """Build a named workload.
 
     ``tiny``   : 16^3 voxels, 2^3 cells of 8^3 (fast CPU tests)
@@ -191,7 +192,12 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
                  to the layers, per-cell layer count 3..8 from the cell size
                  (``extra['m_per_cell']``), 256 sources, 6000 steps
     ``layered_small``: the same recipe on 64x64x32 voxels (parity case)
+    ``paper``  : ``ncell``^3 (default 4^3) cubic cells of ``cell`` voxels
+                 (default 40) at ``ppw`` points per wavelength (default: one
+                 wavelength per cell), 64 sources, 32 x 32 receivers (the
+                 paper's example shape)
     """
+    extra_cell = cell
     mf = 9 if modes_face is None else modes_face
     me = 2 if modes_edge is None else modes_edge
     c_min = np.sqrt(1.0 / 2.0)        # sqrt(sigma_lo / rho_hi) of the generator bounds
@@ -325,6 +331,43 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
                     mpc.append(int(np.clip(round(3 + 5 * (v13 - 8) / 8), 3, 8)))
         wl.extra["m_per_cell"] = np.array(mpc, dtype=np.int32)
         return wl
+    if name == "paper":
+        # the shape of the paper's acoustic examples (Sec. 9): a fine grid far
+        # finer than the wavelength (``ppw`` points per shortest wavelength,
+        # 40 in the paper) split into 4^3 cubic cells of ``cell`` voxels (40 in
+        # the paper), i.e. about one wavelength per cell at the band edge. The
+        # medium is the acoustic generator with its correlation lengths scaled
+        # with the wavelength (6 and 2 voxels at 10 points per wavelength), so
+        # the medium per wavelength matches the 8^3-cell workloads. 64 sources
+        # on an 8 x 8 grid on the first interior z-interface below the top
+        # wall and 32 x 32 receivers on the first one above the bottom wall
+        # (the paper's examples place source and receiver apart), at
+        # coordinates off the cut planes.
+        L = int(extra_cell or 40)
+        ppw_p = float(ppw if ppw != 10.0 else L)
+        nc = int(ncell or 4)
+        nvox = (nc * L,) * 3
+        seed = 7001 + realisation
+        sc = ppw_p / 10.0
+        sigma, rho = acoustic_medium(nvox, seed, ell_sigma=6.0 * sc, ell_rho=2.0 * sc)
+        cuts = tuple(np.arange(L, nc * L, L) for _ in range(3))
+        plane = (nc - 1) * L
+        n = nc * L
+
+        def grid(k, lo):
+            step = (n - 2 * lo) / (k - 1)
+            v = [int(round(lo + step * i)) for i in range(k)]
+            return [x + 1 if x % L == 0 else x for x in v]
+
+        src = np.array([[x, y, plane] for y in grid(8, L // 4) for x in grid(8, L // 4)], dtype=np.int64)
+        if n_sources is not None:
+            src = src[:n_sources]
+        nrs = 32 if n_receivers is None else n_receivers
+        rec = np.array([[x, y, L] for y in grid(nrs, 2) for x in grid(nrs, 2)], dtype=np.int64)
+        f_p2, om2 = _band(np.sqrt(1.0 / 2.0), ppw_p)
+        return Workload(name, nvox, sigma, rho, cuts, m or 4, mf, me, src, rec,
+                        n_steps or 4000, f_p2, om2, -om2 ** 2 / 10.0, seed=seed,
+                        extra={"cell": L, "ppw": ppw_p})
     raise ValueError(f"unknown workload {name!r}")
 
 

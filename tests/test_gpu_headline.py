@@ -90,7 +90,7 @@ def test_headline_shape_every_variant_fp32(headline, ns):
     S, _ = _lib()
     wl, run, ref = headline
     ref = ref[:, :, :ns]
-    for v in range(5):
+    for v in range(S.CELL_VARIANTS):
         tr, info = _gpu(wl, S.SFROM_F32, run.dt, run.w, ns, variant=v)
         assert info["cell_variant"] == v and info["max_b"] == 56 and info["max_m"] == 4
         e = rel(tr, ref)
@@ -107,7 +107,7 @@ def test_headline_shape_every_variant_fp64(headline, ns):
     S, _ = _lib()
     wl, run, ref = headline
     ref = ref[:, :, :ns]
-    for v in range(5):
+    for v in range(S.CELL_VARIANTS):
         tr, info = _gpu(wl, S.SFROM_F64, run.dt, run.w, ns, variant=v)
         assert info["cell_variant"] == v
         e = rel(tr, ref)
@@ -123,7 +123,7 @@ def test_headline_shape_autotuned_equals_a_variant(headline):
     wl, run, ref = headline
     tr, info = _gpu(wl, S.SFROM_F32, run.dt, run.w, 64)
     v = info["cell_variant"]
-    assert 0 <= v <= 4
+    assert 0 <= v < S.CELL_VARIANTS
     pinned, _ = _gpu(wl, S.SFROM_F32, run.dt, run.w, 64, variant=v)
     assert np.array_equal(tr, pinned)
 
@@ -162,7 +162,7 @@ def test_deep_cells_six_to_eight_layers(dev):
         run.blocks[i] = build_cell(Ai, bi, run.part.cell_W(i), wl.shift, int(mpc[i]))
     ref = pipeline.rom_traces(run)
     for prec, tol in ((S.SFROM_F64, 1e-10), (S.SFROM_F32, 1e-4)):
-        for v in range(5):
+        for v in range(S.CELL_VARIANTS):
             tr, info = _gpu(wl, prec, run.dt, run.w, 40, variant=v, m_per_cell=mpc)
             e = rel(tr, ref)
             print(f"layers 6..8, prec {prec}, variant {v}: rel L2 {e:.2e}")

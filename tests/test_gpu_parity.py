@@ -196,7 +196,7 @@ def test_uneven_layers_matrix_cores(dev):
         run.blocks[i] = build_cell(Ai, bi, part.cell_W(i), wl.shift, int(mpc[i]))
     ref = pipeline.rom_traces(run)
     for prec, tol in ((S.SFROM_F32, 1e-4), (S.SFROM_F64, 1e-10)):
-        for v in range(5):
+        for v in range(S.CELL_VARIANTS):
             tr, _, info = _gpu_rom(wl, prec, run.dt, run.w, m_per_cell=mpc, variant=v)
             e = rel(tr, ref)
             print(f"prec {prec} variant {v} (used {info['cell_variant']}): rel L2 vs oracle {e:.2e}")
@@ -216,7 +216,7 @@ def test_cell_variants_match_oracle(dev):
     run = pipeline.setup(wl)
     pipeline.build_all(run)
     ref = pipeline.rom_traces(run)
-    for v in range(5):
+    for v in range(S.CELL_VARIANTS):
         tr, _, info = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w, variant=v)
         e = rel(tr, ref)
         print(f"variant {v}: rel L2 vs oracle {e:.2e}")
