@@ -577,6 +577,8 @@ void build_layout(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx) {
     bc.out_off = off; off += 2 * mb * b;
     bc.p_off = off;
     if (any_wide) off += ts_partials(n, bc.m, b);
+    bc.li_off = off;
+    if (any_wide) off += (n + 63) / 64 * 64 * 64;
     bc.status = 0;
     wsize[i] = off;
   }
@@ -639,7 +641,7 @@ void for_batches(sfrom_t* h, const sfrom_build_opts* o, BuildCtx& ctx, const std
         const int64_t base = woff;
         bc.band_off += base; bc.v_off += base; bc.x_off += base; bc.av_off += base;
         bc.am_off += base; bc.q_off += base; bc.s_off += base; bc.r_off += base; bc.out_off += base;
-        bc.p_off += base;
+        bc.p_off += base; bc.li_off += base;
         woff += ctx.wsize[i];
       }
       HIPCHK(hipMemcpy(d_bc, bcb.data(), cnt * sizeof(BuildCell), hipMemcpyHostToDevice));

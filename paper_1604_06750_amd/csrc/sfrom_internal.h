@@ -70,6 +70,7 @@ struct BuildCell {
   int32_t status;   // per-cell status (written by kernels)
   int32_t pad;
   int64_t p_off;    // blocked build only: partial Gram products, ceil(n / TS_ROWS) x max((m b)^2, m b^2)
+  int64_t li_off;   // blocked build only: inverse of each 64 x 64 diagonal factor block, ceil(n / 64) x 64^2
 };
 
 // Per-cell on-line descriptor.

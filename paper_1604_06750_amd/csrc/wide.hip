@@ -99,7 +99,52 @@ __device__ inline void lds_potrf(double* s, int nb, int* bad) {
   }
 }
 
-// Panel j0, first launch: factor the diagonal block in LDS and store it.
+// Rows [r0, r0 + 64) of the panel's L21 (columns j0 .. j0 + nb - 1) into LDS
+// as t[k][row] (zero outside the matrix or the band).
+__device__ inline void load_l21(const double* band, int ld, int w, int n, int j0, int nb, int64_t r0, double* t) {
+  for (int idx = threadIdx.x; idx < WB * WB; idx += blockDim.x) {
+    const int rr = idx % WB, k = idx / WB;
+    t[k * WB + rr] = (k < nb) ? band_at(band, ld, w, n, r0 + rr, j0 + k) : 0.0;
+  }
+}
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int TLD = WB + 1;   // stride of a staged 64 x 64 result tile (padded against bank conflicts)
+
+// 64 x 64 product tile on the FP64 matrix instructions (four waves):
+// acc[c] += sum_k a[k][row] b[k][col] over K (rounded up to 4; the LDS
+// arrays a[64][64], b[64][64] hold zeros beyond K). Wave w owns rows
+// 16 w .. 16 w + 15 and accumulator c columns 16 c .. 16 c + 15; the
+// instruction takes A(i, k) from lane i + 16 k and B(k, j) from lane
+// j + 16 k, and leaves C(g + 4 r, j) in register r of lane j + 16 g.
+__device__ inline void tile_mfma(doublex4 (&acc)[4], const double* a, const double* b, int K) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, li = lane & 15;
+  const int K4 = (K + 3) & ~3;
+  for (int k0 = 0; k0 < K4; k0 += 4) {
+    const double av = a[(k0 + g) * WB + 16 * w + li];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double bv = b[(k0 + g) * WB + 16 * c + li];
+      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[c], 0, 0, 0);
+    }
+  }
+}
+
+// The tile into LDS as t[col][row] (stride TLD), so that a coalesced pass
+// over rows can apply it; the caller synchronises before reading t.
+__device__ inline void tile_stage(const doublex4 (&acc)[4], double* t) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, li = lane & 15;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t[(16 * c + li) * TLD + 16 * w + g + 4 * r] = acc[c][r];
+}
+
+// Panel j0, first launch: factor the diagonal block in LDS, store it, and
+// store the inverse of the factor (64 x 64, identity beyond nb; M[i + 64 j]
+// = L11^{-1}(i, j)): the panel's triangular solves become products with it
+// (the block is a diagonal block of the Cholesky factor of a positive
+// definite band matrix, so its inverse is as well conditioned as the block).
 __global__ __launch_bounds__(WNT) void k_wide_potrf(BuildBatch bb, int j0) {
   BuildCell& c = bb.d_cells[blockIdx.x];
   const int n = c.n, w = c.w, ld = w + 1;
@@ -117,64 +162,48 @@ __global__ __launch_bounds__(WNT) void k_wide_potrf(BuildBatch bb, int j0) {
     if (j >= k && j - k <= w) band[(int64_t)(j0 + k) * ld + (j - k)] = s[j * (WB + 1) + k];
   }
   if (threadIdx.x == 0 && bad) c.status = WST_NOTNSD;
+  // column j of L11^{-1} by forward substitution, one thread per column
+  double* M = bb.d_work + c.li_off + (int64_t)(j0 / WB) * WB * WB;
+  const int j = threadIdx.x;
+  if (j < WB) {
+    for (int i = 0; i < j; ++i) M[i + WB * j] = 0.0;
+    M[j + WB * j] = 1.0 / s[j * (WB + 1) + j];
+    for (int i = j + 1; i < WB; ++i) {
+      double a = 0.0;
+      for (int k = j; k < i; ++k) a -= s[i * (WB + 1) + k] * M[k + WB * j];
+      M[i + WB * j] = a / s[i * (WB + 1) + i];
+    }
+  }
 }
 
 // Panel j0, second launch: the panel's rows below the diagonal block,
-// L21 = C21 L11^{-T} with the stored L11, one thread per row, PNT rows per
-// workgroup; each row's values live in an LDS column of their own.
-constexpr int PNT = 128;
-__global__ __launch_bounds__(PNT) void k_wide_trsm(BuildBatch bb, int j0) {
+// L21 = C21 L11^{-T} as a product with the stored inverse, one 64-row tile
+// per workgroup.
+__global__ __launch_bounds__(WNT) void k_wide_trsm(BuildBatch bb, int j0) {
   BuildCell& c = bb.d_cells[blockIdx.x];
   const int n = c.n, w = c.w, ld = w + 1;
   if (j0 >= n || c.status) return;
   const int nb = min(WB, n - j0);
   const int nrows = min(w, n - j0 - nb);             // rows of L21 that can be nonzero
-  if ((int)blockIdx.y * PNT >= nrows) return;
+  const int64_t r0 = j0 + nb + (int64_t)blockIdx.y * WB;
+  if ((int)blockIdx.y * WB >= nrows) return;
   double* band = bb.d_work + c.band_off;
-  __shared__ double s[WB * (WB + 1)];
-  __shared__ double xs[WB * PNT];                    // xs[k][thread]
-  load_diag(band, ld, w, n, j0, nb, s);              // the factor L11
+  const double* M = bb.d_work + c.li_off + (int64_t)(j0 / WB) * WB * WB;
+  __shared__ __align__(16) double la[WB * TLD];
+  __shared__ __align__(16) double lb[WB * WB];
+  // la[q][row] = C21(r0 + row, j0 + q); lb[q][k] = L11^{-T}(q, k) = M[k + 64 q]
+  load_l21(band, ld, w, n, j0, nb, r0, la);
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) lb[idx] = M[idx];
   __syncthreads();
-  const int i = blockIdx.y * PNT + threadIdx.x;
-  if (i >= nrows) return;
-  const int64_t r = j0 + nb + i;
-  double* x = xs + threadIdx.x;
-  // row r of C21 (zero where the band ends), then forward substitution with
-  // L11 from LDS: x[k] = (a[k] - sum_{q<k} x[q] L11[k][q]) / L11[k][k]
-  for (int k = 0; k < nb; ++k) x[k * PNT] = band_at(band, ld, w, n, r, j0 + k);
-  for (int k = 0; k < nb; ++k) {
-    double acc = x[k * PNT];
-    for (int q = 0; q < k; ++q) acc -= x[q * PNT] * s[k * (WB + 1) + q];
-    x[k * PNT] = acc / s[k * (WB + 1) + k];
-  }
-  for (int k = 0; k < nb; ++k)
-    if (r - (j0 + k) <= w) band[(int64_t)(j0 + k) * ld + (r - j0 - k)] = x[k * PNT];
-}
-
-// Rows [r0, r0 + 64) of the panel's L21 (columns j0 .. j0 + nb - 1) into LDS
-// as t[k][row] (zero outside the matrix or the band).
-__device__ inline void load_l21(const double* band, int ld, int w, int n, int j0, int nb, int64_t r0, double* t) {
-  for (int idx = threadIdx.x; idx < WB * WB; idx += blockDim.x) {
+  doublex4 acc[4] = {};
+  tile_mfma(acc, la, lb, nb);
+  __syncthreads();
+  tile_stage(acc, la);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
     const int rr = idx % WB, k = idx / WB;
-    t[k * WB + rr] = (k < nb) ? band_at(band, ld, w, n, r0 + rr, j0 + k) : 0.0;
-  }
-}
-
-// 4 x 4 register tile of thread t of a 64 x 64 product: rows 4 (t / 16) ..,
-// columns 4 (t % 16) ..; acc[i][j] += sum_k a[k][row i] b[k][col j] over the
-// K values of LDS arrays a[K][64], b[K][64].
-__device__ inline void tile_fma(double (&acc)[4][4], const double* a, const double* b, int K) {
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
-  for (int k = 0; k < K; ++k) {
-    const double2 a01 = *reinterpret_cast<const double2*>(a + k * WB + tr);
-    const double2 a23 = *reinterpret_cast<const double2*>(a + k * WB + tr + 2);
-    const double2 b01 = *reinterpret_cast<const double2*>(b + k * WB + tc);
-    const double2 b23 = *reinterpret_cast<const double2*>(b + k * WB + tc + 2);
-    const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    const int64_t r = r0 + rr;
+    if (k < nb && rr < nrows - (int)blockIdx.y * WB && r - (j0 + k) <= w) band[(int64_t)(j0 + k) * ld + (r - j0 - k)] = la[k * TLD + rr];
   }
 }
 
@@ -194,23 +223,21 @@ __global__ __launch_bounds__(WNT) void k_wide_update(BuildBatch bb, int j0) {
   const int tj = t - ti * (ti + 1) / 2;
   if (ti * WB >= W || tj > ti) return;
   double* band = bb.d_work + c.band_off;
-  __shared__ __align__(16) double la[WB * WB];
+  __shared__ __align__(16) double la[WB * TLD];
   __shared__ __align__(16) double lb[WB * WB];
   const int64_t r0 = s0 + (int64_t)ti * WB, q0 = s0 + (int64_t)tj * WB;
   load_l21(band, ld, w, n, j0, nb, r0, la);
   load_l21(band, ld, w, n, j0, nb, q0, lb);
   __syncthreads();
-  double acc[4][4] = {};
-  tile_fma(acc, la, lb, nb);
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t cc = q0 + tc + j;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = r0 + tr + i;
-      if (r < s0 + W && cc < s0 + W && r >= cc) band[cc * ld + (r - cc)] -= acc[i][j];
-    }
+  doublex4 acc[4] = {};
+  tile_mfma(acc, la, lb, nb);
+  __syncthreads();
+  tile_stage(acc, la);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    const int rr = idx % WB, cq = idx / WB;
+    const int64_t r = r0 + rr, cc = q0 + cq;
+    if (r < s0 + W && cc < s0 + W && r >= cc) band[cc * ld + (r - cc)] -= la[cq * TLD + rr];
   }
 }
 
@@ -244,32 +271,36 @@ __global__ __launch_bounds__(WNT) void k_wide_solve_end(BuildBatch bb, int j) {
   for (int col = 0; col < b; ++col) X[r + (int64_t)col * n] = -T[r + (int64_t)col * n];
 }
 
-// Forward, panel j0, columns [c0, c0 + 64): Y1 = L11^{-1} T1 in place, one
-// thread per column.
-__global__ __launch_bounds__(WB) void k_wide_fwd_diag(BuildBatch bb, int j, int j0) {
+// Forward, panel j0, columns [c0, c0 + 64): Y1 = L11^{-1} T1 in place, as a
+// product with the stored inverse.
+__global__ __launch_bounds__(WNT) void k_wide_fwd_diag(BuildBatch bb, int j, int j0) {
   BuildCell& c = bb.d_cells[blockIdx.x];
   if (c.status || j + 1 >= c.m) return;
-  const int n = c.n, w = c.w, ld = w + 1, b = c.b;
+  const int n = c.n, b = c.b;
   if (j0 >= n) return;
-  const int col = blockIdx.y * WB + threadIdx.x;
-  if ((int)blockIdx.y * WB >= b) return;
+  const int c0 = blockIdx.y * WB;
+  if (c0 >= b) return;
   const int nb = min(WB, n - j0);
-  const double* band = bb.d_work + c.band_off;
+  const double* M = bb.d_work + c.li_off + (int64_t)(j0 / WB) * WB * WB;
   double* T = bb.d_work + c.av_off;
-  __shared__ double s[WB * (WB + 1)];
-  __shared__ double ys[WB * WB];            // ys[k][thread]
-  load_diag(band, ld, w, n, j0, nb, s);     // now holds L11 (factored)
-  __syncthreads();
-  if (col >= b) return;
-  double* t = T + (int64_t)col * n + j0;
-  double* y = ys + threadIdx.x;
-  for (int k = 0; k < nb; ++k) y[k * WB] = t[k];
-  for (int k = 0; k < nb; ++k) {
-    double acc = y[k * WB];
-    for (int q = 0; q < k; ++q) acc -= s[k * (WB + 1) + q] * y[q * WB];
-    y[k * WB] = acc / s[k * (WB + 1) + k];
+  __shared__ __align__(16) double sa[WB * TLD];
+  __shared__ __align__(16) double sb[WB * WB];
+  // sa[q][k] = L11^{-1}(k, q) = M[k + 64 q]; sb[q][col] = T1(q, c0 + col)
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    sa[idx] = M[idx];
+    const int q = idx % WB, cc = idx / WB;
+    sb[q * WB + cc] = (q < nb && c0 + cc < b) ? T[j0 + q + (int64_t)(c0 + cc) * n] : 0.0;
   }
-  for (int k = 0; k < nb; ++k) t[k] = y[k * WB];
+  __syncthreads();
+  doublex4 acc[4] = {};
+  tile_mfma(acc, sa, sb, nb);
+  __syncthreads();
+  tile_stage(acc, sa);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    const int k = idx % WB, cc = idx / WB;
+    if (k < nb && c0 + cc < b) T[j0 + k + (int64_t)(c0 + cc) * n] = sa[cc * TLD + k];
+  }
 }
 
 // Forward, panel j0: T2 -= L21 Y1 for the rows [s0, s0 + W) below the panel;
@@ -286,7 +317,7 @@ __global__ __launch_bounds__(WNT) void k_wide_fwd_update(BuildBatch bb, int j, i
   if (W <= 0 || ti * WB >= W || tj * WB >= b) return;
   const double* band = bb.d_work + c.band_off;
   double* T = bb.d_work + c.av_off;
-  __shared__ __align__(16) double la[WB * WB];
+  __shared__ __align__(16) double la[WB * TLD];
   __shared__ __align__(16) double yb[WB * WB];
   const int64_t r0 = s0 + (int64_t)ti * WB;
   const int c0 = tj * WB;
@@ -296,18 +327,16 @@ __global__ __launch_bounds__(WNT) void k_wide_fwd_update(BuildBatch bb, int j, i
     yb[k * WB + cc] = (k < nb && c0 + cc < b) ? T[j0 + k + (int64_t)(c0 + cc) * n] : 0.0;
   }
   __syncthreads();
-  double acc[4][4] = {};
-  tile_fma(acc, la, yb, nb);
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
-#pragma unroll
-  for (int jj = 0; jj < 4; ++jj) {
-    const int cc = c0 + tc + jj;
-    if (cc >= b) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = r0 + tr + i;
-      if (r < s0 + W) T[r + (int64_t)cc * n] -= acc[i][jj];
-    }
+  doublex4 acc[4] = {};
+  tile_mfma(acc, la, yb, nb);
+  __syncthreads();
+  tile_stage(acc, la);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    const int rr = idx % WB, cq = idx / WB;
+    const int64_t r = r0 + rr;
+    const int cc = c0 + cq;
+    if (r < s0 + W && cc < b) T[r + (int64_t)cc * n] -= la[cq * TLD + rr];
   }
 }
 
@@ -325,11 +354,10 @@ __global__ __launch_bounds__(WNT) void k_wide_bwd(BuildBatch bb, int j, int j0) 
   const int W = (int)max((int64_t)0, min((int64_t)w, n - s0));
   const double* band = bb.d_work + c.band_off;
   double* T = bb.d_work + c.av_off;
-  __shared__ __align__(16) double la[WB * WB];   // la[row][k] chunk of L21 (as [K = rows][64 = k])
+  __shared__ __align__(16) double la[WB * TLD];  // la[row][k] chunk of L21 (as [K = rows][64 = k])
   __shared__ __align__(16) double xb[WB * WB];   // xb[row][col] chunk of X2
-  __shared__ double s[WB * (WB + 1)];
   // acc[k][col] = sum over the window rows r of L21[r][k] X2[r][col]
-  double acc[4][4] = {};
+  doublex4 acc[4] = {};
   for (int rc = 0; rc < W; rc += WB) {
     const int64_t r0 = s0 + rc;
     // rows fastest across the threads: contiguous in the band and in T
@@ -339,31 +367,32 @@ __global__ __launch_bounds__(WNT) void k_wide_bwd(BuildBatch bb, int j, int j0) 
       xb[rr * WB + q] = (rc + rr < W && c0 + q < b) ? T[r0 + rr + (int64_t)(c0 + q) * n] : 0.0;
     }
     __syncthreads();
-    tile_fma(acc, la, xb, min(WB, W - rc));
+    tile_mfma(acc, la, xb, min(WB, W - rc));
     __syncthreads();
   }
-  // right-hand side of the diagonal solve in LDS (reuse xb as rhs[k][col])
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int k = tr + i, cc = tc + jj;
-      xb[k * WB + cc] = (k < nb && c0 + cc < b) ? T[j0 + k + (int64_t)(c0 + cc) * n] - acc[i][jj] : 0.0;
-    }
-  load_diag(band, ld, w, n, j0, nb, s);
+  // right-hand side of the diagonal solve in LDS (xb as rhs[q][col])
+  tile_stage(acc, la);
   __syncthreads();
-  // L11^T x = rhs, one thread per column: x[k] = (rhs[k] - sum_{q>k} L11[q][k] x[q]) / L11[k][k]
-  const int col = threadIdx.x;
-  if (col < WB && c0 + col < b) {
-    double* x = xb + col;                    // column col of rhs, solved in place
-    for (int k = nb - 1; k >= 0; --k) {
-      double a = x[k * WB];
-      for (int q = k + 1; q < nb; ++q) a -= s[q * (WB + 1) + k] * x[q * WB];
-      x[k * WB] = a / s[k * (WB + 1) + k];
-    }
-    double* t = T + (int64_t)(c0 + col) * n + j0;
-    for (int k = 0; k < nb; ++k) t[k] = x[k * WB];
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    const int k = idx % WB, cc = idx / WB;
+    xb[k * WB + cc] = (k < nb && c0 + cc < b) ? T[j0 + k + (int64_t)(c0 + cc) * n] - la[cc * TLD + k] : 0.0;
+  }
+  // X1 = L11^{-T} rhs: la[q][k] = L11^{-T}(k, q) = L11^{-1}(q, k) = M[q + 64 k]
+  const double* M = bb.d_work + c.li_off + (int64_t)(j0 / WB) * WB * WB;
+  __syncthreads();                               // every thread is done reading the staged tile
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    const int q = idx % WB, k = idx / WB;
+    la[q * WB + k] = M[q + WB * k];
+  }
+  __syncthreads();
+  doublex4 x[4] = {};
+  tile_mfma(x, la, xb, nb);
+  __syncthreads();
+  tile_stage(x, la);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    const int k = idx % WB, cc = idx / WB;
+    if (k < nb && c0 + cc < b) T[j0 + k + (int64_t)(c0 + cc) * n] = la[cc * TLD + k];
   }
 }
 
@@ -420,9 +449,9 @@ __global__ __launch_bounds__(WNT) void k_ts_gram(BuildBatch bb, int mode, int j,
   const int r1 = min(n, r0 + TS_ROWS);
   const int ti = blockIdx.z / ntj, tj = blockIdx.z % ntj;
   if (ti * WB >= o.p || tj * WB >= o.q) return;
-  __shared__ __align__(16) double sa[WB * WB];
+  __shared__ __align__(16) double sa[WB * TLD];
   __shared__ __align__(16) double sb[WB * WB];
-  double acc[4][4] = {};
+  doublex4 acc[4] = {};
   for (int rb = r0; rb < r1; rb += WB) {
     const int nr = min(WB, r1 - rb);
     // sa[row][i] = A[rb + row][ti 64 + i], sb[row][jj] = d B[rb + row][tj 64 + jj]
@@ -435,18 +464,17 @@ __global__ __launch_bounds__(WNT) void k_ts_gram(BuildBatch bb, int mode, int j,
       sb[row * WB + col] = (row < nr && ib < o.q) ? dv * o.B[r + (int64_t)ib * n] : 0.0;
     }
     __syncthreads();
-    tile_fma(acc, sa, sb, nr);
+    tile_mfma(acc, sa, sb, nr);
     __syncthreads();
   }
   double* P = bb.d_work + c.p_off + (int64_t)blockIdx.y * o.p * o.q;
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int gi = ti * WB + tr + i, gj = tj * WB + tc + jj;
-      if (gi < o.p && gj < o.q) P[gi + (int64_t)gj * o.p] = acc[i][jj];
-    }
+  tile_stage(acc, sa);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    const int i = idx % WB, jj = idx / WB;
+    const int gi = ti * WB + i, gj = tj * WB + jj;
+    if (gi < o.p && gj < o.q) P[gi + (int64_t)gj * o.p] = sa[jj * TLD + i];
+  }
 }
 
 // Sum of the partial products in chunk order (symmetrised for the Gram
@@ -481,9 +509,9 @@ __global__ __launch_bounds__(WNT) void k_ts_update(BuildBatch bb, int j) {
   const double* V = bb.d_work + c.v_off;
   const double* coef = bb.d_work + c.s_off;
   double* X = bb.d_work + c.x_off;
-  __shared__ __align__(16) double sa[WB * WB];
+  __shared__ __align__(16) double sa[WB * TLD];
   __shared__ __align__(16) double sb[WB * WB];
-  double acc[4][4] = {};
+  doublex4 acc[4] = {};
   for (int k0 = 0; k0 < jb; k0 += WB) {
     const int nk = min(WB, jb - k0);
     for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
@@ -493,19 +521,15 @@ __global__ __launch_bounds__(WNT) void k_ts_update(BuildBatch bb, int j) {
       sb[kk * WB + col] = (kk < nk && c0 + col < b) ? coef[k0 + kk + (int64_t)(c0 + col) * jb] : 0.0;
     }
     __syncthreads();
-    tile_fma(acc, sa, sb, nk);
+    tile_mfma(acc, sa, sb, nk);
     __syncthreads();
   }
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
-#pragma unroll
-  for (int jj = 0; jj < 4; ++jj) {
-    const int cc = c0 + tc + jj;
-    if (cc >= b) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = r0 + tr + i;
-      if (r < n) X[r + (int64_t)cc * n] -= acc[i][jj];
-    }
+  tile_stage(acc, sa);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < WB * WB; idx += WNT) {
+    const int rr = idx % WB, cq = idx / WB;
+    const int r = r0 + rr, cc = c0 + cq;
+    if (r < n && cc < b) X[r + (int64_t)cc * n] -= sa[cq * TLD + rr];
   }
 }
 
@@ -603,12 +627,12 @@ bool build_is_wide(const BuildBatch& bb, int force) {
 hipError_t launch_wide_chol(const BuildBatch& bb, hipStream_t st) {
   const int nc = bb.ncell;
   hipLaunchKernelGGL(k_wide_assemble, dim3(nc, (bb.max_n + WNT - 1) / WNT), dim3(WNT), 0, st, bb);
-  const int rt = (bb.max_w + PNT - 1) / PNT;                  // row blocks of a panel's L21
+  const int rt = (bb.max_w + WB - 1) / WB;                    // row tiles of a panel's L21
   const int T = (bb.max_w + WB - 1) / WB;                      // tile rows of a trailing window
   const int ntile = T * (T + 1) / 2;
   for (int j0 = 0; j0 < bb.max_n; j0 += WB) {
     hipLaunchKernelGGL(k_wide_potrf, dim3(nc), dim3(WNT), 0, st, bb, j0);
-    if (rt > 0) hipLaunchKernelGGL(k_wide_trsm, dim3(nc, rt), dim3(PNT), 0, st, bb, j0);
+    if (rt > 0) hipLaunchKernelGGL(k_wide_trsm, dim3(nc, rt), dim3(WNT), 0, st, bb, j0);
     if (ntile > 0) hipLaunchKernelGGL(k_wide_update, dim3(nc, ntile), dim3(WNT), 0, st, bb, j0);
   }
   return hipGetLastError();
@@ -621,7 +645,7 @@ hipError_t launch_wide_solve(const BuildBatch& bb, int j, hipStream_t st) {
   const int nrt = std::max((bb.max_w + WB - 1) / WB, 1);
   hipLaunchKernelGGL(k_wide_solve_start, rows, dim3(WNT), 0, st, bb, j);
   for (int j0 = 0; j0 < bb.max_n; j0 += WB) {
-    hipLaunchKernelGGL(k_wide_fwd_diag, dim3(nc, ct), dim3(WB), 0, st, bb, j, j0);
+    hipLaunchKernelGGL(k_wide_fwd_diag, dim3(nc, ct), dim3(WNT), 0, st, bb, j, j0);
     hipLaunchKernelGGL(k_wide_fwd_update, dim3(nc, nrt * ct), dim3(WNT), 0, st, bb, j, j0, nrt);
   }
   const int last = (bb.max_n - 1) / WB * WB;
