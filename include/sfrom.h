@@ -116,6 +116,23 @@ int sfrom_setup_voxel_acoustic(sfrom_t* h, const int32_t nvox[3], const double* 
                                const double* rho, const int32_t ncut[3], const int32_t* cuts,
                                int32_t modes_face, int32_t modes_edge);
 
+/* Convenience set-up for an elastic medium (the anisotropic elastic example
+ * of Sec. 9, in the form B u'' = A u + w(t) g of Sec. 1): displacements at
+ * the corners of unit voxels nvox[0] x nvox[1] x nvox[2], three components
+ * per node, clamped outer walls; unknown 3 k + c for interior node k
+ * (x-fastest) and component c. c21 holds per voxel (x fastest) the 21
+ * upper-triangle entries, row by row, of its symmetric 6 x 6 Voigt stiffness
+ * (strains xx, yy, zz, yz, xz, xy, engineering shears); each voxel adds the
+ * stiffness of the trilinear element on the unit cube (2 x 2 x 2 Gauss
+ * rule) to A with a minus sign and rho / 8 per corner and component to B.
+ * Cells and pieces as in sfrom_setup_voxel_acoustic; a piece's basis takes
+ * each of its scalar DCT-II modes once per component (columns mode by mode,
+ * components x, y, z; the piece's unknowns node by node). Errors: EINVAL,
+ * and those of sfrom_set_pencil, sfrom_add_cell and sfrom_add_piece. */
+int sfrom_setup_voxel_elastic(sfrom_t* h, const int32_t nvox[3], const double* c21, const double* rho,
+                              const int32_t ncut[3], const int32_t* cuts, int32_t modes_face,
+                              int32_t modes_edge);
+
 /* ---------------------------------------------------------------------------
  * Off-line stage (Alg. alg1red stage 1)
  * ------------------------------------------------------------------------ */

@@ -40,6 +40,24 @@ def setup(h, wl, sources=True, receivers=True):
         S.sfrom_set_receivers(h, cp, rw, vl, project=False)
 
 
+def setup_elastic(h, wl, sources=True, receivers=True):
+    """Elastic voxel set-up plus projected point forces (component
+    wl.extra['source_component'], default z) and receivers of all three
+    components at the receiver nodes (receiver r, component c is column
+    3 r + c)."""
+    S.sfrom_setup_voxel_elastic(h, wl.extra["c21"], wl.rho, wl.cuts, wl.modes_face, wl.modes_edge)
+    mp = 3 * max_piece_nodes(wl)
+    comp = int(wl.extra.get("source_component", 2))
+    if sources:
+        d = 3 * node_ids(wl.nvox, wl.sources) + comp
+        cp, rw, vl = S.sfrom_point_columns(h, d, mp)
+        S.sfrom_set_sources(h, cp, rw, vl, project=False)
+    if receivers:
+        d = (3 * node_ids(wl.nvox, wl.receivers)[:, None] + np.arange(3)[None, :]).ravel()
+        cp, rw, vl = S.sfrom_point_columns(h, d, mp)
+        S.sfrom_set_receivers(h, cp, rw, vl, project=False)
+
+
 def interior_cells(wl):
     """Ids (x-fastest over the cut grid) of the 8^3-voxel cells that touch no
     wall: the cells the learned off-line stage predicts."""

@@ -61,6 +61,7 @@ _SIGS = {
     "sfrom_add_cell": [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P],
     "sfrom_add_piece": [_P, C.c_int32, C.c_int32, _P, C.c_int32, _P],
     "sfrom_setup_voxel_acoustic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
+    "sfrom_setup_voxel_elastic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
     "sfrom_build": [_P, C.POINTER(sfrom_build_opts)],
     "sfrom_import_rom": [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P],
     "sfrom_export_rom": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P],
@@ -185,6 +186,19 @@ def sfrom_setup_voxel_acoustic(h, sigma, rho, cuts, modes_face, modes_edge):
     cc = np.concatenate([np.asarray(c, dtype=np.int32) for c in cuts]) if ncut.sum() else np.zeros(1, np.int32)
     _check(h, _lib.sfrom_setup_voxel_acoustic(h, _ptr(nvox), _ptr(s), _ptr(r), _ptr(ncut), _ptr(cc),
                                               modes_face, modes_edge))
+
+
+def sfrom_setup_voxel_elastic(h, c21, rho, cuts, modes_face, modes_edge):
+    """c21: (nx, ny, nz, 21) upper-triangle Voigt stiffness per voxel, rho:
+    (nx, ny, nz); arrays indexed [x, y, z] (x fastest in memory order F)."""
+    rho = np.asarray(rho, np.float64)
+    nvox = np.array(rho.shape, np.int32)
+    r = np.ascontiguousarray(rho.transpose(2, 1, 0))
+    c = np.ascontiguousarray(np.asarray(c21, np.float64).transpose(2, 1, 0, 3))
+    ncut = np.array([len(x) for x in cuts], np.int32)
+    cc = np.ascontiguousarray(np.concatenate([np.asarray(x, np.int32) for x in cuts]) if ncut.sum() else np.zeros(1, np.int32))
+    _check(h, _lib.sfrom_setup_voxel_elastic(h, _ptr(nvox), _ptr(c), _ptr(r), _ptr(ncut), _ptr(cc),
+                                             int(modes_face), int(modes_edge)))
 
 
 def sfrom_build(h, m, shift, online_prec=SFROM_F32, m_per_cell=None, cells_per_batch=0):

@@ -96,6 +96,43 @@ def layered_medium(nvox: Tuple[int, int, int], seed: int,
     return np.ascontiguousarray(sigma), np.ascontiguousarray(rho)
 
 
+def vti_voigt21(lam, mu, eps, delta):
+    """Upper triangle (21 values, row by row) of the 6 x 6 Voigt stiffness of
+    a vertically transversely isotropic medium from lambda, mu and Thomsen's
+    epsilon, delta (vertical axis z): C33 = lambda + 2 mu, C44 = C55 = C66 =
+    mu, C11 = C22 = C33 (1 + 2 eps), C12 = C11 - 2 C66,
+    C13 = C23 = sqrt((C33 - C44)(C33 (1 + 2 delta) - C44)) - C44."""
+    lam, mu, eps, delta = (np.asarray(v, np.float64) for v in (lam, mu, eps, delta))
+    C33 = lam + 2.0 * mu
+    C44 = mu
+    C11 = C33 * (1.0 + 2.0 * eps)
+    C12 = C11 - 2.0 * C44
+    C13 = np.sqrt((C33 - C44) * (C33 * (1.0 + 2.0 * delta) - C44)) - C44
+    z = np.zeros_like(C33)
+    rows = [[C11, C12, C13, z, z, z], [C11, C13, z, z, z], [C33, z, z, z], [C44, z, z], [C44, z], [C44]]
+    return np.stack([v for r in rows for v in r], axis=-1)
+
+
+def elastic_layered_medium(nvox: Tuple[int, int, int], seed: int, z_bounds: Sequence[int],
+                           contrast: float = 3.0, aniso: float = 0.2):
+    """Layered VTI medium (piecewise-constant phases): layer j gets mu and
+    lambda scaled by contrast^(j/(L-1)) in a seeded order (lambda = 2 mu),
+    Thomsen epsilon, delta ~ U[0, aniso] and rho = 1. Returns the per-voxel
+    21 Voigt entries (nx, ny, nz, 21) and rho (nx, ny, nz)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nz = nvox[2]
+    edges = [0] + list(z_bounds) + [nz]
+    L = len(edges) - 1
+    order = rng.permutation(L)
+    mu = contrast ** (order / max(L - 1, 1))
+    eps = aniso * rng.random(L)
+    dl = aniso * rng.random(L)
+    c21 = np.empty(tuple(nvox) + (21,))
+    for j in range(L):
+        c21[:, :, edges[j]:edges[j + 1]] = vti_voigt21(2.0 * mu[j], mu[j], eps[j], dl[j])
+    return np.ascontiguousarray(c21), np.ones(nvox)
+
+
 # --------------------------------------------------------------------------
 # wavelet
 # --------------------------------------------------------------------------
@@ -330,6 +367,35 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
                     v13 = (ex * ey * ez) ** (1.0 / 3.0)
                     mpc.append(int(np.clip(round(3 + 5 * (v13 - 8) / 8), 3, 8)))
         wl.extra["m_per_cell"] = np.array(mpc, dtype=np.int32)
+        return wl
+    if name in ("elastic", "elastic_tiny"):
+        # layered VTI elastic medium (three piecewise-constant phases, shear
+        # modulus contrast 3:1, lambda = 2 mu, Thomsen eps, delta <= 0.2,
+        # rho = 1), cells of 8^3 voxels, vertical point forces on a grid of
+        # face-interior nodes of the first interior z-interface, receivers on
+        # a denser grid of the same plane; the unknown of node k's component
+        # c is 3 k + c
+        if name == "elastic":
+            nvox, zb, nsx, nsy, nrx, nry, steps = (96, 96, 96), [32, 64], 8, 4, 32, 16, 3000
+        else:
+            nvox, zb, nsx, nsy, nrx, nry, steps = (16, 16, 16), [5, 11], 2, 1, 4, 3, 400
+        seed = 9101 + realisation
+        c21, rho = elastic_layered_medium(nvox, seed, zb)
+        cuts = tuple(np.arange(8, n, 8) for n in nvox)
+        plane = 8
+
+        def grid(k, n, lo):
+            v = [int(round(lo + (n - 2 * lo) * (i + 0.5) / k)) for i in range(k)]
+            return [x + 1 if x % 8 == 0 else x for x in v]
+
+        src = np.array([[x, y, plane] for y in grid(nsy, nvox[1], 2) for x in grid(nsx, nvox[0], 2)], dtype=np.int64)
+        rec = np.array([[x, y, plane] for y in grid(nry, nvox[1], 1) for x in grid(nrx, nvox[0], 1)], dtype=np.int64)
+        c_s = 1.0                       # slowest shear speed of the generator (mu >= 1, rho = 1)
+        f_p2, om2 = _band(c_s, ppw)
+        wl = Workload(name, nvox, None, rho, cuts, m or 4, mf if modes_face is not None else 4, me, src, rec,
+                      n_steps or steps, f_p2, om2, -om2 ** 2 / 10.0, seed=seed)
+        wl.extra["c21"] = c21
+        wl.extra["source_component"] = 2
         return wl
     if name == "paper":
         # the shape of the paper's acoustic examples (Sec. 9): a fine grid far

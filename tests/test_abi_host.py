@@ -78,6 +78,45 @@ def test_voxel_setup_matches_oracle(host, name, mf, me):
         assert np.abs(Sp - pc.S).max() <= 1e-14
 
 
+def test_elastic_setup_matches_oracle(host):
+    """The library's elastic set-up (its own Q1 element code) equals the
+    oracle's assembly, cell split and vector piece bases; the medium's Voigt
+    entries equal the oracle's VTI tensor."""
+    from oracle import elastic
+    S, h = host
+    nvox = (9, 8, 10)
+    cuts = (np.array([4]), np.array([3, 5]), np.array([5]))
+    c21, rho = synth.elastic_layered_medium(nvox, 77, [3, 7])
+    rho = rho * np.random.default_rng(4).uniform(1.0, 2.0, nvox)
+    Cv = np.zeros(tuple(nvox) + (6, 6))
+    iu = np.triu_indices(6)
+    Cv[..., iu[0], iu[1]] = c21
+    Cv[..., iu[1], iu[0]] = c21
+    C0 = elastic.vti_stiffness(2.0, 1.0, 0.1, 0.05)
+    assert np.allclose(synth.vti_voigt21(2.0, 1.0, 0.1, 0.05), C0[iu], atol=1e-15)
+    S.sfrom_setup_voxel_elastic(h, c21, rho, cuts, 4, 2)
+    A, b = elastic.assemble_elastic(Cv, rho)
+    rp, cl, av, bv = S.sfrom_export_pencil(h)
+    Ah = sp.csr_matrix((av, cl, rp), shape=A.shape)
+    assert abs(Ah - A).max() <= 1e-14 * abs(A).max()
+    assert np.abs(bv - b).max() <= 1e-15 * b.max()
+    part = elastic.ElasticPartition(nvox, cuts, 4, 2)
+    info = S.sfrom_get_info(h)
+    assert info["n_cells"] == len(part.cells) and info["n_pieces"] == len(part.pieces)
+    for i in range(len(part.cells)):
+        e = S.sfrom_export_cell(h, i)
+        assert np.array_equal(e["global_node"], part.cell_dofs(i))
+        Ai, bi = part.cell_operator(i, Cv, rho)
+        Ae = sp.csr_matrix((e["a"], e["col"], e["rowptr"]), shape=Ai.shape).toarray()
+        assert np.abs(Ae - Ai).max() <= 1e-14 * np.abs(Ai).max()
+        assert np.abs(e["b"] - bi).max() <= 1e-15 * bi.max()
+        assert e["b_dim"] == part.cell_W(i).shape[1]
+    for p, (dofs, Sp_o, _) in enumerate(part.pieces):
+        g, Sp = S.sfrom_export_piece(h, p)
+        assert np.array_equal(g, dofs)
+        assert Sp.shape == Sp_o.shape and np.abs(Sp - Sp_o).max() <= 1e-14
+
+
 def test_point_columns_match_oracle(host):
     S, h = host
     from paper_1604_06750_amd.problem import node_ids, max_piece_nodes
