@@ -64,10 +64,13 @@ typedef enum { SFROM_F64 = 0, SFROM_F32 = 1, SFROM_BF16 = 2 } sfrom_prec;
 /* Create a handle on HIP device `device`; `hip_stream` is a hipStream_t (or
  * NULL for the null stream) on which all work is enqueued. device == -1
  * creates a host-only handle: problem set-up, validation and the export
- * calls work, every call that needs the GPU returns SFROM_EDEVICE. */
+ * calls work, every call that needs the GPU returns SFROM_EDEVICE. On
+ * failure *out is NULL and sfrom_last_error(NULL) names the HIP call that
+ * failed and its error (per calling thread). */
 int sfrom_create(sfrom_t** out, int device, void* hip_stream);
 void sfrom_destroy(sfrom_t* h);
-/* Message for the last failing call; valid until the next call on h. */
+/* Message for the last failing call on h, valid until the next call on h;
+ * with h == NULL, why the calling thread's last sfrom_create failed. */
 const char* sfrom_last_error(const sfrom_t* h);
 
 /* ---------------------------------------------------------------------------

@@ -1769,6 +1769,15 @@ void load_arrays(sfrom_t* h, File& F) {
   (h)->err.clear();                                           \
   return SFROM_OK;
 
+// Why the calling thread's last sfrom_create failed (read through
+// sfrom_last_error(NULL)).
+thread_local std::string g_create_err = "no failed create on this thread";
+
+int create_fail(const char* what, hipError_t e) {
+  g_create_err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return e == hipErrorOutOfMemory ? SFROM_ENOMEM : SFROM_EDEVICE;
+}
+
 extern "C" {
 
 int sfrom_create(sfrom_t** out, int device, void* hip_stream) {
@@ -1782,13 +1791,18 @@ int sfrom_create(sfrom_t** out, int device, void* hip_stream) {
     return SFROM_OK;
   }
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SFROM_EDEVICE;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return create_fail("hipGetDeviceCount", e);
+  if (device < 0 || device >= ndev) {
+    g_create_err = "device " + std::to_string(device) + " not in [0, " + std::to_string(ndev) + ")";
+    return SFROM_EDEVICE;
+  }
   sfrom_t* h = new (std::nothrow) sfrom_t();
   if (!h) return SFROM_ENOMEM;
   h->device = device;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  if (hipSetDevice(device) != hipSuccess) { delete h; return SFROM_EDEVICE; }
-  if (init_scratch(device) != hipSuccess) { delete h; return SFROM_EDEVICE; }
+  if ((e = hipSetDevice(device)) != hipSuccess) { delete h; return create_fail("hipSetDevice", e); }
+  if ((e = init_scratch(device)) != hipSuccess) { delete h; return create_fail("scratch symbol address", e); }
   *out = h;
   return SFROM_OK;
 }
@@ -1802,7 +1816,7 @@ void sfrom_destroy(sfrom_t* h) {
   delete h;
 }
 
-const char* sfrom_last_error(const sfrom_t* h) { return h ? h->err.c_str() : "null handle"; }
+const char* sfrom_last_error(const sfrom_t* h) { return h ? h->err.c_str() : g_create_err.c_str(); }
 
 int sfrom_set_pencil(sfrom_t* h, int64_t n, const int64_t* rowptr, const int32_t* col, const double* a,
                      const double* b) {

@@ -65,3 +65,71 @@ def train(s, x, t, epochs: int, lr: float, batch: int, seed: int):
             cnt += len(idx)
         hist.append(tot / cnt)
     return hist
+
+
+def experiment(n_train_media: int = 8, n_eval_media: int = 10, epochs: int = 40, m: int = 4, tol: float = 1e-3,
+               conv_ch: int = 8, hidden: int = 128, workload: str = "large", log=print):
+    """The learned off-line stage at scale: train on the interior cells of
+    ``n_train_media`` realisations of the 128^3 medium generator (2744
+    interior cells each), then, on each of ``n_eval_media`` held-out
+    realisations, build the ROM with the learned stage and without it and
+    compare acceptance, build times and receiver traces. Returns a dict of
+    the figures (the network's forward/backward/Adam, targets, prediction and
+    transfer-function tests run in libsfrom)."""
+    import time
+    import torch
+    import synth
+    stream = torch.cuda.current_stream().cuda_stream
+    train_wl = [synth.workload(workload, modes_face=4, modes_edge=2, m=m, realisation=100 + r)
+                for r in range(n_train_media)]
+    t0 = time.perf_counter()
+    x, t = training_set(train_wl, m, stream=stream)
+    label_s = time.perf_counter() - t0
+    P = t.shape[1]
+    mu = t.mean(axis=0)
+    sd = t.std(axis=0) + 1e-3 * np.abs(t).mean() + 1e-12
+    s = S.sfrom_surrogate_create(0, stream, conv_ch, hidden, P)
+    out = {"train_cells": int(len(x)), "label_s": label_s}
+    try:
+        S.sfrom_surrogate_set_params(s, init_params(conv_ch, hidden, P, seed=7))
+        S.sfrom_surrogate_set_scale(s, mu.astype(np.float32), sd.astype(np.float32))
+        xd = torch.tensor(x.reshape(len(x), -1), device="cuda")
+        td = torch.tensor(((t - mu) / sd).astype(np.float32), device="cuda")
+        del t
+        t0 = time.perf_counter()
+        hist = train(s, xd, td, epochs=epochs, lr=1e-3, batch=256, seed=3)
+        torch.cuda.synchronize()
+        out.update({"epochs": epochs, "train_s": time.perf_counter() - t0, "loss_first": hist[0], "loss_last": hist[-1]})
+        log(f"[learned] {len(x)} cells, loss {hist[0]:.3e} -> {hist[-1]:.3e} in {out['train_s']:.1f} s")
+        del xd, td
+        evals = []
+        for r in range(n_eval_media):
+            wl = synth.workload(workload, modes_face=4, modes_edge=2, m=m, realisation=r)
+            h = S.sfrom_create(0, stream)
+            try:
+                problem.setup(h, wl)
+                cells = problem.interior_cells(wl)
+                xe = torch.tensor(problem.cell_features(wl, cells).reshape(len(cells), -1), device="cuda")
+                S.sfrom_build(h, m, wl.shift, S.SFROM_F32)          # warm (staged inputs)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                S.sfrom_build(h, m, wl.shift, S.SFROM_F32)
+                torch.cuda.synchronize()
+                plain = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                acc, mis = S.sfrom_build_learned(h, m, wl.shift, S.SFROM_F32, s, cells, xe, wl.omega_max, tol)
+                torch.cuda.synchronize()
+                learned = time.perf_counter() - t0
+                evals.append({"cells": int(len(cells)), "accepted": int(acc.sum()),
+                              "median_mismatch": float(np.median(mis)), "min_mismatch": float(np.min(mis)),
+                              "plain_build_s": plain, "learned_build_s": learned})
+                log(f"[learned] medium {r}: {int(acc.sum())}/{len(cells)} accepted, median mismatch "
+                    f"{np.median(mis):.2e} (min {np.min(mis):.2e}), build {learned:.2f} s learned vs {plain:.2f} s plain")
+            finally:
+                S.sfrom_destroy(h)
+        out["eval"] = evals
+        out["accepted"] = int(sum(e["accepted"] for e in evals))
+        out["evaluated"] = int(sum(e["cells"] for e in evals))
+    finally:
+        S.sfrom_surrogate_destroy(s)
+    return out

@@ -143,7 +143,7 @@ def sfrom_create(device: int = 0, stream: int = 0):
     h = _P()
     rc = _lib.sfrom_create(C.byref(h), device, _P(stream) if stream else None)
     if rc != 0:
-        raise SfromError(rc, "sfrom_create failed")
+        raise SfromError(rc, "sfrom_create failed: " + _lib.sfrom_last_error(None).decode())
     return h
 
 
