@@ -94,9 +94,9 @@ int sfrom_add_cell(sfrom_t* h, int32_t cell, int32_t n_i, const int64_t* global_
                    const int32_t* rowptr_i, const int32_t* col_i, const double* a_i,
                    const double* b_i);
 
-/* Skeleton piece `piece` (0-based): a connected set of k_p skeleton nodes
- * shared by the same cells (a face interior, an edge line or a corner point
- * of a Cartesian partition), global_node[k_p], with an orthonormal boundary
+/* Skeleton piece `piece` (0-based): a set of k_p skeleton nodes shared by
+ * the same cells (a face interior, an edge line or a corner point of a
+ * Cartesian partition), global_node[k_p], with an orthonormal boundary
  * basis S_p (k_p x b_p, column-major, S_p^T S_p = I) (Sec. 4.1). Each cell's
  * boundary basis S_i is block diagonal over its pieces in ascending piece
  * id. Every skeleton node must lie in exactly one piece.
@@ -135,6 +135,42 @@ int sfrom_setup_voxel_acoustic(sfrom_t* h, const int32_t nvox[3], const double* 
 int sfrom_setup_voxel_elastic(sfrom_t* h, const int32_t nvox[3], const double* c21, const double* rho,
                               const int32_t ncut[3], const int32_t* cuts, int32_t modes_face,
                               int32_t modes_edge);
+
+/* Partition of a general pencil (the one given to sfrom_set_pencil) into
+ * n_cells cells by the divide-and-conquer algorithm of App. A (Alg. 2):
+ * each step splits the largest splittable cell with the sets O_1, O_2,
+ * Gamma of Prop. 1 and the operator and mass splitting of Alg. 1 and eq.
+ * alg1B with constant alpha_kl = alpha in [0, 1] and beta_k = beta in (0, 1).
+ * O is a union of breadth-first levels of the cell's graph (adjacency:
+ * a_kl != 0) from a pseudo-peripheral root, up to the level before the one
+ * that reaches half of the cell's nodes, so Gamma is one level. For a
+ * diagonally dominant A every A_i is diagonally dominant and <= 0 (Prop. 2).
+ * Cells are numbered as Alg. 2 leaves them (the split cell's O_1 side keeps
+ * the last position, its O_2 side is appended); each cell's local nodes are
+ * in reverse Cuthill-McKee order. Pieces are the nodes held by two or more
+ * cells grouped by their exact set of cells, numbered by smallest node,
+ * nodes ascending, each with the normalised constant vector as its basis
+ * (call sfrom_gramian_bases for richer ones). Replaces any cells, pieces,
+ * sources and receivers. Requires a connected graph with a nonzero
+ * diagonal. Errors: ESTATE (no pencil), EINVAL (arguments, graph, or fewer
+ * than n_cells splittable cells), ENOMEM. */
+int sfrom_partition_graph(sfrom_t* h, int32_t n_cells, double alpha, double beta);
+
+/* Replace every piece's basis with the leading eigenvectors of its
+ * frequency-limited Gramian (Sec. 4.1, eq. trgr): the eigenpairs (lambda,
+ * z) of a local pencil with lambda <= omega_max^2 (z B-orthonormal; at least
+ * the lowest pair), restricted to the piece, give G = sum z z^T; the basis
+ * holds G's eigenvectors with eigenvalue above eps times the largest, at
+ * most max_modes of them (single-node pieces: [1]). The local pencil is the
+ * sum of the split operators of the cells holding the piece on their union,
+ * cut to the nodes within graph distance depth + 1 of the piece by one
+ * Prop. 1 / Alg. 1 split (alpha = beta = 1/2) with O the nodes within
+ * distance depth (depth < 0: the whole union); it must have at most 4096
+ * nodes (dense eigensolver on the host, one piece per thread). Works on any
+ * partition; sources and receivers must be set again afterwards.
+ * Errors: ESTATE (no partition), EINVAL (arguments, local pencil too
+ * large), ENONFINITE, ENOMEM. */
+int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int32_t max_modes, int32_t depth);
 
 /* ---------------------------------------------------------------------------
  * Off-line stage (Alg. alg1red stage 1)

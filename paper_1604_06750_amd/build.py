@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libsfrom.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = os.environ.get("SFROM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "cartesian.cpp", "elastic.cpp", "offline.hip", "wide.hip", "online.hip", "fine.hip", "surrogate.hip"]
+SOURCES = ["api.cpp", "cartesian.cpp", "elastic.cpp", "general.cpp", "offline.hip", "wide.hip", "online.hip", "fine.hip", "surrogate.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -62,6 +62,8 @@ _SIGS = {
     "sfrom_add_piece": [_P, C.c_int32, C.c_int32, _P, C.c_int32, _P],
     "sfrom_setup_voxel_acoustic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
     "sfrom_setup_voxel_elastic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
+    "sfrom_partition_graph": [_P, C.c_int32, C.c_double, C.c_double],
+    "sfrom_gramian_bases": [_P, C.c_double, C.c_double, C.c_int32, C.c_int32],
     "sfrom_build": [_P, C.POINTER(sfrom_build_opts)],
     "sfrom_import_rom": [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P],
     "sfrom_export_rom": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P],
@@ -199,6 +201,14 @@ def sfrom_setup_voxel_elastic(h, c21, rho, cuts, modes_face, modes_edge):
     cc = np.ascontiguousarray(np.concatenate([np.asarray(x, np.int32) for x in cuts]) if ncut.sum() else np.zeros(1, np.int32))
     _check(h, _lib.sfrom_setup_voxel_elastic(h, _ptr(nvox), _ptr(c), _ptr(r), _ptr(ncut), _ptr(cc),
                                              int(modes_face), int(modes_edge)))
+
+
+def sfrom_partition_graph(h, n_cells, alpha=0.5, beta=0.5):
+    _check(h, _lib.sfrom_partition_graph(h, int(n_cells), float(alpha), float(beta)))
+
+
+def sfrom_gramian_bases(h, omega_max, eps, max_modes, depth):
+    _check(h, _lib.sfrom_gramian_bases(h, float(omega_max), float(eps), int(max_modes), int(depth)))
 
 
 def sfrom_build(h, m, shift, online_prec=SFROM_F32, m_per_cell=None, cells_per_batch=0):

@@ -448,3 +448,36 @@ def random_spd(n: int, rng: np.random.Generator, cond: float = 10.0, scale: floa
     ev = scale * np.logspace(-np.log10(cond), 0.0, n)
     m = (q * ev) @ q.T
     return 0.5 * (m + m.T)
+
+
+# --------------------------------------------------------------------------
+# unstructured input pencil
+# --------------------------------------------------------------------------
+
+def geometric_graph(n: int, k: int, seed: int):
+    """A synthetic unstructured-mesh pencil (the input of a general
+    partition, standing in for a non-Cartesian discretisation): n seeded
+    points in the unit cube, each joined to its k nearest neighbours
+    (symmetrised), edge weight 1 / |x_i - x_j|^2 scaled to mean 1; A = minus
+    the weighted graph Laplacian minus a sink of 0.2 on nodes within 0.08 of
+    the cube's faces (so A < 0, diagonally dominant); b = 0.8 + 0.4 u,
+    u uniform. Returns (A as scipy CSR with sorted columns, b, points)."""
+    import scipy.sparse as sp
+    from scipy.spatial import cKDTree
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.random((n, 3))
+    _, nb = cKDTree(x).query(x, k + 1)
+    rows = np.repeat(np.arange(n), k)
+    cols = nb[:, 1:].ravel()
+    W = sp.coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, n)).tocsr()
+    W = ((W + W.T) > 0).astype(float).tocoo()
+    d2 = np.sum((x[W.row] - x[W.col]) ** 2, axis=1)
+    w = 1.0 / d2
+    w /= w.mean()
+    W = sp.csr_matrix((w, (W.row, W.col)), shape=(n, n))
+    near = np.any((x < 0.08) | (x > 0.92), axis=1)
+    diag = -np.asarray(W.sum(axis=1)).ravel() - 0.2 * near
+    A = (W + sp.diags(diag)).tocsr()
+    A.sort_indices()
+    b = 0.8 + 0.4 * rng.random(n)
+    return A, b, x

@@ -1,0 +1,152 @@
+"""Host-side parity of the general partition and the Gramian bases
+(sfrom_partition_graph, sfrom_gramian_bases on a host-only handle) with the
+oracle (oracle/divconq.py, oracle/gramian.py): cells' node sets and piece
+node sets bit for bit, split operators and masses bit for bit (the library
+takes the same products and sums in the same order), piece projectors
+S_p S_p^T within 1e-9 and equal basis sizes; plus the error paths."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import divconq as dc
+from oracle import fine
+from oracle import gramian as gr
+
+
+def _lib():
+    from paper_1604_06750_amd import sfrom
+    return sfrom
+
+
+def _handle(A, b):
+    S = _lib()
+    h = S.sfrom_create(-1, 0)
+    A = sp.csr_matrix(A); A.sort_indices()
+    S.sfrom_set_pencil(h, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, b)
+    return h
+
+
+def _acoustic(nvox, seed):
+    sig, rho = synth.acoustic_medium(nvox, seed, ell_sigma=4.0, ell_rho=2.0)
+    return fine.assemble_acoustic(sig, rho)
+
+
+def _check_partition(h, P):
+    S = _lib()
+    info = S.sfrom_get_info(h)
+    assert info["n_cells"] == len(P.subs) and info["n_pieces"] == len(P.pieces)
+    for i, s in enumerate(P.subs):
+        c = S.sfrom_export_cell(h, i)
+        g = c["global_node"]
+        o = np.argsort(g)
+        assert np.array_equal(g[o], s.nodes)
+        n = len(g)
+        Al = sp.csr_matrix((c["a"], c["col"], c["rowptr"]), shape=(n, n)).toarray()[np.ix_(o, o)]
+        assert np.array_equal(Al, s.A.toarray()), f"cell {i}: split operator differs"
+        assert np.array_equal(c["b"][o], s.b)
+        # local order is a permutation with a band no wider than the ascending order's
+        rp, cl = c["rowptr"], c["col"]
+        bw = max(abs(r - cl[k]) for r in range(n) for k in range(rp[r], rp[r + 1]))
+        As = s.A.tocoo()
+        assert bw <= np.abs(As.row - As.col).max()
+    for p, pc in enumerate(P.pieces):
+        g, Sb = S.sfrom_export_piece(h, p)
+        assert np.array_equal(g, pc.nodes)
+        assert Sb.shape[1] == 1 and np.allclose(Sb[:, 0], 1.0 / np.sqrt(len(g)))
+
+
+def _check_bases(h, P, omega_max, eps, max_modes, depth, tol=1e-9):
+    S = _lib()
+    ops = {c: (s.nodes, s.A, s.b) for c, s in enumerate(P.subs)}
+    ref = gr.gramian_bases(P, ops, omega_max, eps, max_modes, depth)
+    S.sfrom_gramian_bases(h, omega_max, eps, max_modes, depth)
+    worst = 0.0
+    for p, pc in enumerate(P.pieces):
+        g, Sb = S.sfrom_export_piece(h, p)
+        assert Sb.shape[1] == ref[p].shape[1], f"piece {p}: {Sb.shape[1]} vs {ref[p].shape[1]} modes"
+        assert np.allclose(Sb.T @ Sb, np.eye(Sb.shape[1]), atol=1e-12)
+        worst = max(worst, np.abs(Sb @ Sb.T - ref[p] @ ref[p].T).max())
+    assert worst <= tol, worst
+    return ref
+
+
+def test_partition_and_bases_acoustic():
+    A, b = _acoustic((12, 12, 12), 3)
+    P = dc.GeneralPartition(A, b, 8)
+    S = _lib()
+    h = _handle(A, b)
+    try:
+        S.sfrom_partition_graph(h, 8)
+        _check_partition(h, P)
+        _check_bases(h, P, 0.8, 1e-6, 6, -1)
+        _check_bases(h, P, 0.8, 1e-6, 6, 2)
+    finally:
+        S.sfrom_destroy(h)
+
+
+def test_partition_and_bases_unstructured_graph():
+    A, b, _ = synth.geometric_graph(1500, 6, 5)
+    P = dc.GeneralPartition(A, b, 5)
+    S = _lib()
+    h = _handle(A, b)
+    try:
+        S.sfrom_partition_graph(h, 5)
+        _check_partition(h, P)
+        _check_bases(h, P, 0.45, 1e-6, 5, 1)
+    finally:
+        S.sfrom_destroy(h)
+
+
+def test_partition_alpha_beta():
+    A, b = _acoustic((8, 8, 8), 4)
+    P = dc.GeneralPartition(A, b, 3, alpha=0.3, beta=0.7)
+    S = _lib()
+    h = _handle(A, b)
+    try:
+        S.sfrom_partition_graph(h, 3, 0.3, 0.7)
+        _check_partition(h, P)
+    finally:
+        S.sfrom_destroy(h)
+
+
+def test_general_errors():
+    S = _lib()
+    h = S.sfrom_create(-1, 0)
+    try:
+        with pytest.raises(S.SfromError) as e:
+            S.sfrom_partition_graph(h, 2)
+        assert e.value.name == "ESTATE"
+        with pytest.raises(S.SfromError) as e:
+            S.sfrom_gramian_bases(h, 1.0, 1e-6, 4, 1)
+        assert e.value.name == "ESTATE"
+        A, b = _acoustic((6, 6, 6), 1)
+        A = sp.csr_matrix(A); A.sort_indices()
+        S.sfrom_set_pencil(h, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, b)
+        for args in ((1,), (2, 1.5), (2, 0.5, 0.0), (2, 0.5, 1.0)):
+            with pytest.raises(S.SfromError) as e:
+                S.sfrom_partition_graph(h, *args)
+            assert e.value.name == "EINVAL"
+        with pytest.raises(S.SfromError) as e:
+            S.sfrom_partition_graph(h, 10 ** 5)             # more cells than splittable subdomains
+        assert e.value.name == "EINVAL" and "split" in S.sfrom_last_error(h)
+        # a disconnected graph
+        D = sp.block_diag([A, A]).tocsr(); D.sort_indices()
+        S.sfrom_set_pencil(h, D.indptr.astype(np.int64), D.indices.astype(np.int32), D.data, np.concatenate([b, b]))
+        with pytest.raises(S.SfromError) as e:
+            S.sfrom_partition_graph(h, 2)
+        assert e.value.name == "EINVAL" and "connected" in S.sfrom_last_error(h)
+        # a local pencil beyond the dense limit
+        B, bb = _acoustic((20, 20, 20), 2)
+        B = sp.csr_matrix(B); B.sort_indices()
+        S.sfrom_set_pencil(h, B.indptr.astype(np.int64), B.indices.astype(np.int32), B.data, bb)
+        S.sfrom_partition_graph(h, 2)
+        with pytest.raises(S.SfromError) as e:
+            S.sfrom_gramian_bases(h, 1.0, 1e-6, 4, -1)
+        assert e.value.name == "EINVAL" and "dense limit" in S.sfrom_last_error(h)
+        for args in ((0.0, 1e-6, 4, 1), (1.0, 1.0, 4, 1), (1.0, 1e-6, 0, 1)):
+            with pytest.raises(S.SfromError) as e:
+                S.sfrom_gramian_bases(h, *args)
+            assert e.value.name == "EINVAL"
+    finally:
+        S.sfrom_destroy(h)
