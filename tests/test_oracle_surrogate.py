@@ -120,3 +120,51 @@ def test_tf_mismatch_accepts_lanczos_and_rejects_perturbed(floating_cell):
     G2 = [g.copy() for g in G]
     G2[1] = 1.01 * G2[1]
     assert sg.tf_mismatch(A, b, W, Gh, G2, wmax) > 1e-3
+
+
+def test_adam_constant_gradient_and_scale_invariance():
+    """Invariants of the moment recurrences beyond the first step: for a
+    constant gradient the bias-corrected moments equal g and g^2 at every
+    step, so every step moves by -lr g / (|g| + eps); and scaling all
+    gradients by c > 0 leaves the steps unchanged (eps negligible). A
+    dropped decay term, a wrong bias-correction power or a missing square
+    root fails one of these from step 2 on."""
+    rng = np.random.default_rng(5)
+    th = rng.normal(size=7)
+    g = rng.normal(size=7)
+    st = (np.zeros(7), np.zeros(7), 0)
+    cur = th.copy()
+    for t in range(1, 11):
+        nxt, st = sg.adam_step(cur, g, st, 1e-2)
+        assert np.allclose(nxt - cur, -1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-16), t
+        cur = nxt
+    gs = [rng.normal(size=7) for _ in range(6)]
+    a, sa = th.copy(), (np.zeros(7), np.zeros(7), 0)
+    c, sc = th.copy(), (np.zeros(7), np.zeros(7), 0)
+    for gk in gs:
+        a, sa = sg.adam_step(a, gk, sa, 1e-3, eps=1e-30)
+        c, sc = sg.adam_step(c, 1e4 * gk, sc, 1e-3, eps=1e-30)
+    assert np.allclose(a, c, rtol=0, atol=1e-13)
+    # a sign flip of the gradient at step 2 partly cancels the first moment:
+    # m_2 = 0.9 * 0.1 g - 0.1 g = -0.01 g, v_2 = 0.001999 g^2 (bias factors 0.19, 0.001999)
+    th0 = np.array([0.0]); s2 = (np.zeros(1), np.zeros(1), 0)
+    th1, s2 = sg.adam_step(th0, np.array([2.0]), s2, 1.0, eps=0.0)
+    th2, s2 = sg.adam_step(th1, np.array([-2.0]), s2, 1.0, eps=0.0)
+    mh = -0.01 * 2.0 / (1 - 0.9 ** 2)
+    vh = (0.999 * 0.001 * 4.0 + 0.001 * 4.0) / (1 - 0.999 ** 2)
+    assert abs((th2 - th1)[0] - (-mh / np.sqrt(vh))) < 1e-12
+
+
+def test_reconstruct_layout_by_hand():
+    """b = 2, m = 3: the factor vector is [L(Ghat^2), L(G^2), L(Ghat^3),
+    L(G^3)], each the row-major lower triangle (l11, l21, l22); the blocks
+    are L L^T plus the relative shift, written out by hand here."""
+    y = np.array([1.0, 2.0, 3.0,   4.0, 0.5, 1.0,   2.0, -1.0, 1.0,   3.0, 0.0, 2.0])
+    Gh, G = sg.reconstruct(y, 2, 3)
+    hand = [np.array([[1.0, 2.0], [2.0, 13.0]]), np.array([[16.0, 2.0], [2.0, 1.25]]),
+            np.array([[4.0, -2.0], [-2.0, 2.0]]), np.array([[9.0, 0.0], [0.0, 4.0]])]
+    got = [Gh[0], G[0], Gh[1], G[1]]
+    for M, H in zip(got, hand):
+        shift = M - H
+        assert np.allclose(shift, shift[0, 0] * np.eye(2), atol=1e-15)
+        assert 0.0 <= shift[0, 0] <= 1e-9 * np.trace(H)
