@@ -71,6 +71,54 @@ def build(verbose: bool = True, incremental: bool = False) -> str:
     return OUT
 
 
+# Host sanitizers: AddressSanitizer and UndefinedBehaviorSanitizer on the
+# host code only (each flag behind -Xarch_host; device code is compiled as
+# usual). The library is loaded with the ASan runtime preloaded
+# (asan_runtime()) and SFROM_LIBRARY pointing at it, and exercised through
+# host-only handles.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SAN_DIR = os.path.join(BUILD_DIR, "sanitize")
+
+
+def asan_runtime() -> str:
+    r = subprocess.run([_hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return r.stdout.strip()
+
+
+def build_sanitized(verbose: bool = True) -> str:
+    """libsfrom.so with host ASan + UBSan in _build/sanitize/ (rebuilt when
+    a source or header is newer than it)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    out = os.path.join(SAN_DIR, "libsfrom.so")
+    deps = [os.path.join(CSRC, x) for x in SOURCES] + [os.path.join(CSRC, "sfrom_internal.h"),
+                                                       os.path.join(os.path.dirname(HERE), "include", "sfrom.h"),
+                                                       __file__]
+    if os.path.exists(out) and os.path.getmtime(out) >= max(os.path.getmtime(d) for d in deps):
+        return out
+
+    def comp(src):
+        obj = os.path.join(SAN_DIR, os.path.basename(src) + ".o")
+        cmd = [_hipcc(), "-x", "hip", *COMMON, *SANITIZE, "-g", "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(comp, SOURCES))
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *SANITIZE, "-shared-libsan", *objs,
+           "-o", out + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(out + ".tmp", out)
+    if verbose:
+        print(f"built {out}")
+    return out
+
+
 if __name__ == "__main__":
     build(incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsfrom.so")
+# SFROM_LIBRARY selects another build of the same library (the host-
+# sanitized one of build.build_sanitized, for instance)
+LIB_PATH = os.environ.get("SFROM_LIBRARY") or os.path.join(_HERE, "libsfrom.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_1604_06750_amd.build`")
