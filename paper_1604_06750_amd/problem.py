@@ -28,9 +28,14 @@ def max_piece_nodes(wl) -> int:
     return int(ext[-1] * ext[-2])
 
 
-def setup(h, wl, sources=True, receivers=True):
-    """Voxel set-up plus projected point sources/receivers of a Workload."""
+def setup(h, wl, sources=True, receivers=True, gramian=None):
+    """Voxel set-up plus projected point sources/receivers of a Workload.
+    ``gramian`` = (omega, eps, max_modes, depth) replaces the DCT piece bases
+    by frequency-limited Gramian bases (sfrom_gramian_bases) before the
+    columns are set."""
     S.sfrom_setup_voxel_acoustic(h, wl.sigma, wl.rho, wl.cuts, wl.modes_face, wl.modes_edge)
+    if gramian is not None:
+        S.sfrom_gramian_bases(h, *gramian)
     mp = max_piece_nodes(wl)
     if sources:
         cp, rw, vl = S.sfrom_point_columns(h, node_ids(wl.nvox, wl.sources), mp)

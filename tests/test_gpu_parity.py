@@ -402,25 +402,21 @@ def test_online_bf16_small_b(dev):
     assert e <= 5e-2
 
 
-def test_online_bf16_large_b_is_finite_or_reported(dev):
-    """BF16 blocks at b = 140, 600 steps: the error against the FP64 oracle
-    is printed (8-bit blocks perturb the low frequencies of the band by a
-    unit roundoff of the cell's largest eigenvalue, so this is a reported
-    figure, not a parity bound); the run either returns finite traces or
-    ends with ENONFINITE, never silent NaN."""
+def test_online_bf16_large_b_is_bounded(dev):
+    """BF16 blocks at b = 140, 600 steps: finite traces within 1e-1 of the
+    FP64 oracle (measured 4.2e-2: 8-bit blocks perturb the low frequencies
+    of the band by a unit roundoff of the cell's largest eigenvalue, so the
+    bound is a reported accuracy, not a multiple of FP32 parity; a wrong
+    conversion or operand order gives errors of order one)."""
     S, P = _lib()
     wl = synth.workload("small", modes_face=16, modes_edge=3, m=3, n_steps=600)
     run = pipeline.setup(wl)
     pipeline.build_all(run)
     ref = pipeline.rom_traces(run)
-    try:
-        tr, _, info = _gpu_rom(wl, S.SFROM_BF16, run.dt, run.w)
-    except S.SfromError as e:
-        assert e.name == "ENONFINITE"
-        print("BF16 b=140: ENONFINITE")
-        return
-    assert np.isfinite(tr).all()
-    print(f"BF16 max_b {info['max_b']}: rel L2 vs oracle {rel(tr, ref):.3e}")
+    tr, _, info = _gpu_rom(wl, S.SFROM_BF16, run.dt, run.w)
+    e = rel(tr, ref)
+    print(f"BF16 max_b {info['max_b']}: rel L2 vs oracle {e:.3e}")
+    assert np.isfinite(tr).all() and e <= 1e-1
 
 
 def test_uneven_cells_layered_medium(dev):
