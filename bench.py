@@ -333,6 +333,80 @@ def elastic_block(S, problem, synth, stream, dev, ref_steps=1000, fine_steps=300
         S.sfrom_destroy(h)
 
 
+def layered_block(S, problem, synth, stream, dev, ref_steps=600, fine_steps=200):
+    """The uneven-cell case: 256 x 256 x 128 voxels with six layers (contrast
+    3:1, +-10% smooth perturbation), cells of 8..16 voxels aligned to the
+    layers with m_i = 3..8 by cell size, 4 face + 2 edge + 1 corner modes,
+    256 sources, 6000 steps. One warm-up and one timed job for the BF16
+    (FP32 accumulation) and the FP32 on-line blocks; the fine grid's rate
+    from ``fine_steps`` FP32 steps; receiver errors against the FP64 fine
+    grid over the first ``ref_steps`` steps."""
+    import torch
+    wl = synth.workload("layered", modes_face=4, modes_edge=2)
+    nt = wl.n_steps
+    mpc = wl.extra["m_per_cell"]
+    h = S.sfrom_create(0, stream.cuda_stream)
+    try:
+        t0 = time.perf_counter()
+        problem.setup(h, wl)
+        lam = S.sfrom_fine_lambda_max(h)
+        dt = wl.cfl_fraction * 2.0 / np.sqrt(lam)
+        info = S.sfrom_get_info(h)
+        ns, nr = info["n_sources"], info["n_receivers"]
+        log(f"[bench] layered set-up {time.perf_counter() - t0:.1f} s: n={info['n']}, cells={info['n_cells']}")
+        w = torch.tensor(synth.ricker(nt, dt, wl.f_p), dtype=torch.float64, device=dev)
+        tr = torch.zeros((nt, nr, ns), dtype=torch.float32, device=dev)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        res = {}
+        roms = {}
+        for name, prec in (("bf16", S.SFROM_BF16), ("f32", S.SFROM_F32)):
+            def job():
+                S.sfrom_build(h, int(mpc.max()), wl.shift, prec, m_per_cell=mpc)
+                e1.record(stream)
+                S.sfrom_reset(h)
+                S.sfrom_run(h, nt, dt, w, tr)
+            job()
+            torch.cuda.synchronize()
+            e0.record(stream)
+            job()
+            e2.record(stream)
+            torch.cuda.synchronize()
+            job_ms, online_ms = e0.elapsed_time(e2), e1.elapsed_time(e2)
+            roms[name] = tr[:ref_steps].double().cpu().numpy()
+            res[name] = {"job_source_steps_per_s": round(ns * nt / (job_ms / 1e3), 1),
+                         "online_source_steps_per_s": round(ns * nt / (online_ms / 1e3), 1),
+                         "build_ms": round(job_ms - online_ms, 1), "online_ms": round(online_ms, 1)}
+            log(f"[bench] layered {name}: job {job_ms:.0f} ms (on-line {online_ms:.0f} ms)")
+        built = S.sfrom_get_info(h)
+        del tr
+        tf = torch.zeros((fine_steps, nr, ns), dtype=torch.float32, device=dev)
+        S.sfrom_fine_run(h, 20, dt, w, tf, S.SFROM_F32)
+        S.sfrom_fine_reset(h)
+        e0.record(stream)
+        S.sfrom_fine_run(h, fine_steps, dt, w, tf, S.SFROM_F32)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        fine_ssps = ns / (e0.elapsed_time(e2) / fine_steps / 1e3)
+        del tf
+        S.sfrom_fine_reset(h)
+        t64 = torch.zeros((ref_steps, nr, ns), dtype=torch.float64, device=dev)
+        S.sfrom_fine_run(h, ref_steps, dt, w, t64, S.SFROM_F64)
+        torch.cuda.synchronize()
+        ref = t64.cpu().numpy()
+        for name in res:
+            err = float(np.linalg.norm(roms[name] - ref) / np.linalg.norm(ref))
+            res[name].update({"rel_l2_vs_fine_fp64_first_steps": err, "meets_gate": bool(err <= GATE),
+                              "speedup_online_vs_fine": round(res[name]["online_source_steps_per_s"] / fine_ssps, 3),
+                              "speedup_job_vs_fine": round(res[name]["job_source_steps_per_s"] / fine_ssps, 3)})
+        return {"workload": (f"3D layered acoustic, {wl.nvox[0]}x{wl.nvox[1]}x{wl.nvox[2]} voxels, 6 layers, "
+                             f"{info['n_cells']} cells of 8..16 voxels, m_i {int(mpc.min())}..{int(mpc.max())}, "
+                             f"4 face + 2 edge + 1 corner modes, {ns} sources, {nr} receivers, {nt} steps"),
+                "n_fine": info["n"], "max_b": built["max_b"], "error_steps": ref_steps,
+                "fine_source_steps_per_s": round(fine_ssps, 1), **res}
+    finally:
+        S.sfrom_destroy(h)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +424,7 @@ def main():
                     help="skip the extra measurement at 4 face + 2 edge modes, m = 4 (b = 56)")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped workload")
     ap.add_argument("--no-elastic", action="store_true", help="skip the layered elastic workload")
+    ap.add_argument("--no-layered", action="store_true", help="skip the layered uneven-cell workload")
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
@@ -497,6 +572,7 @@ def main():
         extra = extra_setting(S, problem, synth, args, stream, dev, tdt, prec, nt, dt, w, fine_ssps)
     paper = None if args.no_paper else paper_shaped(S, problem, synth, stream, dev)
     elastic = None if args.no_elastic else elastic_block(S, problem, synth, stream, dev)
+    layered = None if args.no_layered else layered_block(S, problem, synth, stream, dev)
     out = {
         "metric": METRIC,
         # the metric is defined at the gate: no value when the traces miss it
@@ -539,6 +615,7 @@ def main():
         "extra_b56_m4": extra,
         "paper_shaped": paper,
         "elastic": elastic,
+        "layered": layered,
     }
     S.sfrom_destroy(h)
     if not args.no_cpu:
