@@ -407,6 +407,91 @@ def layered_block(S, problem, synth, stream, dev, ref_steps=600, fine_steps=200)
         S.sfrom_destroy(h)
 
 
+def general_block(S, synth, stream, dev, n=200_000, n_cells=128, ns=64, nr=256, nt=3000):
+    """General sparse input: a seeded unstructured pencil (n points, 6
+    nearest neighbours), partitioned by the divide-and-conquer algorithm of
+    App. A into ``n_cells`` cells, Gramian piece bases (2 omega_max, eps 1e-4,
+    at most 4 modes, slab depth 1), m = 3 with the breakdown policy on; the
+    band edge is omega_max = sqrt(lambda_max) / 10, point sources and
+    receivers at seeded skeleton nodes. One warm-up and one timed job (FP32
+    on-line), the generic fine kernel's rate and the receiver error against
+    the FP64 fine grid."""
+    import torch
+    A, bv, _ = synth.geometric_graph(n, 6, 17)
+    h = S.sfrom_create(0, stream.cuda_stream)
+    try:
+        t0 = time.perf_counter()
+        S.sfrom_set_pencil(h, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, bv)
+        S.sfrom_partition_graph(h, n_cells)
+        lam = S.sfrom_fine_lambda_max(h)
+        om = np.sqrt(lam) / 10.0
+        S.sfrom_gramian_bases(h, 2.0 * om, 1e-4, 4, 1)
+        info = S.sfrom_get_info(h)
+        pieces = [S.sfrom_export_piece(h, p)[0] for p in range(info["n_pieces"])]
+        skel = np.sort(np.concatenate(pieces))
+        kmax = max(len(g) for g in pieces)
+        rng = np.random.Generator(np.random.PCG64(29))
+        cp, rw, vl = S.sfrom_point_columns(h, np.sort(rng.choice(skel, ns, replace=False)), kmax)
+        S.sfrom_set_sources(h, cp, rw, vl, project=False)
+        cp, rw, vl = S.sfrom_point_columns(h, np.sort(rng.choice(skel, nr, replace=False)), kmax)
+        S.sfrom_set_receivers(h, cp, rw, vl, project=False)
+        S.sfrom_set_breakdown_policy(h, 1)
+        setup_s = time.perf_counter() - t0
+        log(f"[bench] general set-up {setup_s:.1f} s: n={n}, cells={info['n_cells']}, pieces={info['n_pieces']}")
+        dt = 0.5 * 2.0 / np.sqrt(lam)
+        w = torch.tensor(synth.ricker(nt, dt, om / (2.0 * np.pi * 2.5)), dtype=torch.float64, device=dev)
+        tr = torch.zeros((nt, nr, ns), dtype=torch.float32, device=dev)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+
+        def job():
+            S.sfrom_build(h, 3, -om ** 2 / 10.0, S.SFROM_F32)
+            e1.record(stream)
+            S.sfrom_reset(h)
+            S.sfrom_run(h, nt, dt, w, tr)
+        job()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        job()
+        e2.record(stream)
+        torch.cuda.synchronize()
+        job_ms, online_ms = e0.elapsed_time(e2), e1.elapsed_time(e2)
+        built = S.sfrom_get_info(h)
+        m_cells = [len(S.sfrom_export_rom(h, i)[0]) for i in range(info["n_cells"])]
+        rom = tr.double().cpu().numpy()
+        tf = torch.zeros((nt, nr, ns), dtype=torch.float32, device=dev)
+        S.sfrom_fine_run(h, 50, dt, w, tf, S.SFROM_F32)
+        S.sfrom_fine_reset(h)
+        e0.record(stream)
+        S.sfrom_fine_run(h, nt, dt, w, tf, S.SFROM_F32)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        fine_ssps = ns * nt / (e0.elapsed_time(e2) / 1e3)
+        del tf
+        S.sfrom_fine_reset(h)
+        t64 = torch.zeros((nt, nr, ns), dtype=torch.float64, device=dev)
+        S.sfrom_fine_run(h, nt, dt, w, t64, S.SFROM_F64)
+        torch.cuda.synchronize()
+        ref = t64.cpu().numpy()
+        err = float(np.linalg.norm(rom - ref) / np.linalg.norm(ref))
+        return {"workload": (f"unstructured pencil, {n} nodes (6 nearest neighbours), {info['n_cells']} cells by "
+                             f"the divide-and-conquer partition, {info['n_pieces']} pieces with Gramian bases "
+                             f"(2 omega_max, eps 1e-4, <= 4 modes, slab depth 1), m = 3 with the breakdown policy, "
+                             f"{ns} sources, {nr} receivers, {nt} steps, FP32 on-line"),
+                "setup_s": round(setup_s, 2), "max_b": built["max_b"], "piece_dofs": built["n_piece_dofs"],
+                "cells_with_m_below_3": int(sum(1 for m in m_cells if m < 3)),
+                "note": ("the level-set separators of the partition meet in small junction pieces; cells that touch "
+                         "them only through skeleton nodes lose Krylov rank (Assumption 1) and run with m_i < 3, "
+                         "which the receiver error reflects; the path itself matches the oracle (GPU tests)"),
+                "rel_l2_vs_fine_fp64": err, "meets_gate": bool(err <= GATE),
+                "job_source_steps_per_s": round(ns * nt / (job_ms / 1e3), 1),
+                "online_source_steps_per_s": round(ns * nt / (online_ms / 1e3), 1),
+                "fine_source_steps_per_s": round(fine_ssps, 1), "fine_kernel": "generic CSR rows",
+                "build_ms": round(job_ms - online_ms, 1), "online_ms": round(online_ms, 1),
+                "speedup_online_vs_fine": round(ns * nt / (online_ms / 1e3) / fine_ssps, 3)}
+    finally:
+        S.sfrom_destroy(h)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,6 +510,7 @@ def main():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped workload")
     ap.add_argument("--no-elastic", action="store_true", help="skip the layered elastic workload")
     ap.add_argument("--no-layered", action="store_true", help="skip the layered uneven-cell workload")
+    ap.add_argument("--no-general", action="store_true", help="skip the general sparse (unstructured) workload")
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
@@ -573,6 +659,7 @@ def main():
     paper = None if args.no_paper else paper_shaped(S, problem, synth, stream, dev)
     elastic = None if args.no_elastic else elastic_block(S, problem, synth, stream, dev)
     layered = None if args.no_layered else layered_block(S, problem, synth, stream, dev)
+    general = None if args.no_general else general_block(S, synth, stream, dev)
     out = {
         "metric": METRIC,
         # the metric is defined at the gate: no value when the traces miss it
@@ -616,6 +703,7 @@ def main():
         "paper_shaped": paper,
         "elastic": elastic,
         "layered": layered,
+        "general": general,
     }
     S.sfrom_destroy(h)
     if not args.no_cpu:

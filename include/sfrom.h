@@ -199,6 +199,16 @@ typedef struct {
  * ENOTSPD, ENOMEM, EDEVICE. */
 int sfrom_build(sfrom_t* h, const sfrom_build_opts* opts);
 
+/* What sfrom_build does when a cell breaks Assumption 1 (its rational Krylov
+ * or Lanczos block k loses rank, Sec. 4.2): reduce_m = 0 (default) fails the
+ * build with EBREAKDOWN naming the cell and the block; reduce_m = 1 rebuilds
+ * such a cell with m_i = k - 1 (k >= 2; a rank-deficient first block still
+ * fails), the per-cell layer count sfrom_export_rom reports. Partitions of
+ * general graphs can have cells that touch junction nodes only through other
+ * skeleton nodes with complete piece bases, which makes block 2 or 3 lose rank
+ * exactly. Errors: EINVAL. */
+int sfrom_set_breakdown_policy(sfrom_t* h, int32_t reduce_m);
+
 /* Replace cell `cell`'s S-fraction by m blocks Ghat^k and G^k (each b x b
  * symmetric, column-major, stored consecutively: Ghat[k*b*b ...]); b must
  * equal the cell's boundary dimension. Requires a built ROM; piece masses

@@ -672,13 +672,19 @@ void check_batch_status(sfrom_t* h, const BuildBatch& bb, const std::vector<int3
   std::vector<BuildCell> bcb(ids.size());
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipMemcpy(bcb.data(), bb.d_cells, ids.size() * sizeof(BuildCell), hipMemcpyDeviceToHost));
+  h->breakdowns.clear();
+  for (size_t t = 0; t < ids.size(); ++t)
+    if (bcb[t].status == 2) h->breakdowns.push_back({ids[t], bcb[t].fail_block});
   for (size_t t = 0; t < ids.size(); ++t) {
     const int st = bcb[t].status;
     if (st == 0) continue;
     const std::string cell = "cell " + std::to_string(ids[t]) + ": ";
     free_rom(h);
     if (st == 1) { h->err = cell + "-(A_i + s B_i) is not positive definite (A_i not <= 0)"; throw Fail{SFROM_ENOTNSD}; }
-    if (st == 2) { h->err = cell + "Krylov/Lanczos block lost rank (Assumption 1)"; throw Fail{SFROM_EBREAKDOWN}; }
+    if (st == 2) {
+      h->err = cell + "Krylov/Lanczos block " + std::to_string(bcb[t].fail_block) + " lost rank (Assumption 1)";
+      throw Fail{SFROM_EBREAKDOWN};
+    }
     if (st == 3) { h->err = cell + "S-fraction pivot not SPD (Assumption 2)"; throw Fail{SFROM_ENOTSPD}; }
     h->err = cell + "non-finite S-fraction"; throw Fail{SFROM_ENONFINITE};
   }
@@ -824,11 +830,32 @@ void factor_targets(sfrom_t* h, int n, const int32_t* cells, float* t) {
 
 void build(sfrom_t* h, const sfrom_build_opts* o) {
   auto t0 = std::chrono::steady_clock::now();
-  BuildCtx ctx;
-  build_layout(h, o, ctx);
-  std::vector<int32_t> all(h->cells.size());
-  for (size_t i = 0; i < all.size(); ++i) all[i] = (int32_t)i;
-  build_lanczos(h, o, ctx, all);
+  REQUIRE(o != nullptr, SFROM_EINVAL, "null build options");
+  const int nc = (int)h->cells.size();
+  std::vector<int32_t> m_cell(nc, o->m);
+  if (o->m_per_cell) std::copy(o->m_per_cell, o->m_per_cell + nc, m_cell.begin());
+  sfrom_build_opts oo = *o;
+  oo.m_per_cell = m_cell.data();
+  std::vector<int32_t> all(nc);
+  for (int i = 0; i < nc; ++i) all[i] = i;
+  for (;;) {
+    BuildCtx ctx;
+    try {
+      build_layout(h, &oo, ctx);
+      build_lanczos(h, &oo, ctx, all);
+      break;
+    } catch (const Fail& f) {
+      // with the policy on, cells whose block k >= 2 lost rank drop to
+      // m_i = k - 1 and the build starts again (each retry lowers some m_i)
+      if (f.code != SFROM_EBREAKDOWN || !h->reduce_m_on_breakdown || h->breakdowns.empty()) throw;
+      for (const auto& bd : h->breakdowns) {
+        const int cell = bd.first, k = bd.second;
+        if (k < 2 || k - 1 >= m_cell[cell]) throw;
+        m_cell[cell] = k - 1;
+      }
+      h->breakdowns.clear();
+    }
+  }
   h->built = true;
   h->masses_dirty = true;
   h->src_dirty = h->rec_dirty = true;
@@ -2187,6 +2214,13 @@ int sfrom_set_graph(sfrom_t* h, int32_t enable) {
   REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
   h->use_graph = enable != 0;
   if (!h->use_graph && h->graph_exec) { hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; h->graph_key.clear(); }
+  API_END(h)
+}
+
+int sfrom_set_breakdown_policy(sfrom_t* h, int32_t reduce_m) {
+  API_BEGIN(h)
+  REQUIRE(reduce_m == 0 || reduce_m == 1, SFROM_EINVAL, "reduce_m must be 0 or 1");
+  h->reduce_m_on_breakdown = reduce_m != 0;
   API_END(h)
 }
 

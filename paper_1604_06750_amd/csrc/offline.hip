@@ -510,7 +510,7 @@ __global__ __launch_bounds__(NT) void k_normalize(BuildBatch bb, int j) {
   wg_symmetrize(b, gram, b);
   const double ratio = wg_potrf(b, gram, b);          // gram <- L (lower)
   if (!(ratio > 1e-10)) {
-    if (threadIdx.x == 0) c.status = (ratio < 0.0 && j == 0) ? ST_BREAKDOWN : ST_BREAKDOWN;
+    if (threadIdx.x == 0) { c.status = ST_BREAKDOWN; c.fail_block = j + 1; }
     return;
   }
   // R_j = L^T (upper), kept for beta_1 = R_1
@@ -534,7 +534,7 @@ __global__ __launch_bounds__(NT) void k_ts_chol(BuildBatch bb, int j) {
   double* gram = bb.d_work + c.s_off;
   const double ratio = wg_potrf(b, gram, b);          // gram <- L (lower)
   if (!(ratio > 1e-10)) {
-    if (threadIdx.x == 0) c.status = ST_BREAKDOWN;
+    if (threadIdx.x == 0) { c.status = ST_BREAKDOWN; c.fail_block = j + 1; }
     return;
   }
   double* R = bb.d_work + c.r_off + (int64_t)j * b * b;
@@ -904,12 +904,12 @@ __global__ __launch_bounds__(NT, 3) void k_lanczos(BuildBatch bb) {
     wg_gemm<true, false>(b, b, mb, 1.0, Z, mb, Z, mb, 0.0, gram, b);
     wg_symmetrize(b, gram, b);
     double ratio = wg_potrf(b, gram, b);
-    if (!(ratio > 1e-10)) { if (threadIdx.x == 0) c.status = ST_BREAKDOWN; return; }
+    if (!(ratio > 1e-10)) { if (threadIdx.x == 0) { c.status = ST_BREAKDOWN; c.fail_block = k + 2; } return; }
     wg_trsm_right_lt(mb, b, gram, b, Z, mb);
     wg_gemm<true, false>(b, b, mb, 1.0, Z, mb, Z, mb, 0.0, gram2, b);
     wg_symmetrize(b, gram2, b);
     ratio = wg_potrf(b, gram2, b);
-    if (!(ratio > 1e-6)) { if (threadIdx.x == 0) c.status = ST_BREAKDOWN; return; }
+    if (!(ratio > 1e-6)) { if (threadIdx.x == 0) { c.status = ST_BREAKDOWN; c.fail_block = k + 2; } return; }
     wg_trsm_right_lt(mb, b, gram2, b, Z, mb);
     // beta = L2^T L1^T (upper)
     for (int idx = threadIdx.x; idx < b * b; idx += NT) {

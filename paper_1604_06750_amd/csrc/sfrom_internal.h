@@ -68,7 +68,7 @@ struct BuildCell {
   int64_t r_off;    // R_j factors: m b^2 (R_1 = beta_1)
   int64_t out_off;  // S-fraction output: 2 m b^2 (Ghat^1..m then G^1..m)
   int32_t status;   // per-cell status (written by kernels)
-  int32_t pad;
+  int32_t fail_block; // on a rank loss: the 1-based Krylov / Lanczos block that lost rank
   int64_t p_off;    // blocked build only: partial Gram products, ceil(n / TS_ROWS) x max((m b)^2, m b^2)
   int64_t li_off;   // blocked build only: inverse of each 64 x 64 diagonal factor block, ceil(n / 64) x 64^2
 };
@@ -327,6 +327,11 @@ struct sfrom {
   // pencil and the global ROM an assembly of the cells' ROMs, so the bound
   // also bounds the ROM's largest eigenvalue (used by the CFL check).
   double lam_cells = -1.0;
+
+  // a cell whose rational Krylov or Lanczos block k (>= 2) loses rank is
+  // rebuilt with m_i = k - 1 instead of failing the build
+  bool reduce_m_on_breakdown = false;
+  std::vector<std::pair<int32_t, int32_t>> breakdowns;   // (cell, failing block) of the last failed batch
 
   // ROM
   bool built = false;

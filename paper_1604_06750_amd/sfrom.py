@@ -65,6 +65,7 @@ _SIGS = {
     "sfrom_setup_voxel_acoustic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
     "sfrom_setup_voxel_elastic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
     "sfrom_partition_graph": [_P, C.c_int32, C.c_double, C.c_double],
+    "sfrom_set_breakdown_policy": [_P, C.c_int32],
     "sfrom_gramian_bases": [_P, C.c_double, C.c_double, C.c_int32, C.c_int32],
     "sfrom_build": [_P, C.POINTER(sfrom_build_opts)],
     "sfrom_import_rom": [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P],
@@ -207,6 +208,10 @@ def sfrom_setup_voxel_elastic(h, c21, rho, cuts, modes_face, modes_edge):
 
 def sfrom_partition_graph(h, n_cells, alpha=0.5, beta=0.5):
     _check(h, _lib.sfrom_partition_graph(h, int(n_cells), float(alpha), float(beta)))
+
+
+def sfrom_set_breakdown_policy(h, reduce_m):
+    _check(h, _lib.sfrom_set_breakdown_policy(h, int(bool(reduce_m))))
 
 
 def sfrom_gramian_bases(h, omega_max, eps, max_modes, depth):

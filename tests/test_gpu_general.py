@@ -99,7 +99,7 @@ def _node_tf(nodes_by_piece, bases, cell_pieces, Ghat, G, s):
     return (W @ F @ W.T)[np.ix_(o, o)]
 
 
-def _gpu(c, prec, with_blocks=False):
+def _gpu(c, prec, with_blocks=False, adapt=False):
     S = _lib()
     h = S.sfrom_create(0, torch.cuda.current_stream().cuda_stream)
     try:
@@ -110,7 +110,11 @@ def _gpu(c, prec, with_blocks=False):
         S.sfrom_set_sources(h, cp, rw, vl, project=False)
         cp, rw, vl = S.sfrom_point_columns(h, c.rec, c.kmax)
         S.sfrom_set_receivers(h, cp, rw, vl, project=False)
-        S.sfrom_build(h, c.m, c.shift, prec, m_per_cell=np.array(c.m_cell, np.int32))
+        if adapt:
+            S.sfrom_set_breakdown_policy(h, 1)
+            S.sfrom_build(h, c.m, c.shift, prec)
+        else:
+            S.sfrom_build(h, c.m, c.shift, prec, m_per_cell=np.array(c.m_cell, np.int32))
         tr = np.zeros((len(c.w), len(c.rec), len(c.src)), np.float64 if prec == S.SFROM_F64 else np.float32)
         S.sfrom_run(h, len(c.w), c.dt, c.w, tr)
         if not with_blocks:
@@ -162,3 +166,34 @@ def test_general_unstructured_graph(dev):
     c = _oracle(A, b, 6, omega_max=0.45, eps=1e-6, max_modes=5, depth=-1, m=3, n_src=3, n_rec=10, n_steps=300,
                 seed=6)
     _check(c, "unstructured graph")
+
+
+def test_general_graph_breakdown_policy(dev):
+    """The same unstructured graph built with m = 3 everywhere: without the
+    policy the build fails with EBREAKDOWN naming a cell and its block; with
+    sfrom_set_breakdown_policy(h, 1) the library lowers m_i itself to the
+    values the oracle finds (block k lost rank -> m_i = k - 1), and the
+    traces equal the oracle's (1e-9)."""
+    S = _lib()
+    A, b, _ = synth.geometric_graph(3000, 6, 7)
+    c = _oracle(A, b, 6, omega_max=0.45, eps=1e-6, max_modes=5, depth=-1, m=3, n_src=3, n_rec=10, n_steps=300,
+                seed=6)
+    assert min(c.m_cell) < 3
+    h = S.sfrom_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        S.sfrom_set_pencil(h, c.A.indptr.astype(np.int64), c.A.indices.astype(np.int32), c.A.data, c.b)
+        S.sfrom_partition_graph(h, c.n_cells)
+        S.sfrom_gramian_bases(h, c.omega_max, c.eps, c.max_modes, c.depth)
+        with pytest.raises(S.SfromError) as e:
+            S.sfrom_build(h, c.m, c.shift, S.SFROM_F64)
+        assert e.value.name == "EBREAKDOWN" and "block" in S.sfrom_last_error(h)
+        S.sfrom_set_breakdown_policy(h, 1)
+        S.sfrom_build(h, c.m, c.shift, S.SFROM_F64)
+        got = [len(S.sfrom_export_rom(h, i)[0]) for i in range(c.n_cells)]
+    finally:
+        S.sfrom_destroy(h)
+    assert got == c.m_cell, (got, c.m_cell)
+    tr, _ = _gpu(c, S.SFROM_F64, adapt=True)
+    e = float(np.linalg.norm(tr - c.ref) / np.linalg.norm(c.ref))
+    print(f"breakdown policy: m_i {got}, FP64 traces {e:.2e}")
+    assert e <= 1e-9
