@@ -125,6 +125,26 @@ def cpu_baseline(args, ns_target, nsteps_target, ncells_target, budget_s):
         nsteps *= 2
     job = t_build / ncell * ncells_target + t_step / ncell * ncells_target * nsteps_target
     cores = len(os.sched_getaffinity(0))
+    # the oracle's fine-grid leapfrog on the same sub-block and sources,
+    # scaled by the node count to the full grid
+    from oracle import fine as ofine
+    fsteps = 8
+    t0 = time.perf_counter()
+    ofine.leapfrog(run.A, run.b, run.G_src, run.Q_rec, np.resize(run.w, fsteps), run.dt)
+    t_fine = (time.perf_counter() - t0) / fsteps
+    n_full = int(np.prod([v - 1 for v in big.nvox]))
+    fine_rate = ns_target / (t_fine * n_full / run.A.shape[0])
+    # the ROM leapfrog on one thread (BLAS limited to one thread)
+    rom1 = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            rom.leapfrog(F, Qr, np.resize(run.w, 4), run.dt)
+            t1 = (time.perf_counter() - t0) / 4
+        rom1 = ns_target / (t1 / ncell * ncells_target)
+    except ImportError:
+        pass
     return {
         "value": ns_target * nsteps_target / job,
         "unit": "source-steps/s",
@@ -137,6 +157,10 @@ def cpu_baseline(args, ns_target, nsteps_target, ncells_target, budget_s):
                    f"products single-threaded"),
         "build_s_per_cell": t_build / ncell,
         "online_s_per_cell_step": t_step / ncell,
+        "oracle_fine_source_steps_per_s": fine_rate,
+        "oracle_fine_sample": (f"{fsteps} FP64 fine-grid leapfrog steps on the same sub-block and sources "
+                               f"({t_fine * 1e3:.0f} ms/step), scaled by the node count to the full grid"),
+        "oracle_rom_online_source_steps_per_s_one_thread": rom1,
     }
 
 
