@@ -370,3 +370,25 @@ def test_local_pencil_slab_is_a_prop2_split():
     AUd = AU.toarray()
     keep = np.searchsorted(U, nodes)
     assert np.abs(Ad[loc] - AUd[np.ix_(locU, keep)]).max() <= 1e-14 * np.abs(AUd).max()
+
+
+def test_alg1_needs_diagonal_dominance():
+    """Prop. 2's hypothesis matters: the Q1 elastic operator is not
+    diagonally dominant, and Alg. 2 / Alg. 1 applied to it gives split
+    operators with positive eigenvalues (so the general partition is not
+    used for it; its cells are split voxel by voxel instead), while the
+    diagonally dominant acoustic operator of the same grid stays A_i <= 0."""
+    from oracle import elastic
+    rng = np.random.default_rng(3)
+    nvox = (6, 6, 6)
+    Cv = np.empty(nvox + (6, 6))
+    Cv[...] = elastic.vti_stiffness(2.0, 1.0, 0.1, 0.05)
+    rho = 1.0 + rng.random(nvox)
+    A, b = elastic.assemble_elastic(Cv, rho)
+    subs = dc.alg2_partition(A, b, 4)
+    _check_split(A, b, subs)
+    worst = max(np.linalg.eigvalsh(s.A.toarray()).max() / abs(s.A).max() for s in subs)
+    assert worst > 1e-3
+    Aa, ba = fine.assemble_acoustic(1.0 + rng.random(nvox), rho)
+    for s in dc.alg2_partition(Aa, ba, 4):
+        assert np.linalg.eigvalsh(s.A.toarray()).max() <= 1e-12 * abs(s.A).max()
