@@ -360,8 +360,8 @@ def elastic_block(S, problem, synth, stream, dev, ref_steps=1000, fine_steps=300
 def layered_block(S, problem, synth, stream, dev, ref_steps=600, fine_steps=200):
     """The uneven-cell case: 256 x 256 x 128 voxels with six layers (contrast
     3:1, +-10% smooth perturbation), cells of 8..16 voxels aligned to the
-    layers with m_i = 3..8 by cell size, 4 face + 2 edge + 1 corner modes,
-    256 sources, 6000 steps. One warm-up and one timed job for the BF16
+    layers with m_i = 3..8 by cell size, 4/6/8 face modes by face area,
+    2 edge + 1 corner modes, 256 sources, 6000 steps. One warm-up and one timed job for the BF16
     (FP32 accumulation) and the FP32 on-line blocks; the fine grid's rate
     from ``fine_steps`` FP32 steps; receiver errors against the FP64 fine
     grid over the first ``ref_steps`` steps."""
@@ -424,7 +424,8 @@ def layered_block(S, problem, synth, stream, dev, ref_steps=600, fine_steps=200)
                               "speedup_job_vs_fine": round(res[name]["job_source_steps_per_s"] / fine_ssps, 3)})
         return {"workload": (f"3D layered acoustic, {wl.nvox[0]}x{wl.nvox[1]}x{wl.nvox[2]} voxels, 6 layers, "
                              f"{info['n_cells']} cells of 8..16 voxels, m_i {int(mpc.min())}..{int(mpc.max())}, "
-                             f"4 face + 2 edge + 1 corner modes, {ns} sources, {nr} receivers, {nt} steps"),
+                             f"4/6/8 face modes by face area (<=100, <=169, larger voxels) + 2 edge + 1 corner, "
+                             f"{ns} sources, {nr} receivers, {nt} steps"),
                 "n_fine": info["n"], "max_b": built["max_b"], "error_steps": ref_steps,
                 "fine_source_steps_per_s": round(fine_ssps, 1), **res}
     finally:
@@ -618,6 +619,20 @@ def main():
     torch.cuda.synchronize()
     online_ms = e0.elapsed_time(e1)
     rom_tr = tr.double().cpu().numpy()
+    # the same on-line run replayed from a captured hipGraph (the capture
+    # run first, then one timed replay)
+    S.sfrom_set_graph(h, True)
+    S.sfrom_reset(h)
+    S.sfrom_run(h, nt, dt, w, tr)
+    S.sfrom_reset(h)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    S.sfrom_run(h, nt, dt, w, tr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    online_graph_ms = e0.elapsed_time(e1)
+    graph_same = bool(np.array_equal(tr.double().cpu().numpy(), rom_tr))
+    S.sfrom_set_graph(h, False)
 
     # fine-grid comparator (same dt), timed in the on-line precision
     S.sfrom_fine_reset(h)
@@ -715,6 +730,8 @@ def main():
         "build_ms": round(float(np.mean(build_ms)), 2),
         "online_ms": round(online_ms, 2),
         "online_source_steps_per_s": round(online_ssps, 1),
+        "online_graph_source_steps_per_s": round(ns * nt / (online_graph_ms / 1e3), 1),
+        "graph_replay_bitwise_equal": graph_same,
         "fine_ms": round(fine_ms, 2),
         "fine_source_steps_per_s": round(fine_ssps, 1),
         "speedup_job_vs_fine": round(value / fine_ssps, 3),

@@ -119,6 +119,18 @@ int sfrom_setup_voxel_acoustic(sfrom_t* h, const int32_t nvox[3], const double* 
                                const double* rho, const int32_t ncut[3], const int32_t* cuts,
                                int32_t modes_face, int32_t modes_edge);
 
+/* sfrom_setup_voxel_acoustic with the face-mode count chosen per face from
+ * its area in voxels, (n1 + 1)(n2 + 1) for a face interior of n1 x n2 nodes:
+ * rule k (the first with area <= face_area_max[k]) gives face_modes[k]
+ * modes; a face larger than every bound takes the last rule's count. For
+ * partitions with cells of uneven size (face modes growing with the face).
+ * Errors: as sfrom_setup_voxel_acoustic, EINVAL for rules without positive
+ * counts or increasing bounds. */
+int sfrom_setup_voxel_acoustic_rules(sfrom_t* h, const int32_t nvox[3], const double* sigma,
+                                     const double* rho, const int32_t ncut[3], const int32_t* cuts,
+                                     int32_t n_rules, const int32_t* face_area_max,
+                                     const int32_t* face_modes, int32_t modes_edge);
+
 /* Convenience set-up for an elastic medium (the anisotropic elastic example
  * of Sec. 9, in the form B u'' = A u + w(t) g of Sec. 1): displacements at
  * the corners of unit voxels nvox[0] x nvox[1] x nvox[2], three components

@@ -21,6 +21,8 @@ Readings (the paper leaves these open or states them for 2D only):
   needs a reference that is not part of the paper, so each piece gets the
   lowest separable orthonormal DCT-II modes (the constant mode included):
   face modes ordered by (max(p, q), p, q), edge modes 0, 1, ..., corners [1].
+  Uneven partitions may give each face a count by its area (a rule
+  (n1, n2) -> count).
   S_i is block diagonal over the cell's pieces as in Sec. 4.1.
 """
 from __future__ import annotations
@@ -86,7 +88,9 @@ class Cell:
 class CartesianPartition:
     """Coarse-cell partition of a voxel grid with interior cut planes."""
 
-    def __init__(self, nvox, cuts, modes_face: int, modes_edge: int):
+    def __init__(self, nvox, cuts, modes_face, modes_edge: int):
+        """``modes_face`` is a count, or a function (n1, n2) -> count of the
+        face interior's node extents (face modes by face area)."""
         self.nvox = tuple(int(v) for v in nvox)
         self.cuts = [np.asarray(c, dtype=np.int64) for c in cuts]
         self.modes_face = modes_face
@@ -189,7 +193,8 @@ class CartesianPartition:
                 else:
                     per_axis.append([key[a] // 2])
             cells = sorted(self.cell_id(a, b, c) for c in per_axis[2] for b in per_axis[1] for a in per_axis[0])
-            S = piece_basis(dims, kind, self.modes_face, self.modes_edge)
+            mf = self.modes_face(*dims) if (kind == 1 and callable(self.modes_face)) else self.modes_face
+            S = piece_basis(dims, kind, mf, self.modes_edge)
             self.pieces.append(Piece(key, kind, members, dims, cells, S))
             for c in cells:
                 self.cells[c].pieces.append(p)

@@ -34,7 +34,14 @@ class OracleRun:
 def setup(wl, dt=None, n_steps=None):
     """Fine pencil, partition, projected point sources/receivers, dt, wavelet."""
     A, b = fine.assemble_acoustic(wl.sigma, wl.rho)
-    part = CartesianPartition(wl.nvox, wl.cuts, wl.modes_face, wl.modes_edge)
+    rules = getattr(wl, "extra", {}).get("face_rules")
+    if rules is None:
+        mf = wl.modes_face
+    else:
+        def mf(n1, n2):
+            area = (n1 + 1) * (n2 + 1)
+            return next((mo for am, mo in zip(*rules) if area <= am), rules[1][-1])
+    part = CartesianPartition(wl.nvox, wl.cuts, mf, wl.modes_edge)
     if dt is None:
         dt = fine.cfl_dt(A, b, wl.cfl_fraction)
     w = synth.ricker(n_steps or wl.n_steps, dt, wl.f_p)

@@ -126,13 +126,66 @@ std::vector<double> dct_vec(int n, int k) {
   return v;
 }
 
+// Face-mode count of a face interior of n1 x n2 nodes: the first rule whose
+// area bound (in voxels, (n1 + 1)(n2 + 1)) it meets, else the fixed count.
+struct FaceModes {
+  int32_t fixed = 0;
+  int32_t n_rules = 0;
+  const int32_t* area_max = nullptr;
+  const int32_t* modes = nullptr;
+  int operator()(int n1, int n2) const {
+    if (n_rules == 0) return fixed;
+    const int64_t area = (int64_t)(n1 + 1) * (n2 + 1);
+    for (int k = 0; k < n_rules; ++k)
+      if (area <= area_max[k]) return modes[k];
+    return modes[n_rules - 1];
+  }
+};
+
+int setup_acoustic(sfrom_t* h, const int32_t nvox[3], const double* sigma, const double* rho,
+                   const int32_t ncut[3], const int32_t* cuts, const FaceModes& face_modes, int32_t modes_edge);
+
 }  // namespace
 
 extern "C" int sfrom_setup_voxel_acoustic(sfrom_t* h, const int32_t nvox[3], const double* sigma,
                                           const double* rho, const int32_t ncut[3], const int32_t* cuts,
                                           int32_t modes_face, int32_t modes_edge) {
   if (!h) return SFROM_EINVAL;
-  if (!nvox || !sigma || !rho || !ncut || (!cuts && ncut[0] + ncut[1] + ncut[2] > 0) || modes_face < 1 || modes_edge < 1) {
+  if (modes_face < 1) {
+    h->err = "bad voxel set-up arguments";
+    return SFROM_EINVAL;
+  }
+  FaceModes fm;
+  fm.fixed = modes_face;
+  return setup_acoustic(h, nvox, sigma, rho, ncut, cuts, fm, modes_edge);
+}
+
+extern "C" int sfrom_setup_voxel_acoustic_rules(sfrom_t* h, const int32_t nvox[3], const double* sigma,
+                                                const double* rho, const int32_t ncut[3], const int32_t* cuts,
+                                                int32_t n_rules, const int32_t* face_area_max,
+                                                const int32_t* face_modes, int32_t modes_edge) {
+  if (!h) return SFROM_EINVAL;
+  if (n_rules < 1 || !face_area_max || !face_modes) {
+    h->err = "bad face-mode rules";
+    return SFROM_EINVAL;
+  }
+  for (int k = 0; k < n_rules; ++k)
+    if (face_modes[k] < 1 || (k > 0 && face_area_max[k] <= face_area_max[k - 1])) {
+      h->err = "face-mode rules need counts >= 1 and increasing area bounds";
+      return SFROM_EINVAL;
+    }
+  FaceModes fm;
+  fm.n_rules = n_rules;
+  fm.area_max = face_area_max;
+  fm.modes = face_modes;
+  return setup_acoustic(h, nvox, sigma, rho, ncut, cuts, fm, modes_edge);
+}
+
+namespace {
+
+int setup_acoustic(sfrom_t* h, const int32_t nvox[3], const double* sigma, const double* rho,
+                   const int32_t ncut[3], const int32_t* cuts, const FaceModes& face_modes, int32_t modes_edge) {
+  if (!nvox || !sigma || !rho || !ncut || (!cuts && ncut[0] + ncut[1] + ncut[2] > 0) || modes_edge < 1) {
     h->err = "bad voxel set-up arguments";
     return SFROM_EINVAL;
   }
@@ -295,7 +348,7 @@ extern "C" int sfrom_setup_voxel_acoustic(sfrom_t* h, const int32_t nvox[3], con
         if (u[0] != v[0]) return u[0] < v[0];
         return u[1] < v[1];
       });
-      bp = std::min<int>(modes_face, (int)pairs.size());
+      bp = std::min<int>(face_modes(n1, n2), (int)pairs.size());
       for (int k = 0; k < bp; ++k) {
         const auto v1 = dct_vec(n1, pairs[k][0]);
         const auto v2 = dct_vec(n2, pairs[k][1]);
@@ -309,3 +362,5 @@ extern "C" int sfrom_setup_voxel_acoustic(sfrom_t* h, const int32_t nvox[3], con
   h->err.clear();
   return SFROM_OK;
 }
+
+}  // namespace

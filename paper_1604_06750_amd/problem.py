@@ -33,7 +33,11 @@ def setup(h, wl, sources=True, receivers=True, gramian=None):
     ``gramian`` = (omega, eps, max_modes, depth) replaces the DCT piece bases
     by frequency-limited Gramian bases (sfrom_gramian_bases) before the
     columns are set."""
-    S.sfrom_setup_voxel_acoustic(h, wl.sigma, wl.rho, wl.cuts, wl.modes_face, wl.modes_edge)
+    rules = getattr(wl, "extra", {}).get("face_rules")
+    if rules is not None:
+        S.sfrom_setup_voxel_acoustic_rules(h, wl.sigma, wl.rho, wl.cuts, rules[0], rules[1], wl.modes_edge)
+    else:
+        S.sfrom_setup_voxel_acoustic(h, wl.sigma, wl.rho, wl.cuts, wl.modes_face, wl.modes_edge)
     if gramian is not None:
         S.sfrom_gramian_bases(h, *gramian)
     mp = max_piece_nodes(wl)

@@ -64,6 +64,7 @@ _SIGS = {
     "sfrom_add_piece": [_P, C.c_int32, C.c_int32, _P, C.c_int32, _P],
     "sfrom_setup_voxel_acoustic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
     "sfrom_setup_voxel_elastic": [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
+    "sfrom_setup_voxel_acoustic_rules": [_P, _P, _P, _P, _P, _P, C.c_int32, _P, _P, C.c_int32],
     "sfrom_partition_graph": [_P, C.c_int32, C.c_double, C.c_double],
     "sfrom_set_breakdown_policy": [_P, C.c_int32],
     "sfrom_gramian_bases": [_P, C.c_double, C.c_double, C.c_int32, C.c_int32],
@@ -191,6 +192,20 @@ def sfrom_setup_voxel_acoustic(h, sigma, rho, cuts, modes_face, modes_edge):
     cc = np.concatenate([np.asarray(c, dtype=np.int32) for c in cuts]) if ncut.sum() else np.zeros(1, np.int32)
     _check(h, _lib.sfrom_setup_voxel_acoustic(h, _ptr(nvox), _ptr(s), _ptr(r), _ptr(ncut), _ptr(cc),
                                               modes_face, modes_edge))
+
+
+def sfrom_setup_voxel_acoustic_rules(h, sigma, rho, cuts, face_area_max, face_modes, modes_edge):
+    """As sfrom_setup_voxel_acoustic with face-mode counts by face area."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    nvox = np.array(sigma.shape, dtype=np.int32)
+    s = np.ascontiguousarray(sigma.transpose(2, 1, 0)).ravel()
+    r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64).transpose(2, 1, 0)).ravel()
+    ncut = np.array([len(c) for c in cuts], dtype=np.int32)
+    cc = np.concatenate([np.asarray(c, dtype=np.int32) for c in cuts]) if ncut.sum() else np.zeros(1, np.int32)
+    am = np.ascontiguousarray(face_area_max, dtype=np.int32)
+    fm = np.ascontiguousarray(face_modes, dtype=np.int32)
+    _check(h, _lib.sfrom_setup_voxel_acoustic_rules(h, _ptr(nvox), _ptr(s), _ptr(r), _ptr(ncut), _ptr(cc),
+                                                    len(am), _ptr(am), _ptr(fm), modes_edge))
 
 
 def sfrom_setup_voxel_elastic(h, c21, rho, cuts, modes_face, modes_edge):

@@ -227,7 +227,8 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
     ``layered``: 256x256x128 voxels, 6 layers of contrast 3:1 with a +-10%
                  smooth perturbation, non-uniform cells of 8..16 voxels aligned
                  to the layers, per-cell layer count 3..8 from the cell size
-                 (``extra['m_per_cell']``), 256 sources, 6000 steps
+                 (``extra['m_per_cell']``), face modes 4/6/8 by face area
+                 (``extra['face_rules']``), 256 sources, 6000 steps
     ``layered_small``: the same recipe on 64x64x32 voxels (parity case)
     ``paper``  : ``ncell``^3 (default 4^3) cubic cells of ``cell`` voxels
                  (default 40) at ``ppw`` points per wavelength (default: one
@@ -367,6 +368,9 @@ def workload(name: str, *, modes_face: Optional[int] = None, modes_edge: Optiona
                     v13 = (ex * ey * ez) ** (1.0 / 3.0)
                     mpc.append(int(np.clip(round(3 + 5 * (v13 - 8) / 8), 3, 8)))
         wl.extra["m_per_cell"] = np.array(mpc, dtype=np.int32)
+        if name == "layered":
+            # face modes by face area in voxels: <= 100 -> 4, <= 169 -> 6, else 8
+            wl.extra["face_rules"] = ([100, 169, 2 ** 31 - 1], [4, 6, 8])
         return wl
     if name in ("elastic", "elastic_tiny"):
         # layered VTI elastic medium (three piecewise-constant phases, shear

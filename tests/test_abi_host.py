@@ -252,3 +252,34 @@ def test_checkpoint_calls_need_a_device(host, tmp_path):
         with pytest.raises(S.SfromError) as e:
             f(h, str(tmp_path / "x.ckp"))
         assert e.value.name == "EDEVICE"
+
+
+def test_face_modes_by_area_match_oracle(host):
+    """Uneven cells with face-mode counts by face area (voxel areas <= 20 ->
+    1 mode, <= 40 -> 3, else 5): every piece's basis equals the oracle's
+    DCT modes for the count its face's area selects."""
+    S, h = host
+    rng = np.random.default_rng(8)
+    nvox = (13, 12, 9)
+    sigma = rng.uniform(1, 4, nvox); rho = rng.uniform(1, 2, nvox)
+    cuts = (np.array([4, 10]), np.array([5]), np.array([4]))
+    area_max, modes = [20, 40, 10 ** 6], [1, 3, 5]
+
+    def rule(n1, n2):
+        area = (n1 + 1) * (n2 + 1)
+        return next(mo for am, mo in zip(area_max, modes) if area <= am)
+
+    S.sfrom_setup_voxel_acoustic_rules(h, sigma, rho, cuts, area_max, modes, 2)
+    part = CartesianPartition(nvox, cuts, rule, 2)
+    info = S.sfrom_get_info(h)
+    assert info["n_pieces"] == len(part.pieces)
+    counts = set()
+    for p, pc in enumerate(part.pieces):
+        g, Sp = S.sfrom_export_piece(h, p)
+        assert np.array_equal(g, pc.nodes)
+        assert Sp.shape == pc.S.shape and np.abs(Sp - pc.S).max() <= 1e-14
+        if pc.kind == 1:
+            counts.add(pc.S.shape[1])
+    assert counts == {1, 3, 5}
+    with pytest.raises(S.SfromError):
+        S.sfrom_setup_voxel_acoustic_rules(h, sigma, rho, cuts, [40, 20], [1, 3], 2)
