@@ -444,6 +444,29 @@ def test_uneven_cells_layered_medium(dev):
     assert e32 <= 1e-4
 
 
+def test_layered_face_modes_by_area(dev):
+    """The uneven-cell workload with face-mode counts by face area (the
+    256x256x128 configuration's rule scaled to the small grid's faces:
+    voxel areas <= 100 -> 2, <= 169 -> 4, else 6 modes) and per-cell m:
+    FP64 traces against the oracle (1e-10), FP32 (1e-4)."""
+    S, P = _lib()
+    wl = synth.workload("layered_small", modes_face=4, modes_edge=2, n_steps=300)
+    wl.extra["face_rules"] = ([100, 169, 2 ** 31 - 1], [2, 4, 6])
+    mpc = wl.extra["m_per_cell"]
+    run = pipeline.setup(wl)
+    part = run.part
+    counts = {pc.S.shape[1] for pc in part.pieces if pc.kind == 1}
+    for i in range(len(part.cells)):
+        Ai, bi = part.cell_operator(i, wl.sigma, wl.rho)
+        run.blocks[i] = build_cell(Ai, bi, part.cell_W(i), wl.shift, int(mpc[i]))
+    ref = pipeline.rom_traces(run)
+    tr64, _, info = _gpu_rom(wl, S.SFROM_F64, run.dt, run.w, m_per_cell=mpc)
+    tr32, _, _ = _gpu_rom(wl, S.SFROM_F32, run.dt, run.w, m_per_cell=mpc)
+    e64, e32 = rel(tr64, ref), rel(tr32, ref)
+    print(f"face modes by area {sorted(counts)}: max b {info['max_b']}, FP64 {e64:.2e}, FP32 {e32:.2e}")
+    assert len(counts) >= 2 and e64 <= 1e-10 and e32 <= 1e-4
+
+
 def test_graph_is_recaptured_after_new_receivers(dev):
     """With graph replay on, replacing the receivers by the same number of
     different columns (here: their order reversed) takes effect at the next
