@@ -254,7 +254,11 @@ class GeneralPartition:
         self.A = sp.csr_matrix(A)
         self.b = np.asarray(b, dtype=float)
         self.n = self.A.shape[0]
-        self.subs = alg2_partition(self.A, self.b, n_cells, alpha, beta, choose_O)
+        self._index(alg2_partition(self.A, self.b, n_cells, alpha, beta, choose_O))
+
+    def _index(self, subs):
+        """Cells, and pieces grouped by owner sets, of the subdomains ``subs``."""
+        self.subs = subs
         self.cells = [GCell(s.nodes) for s in self.subs]
         owners = [[] for _ in range(self.n)]
         for c, s in enumerate(self.subs):
