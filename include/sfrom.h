@@ -184,6 +184,43 @@ int sfrom_partition_graph(sfrom_t* h, int32_t n_cells, double alpha, double beta
  * large), ENONFINITE, ENOMEM. */
 int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int32_t max_modes, int32_t depth);
 
+/* Remove the corner set of the current partition with hanging nodes (App. B,
+ * eq. nocorners; the 2D example of Sec. 3): every node held by three or more
+ * cells is replaced by one hanging node per pair of its cells that share a
+ * node outside the corner set (every pair of its cells if that leaves one
+ * of them out), held by those two cells only. Each cell's entries at the
+ * removed node are shared equally among its copies (link weights to kept
+ * nodes, the row sum on the diagonal, the mass; links between two removed
+ * nodes join copies of the same pair), so that E^T A' E = A and
+ * E^T B' E = B for E the map that copies an old value to its copies, and
+ * A_i' <= 0 where A_i is a graph Laplacian with a non-positive remainder.
+ * (App. B as printed copies each cell's row whole into every copy; that
+ * leaves A' indefinite.) New numbering: old nodes ascending, a kept node
+ * one id, a removed node one per pair, pairs in lexicographic order.
+ * Replaces the pencil (n becomes *n_new), the cells (same ids, local order
+ * kept, copies in place of the removed node) and the pieces (the pair
+ * interfaces, each held by two cells, numbered by smallest node, constant
+ * one-column bases: call sfrom_gramian_bases for richer ones); sources and
+ * receivers are cleared and use the new numbering. Outputs (each may be
+ * NULL): the new node count, the number of removed nodes and of hanging
+ * nodes. A partition without a corner set is left as it is (*n_corner = 0).
+ * Works on any partition (sfrom_partition_graph, sfrom_add_cell /
+ * sfrom_add_piece, the voxel set-ups). Errors: ESTATE (no partition, or the
+ * corner set was already removed), EINVAL (too large), ENOMEM. */
+int sfrom_remove_corner_set(sfrom_t* h, int64_t* n_new, int32_t* n_corner, int64_t* n_hanging);
+
+/* The maps of the last sfrom_remove_corner_set, into caller arrays (each may
+ * be NULL): new_of_old (old node count: the new id of a kept node, -1 for a
+ * removed one), corner (n_corner removed old nodes, ascending), hang_ptr
+ * (n_corner + 1), hang_node (n_hanging new ids: the copies of corner[k] are
+ * hang_node[hang_ptr[k] .. hang_ptr[k+1]), in pair order) and hang_weight
+ * (n_hanging: b'_l / b_k, summing to one per removed node; the value at the
+ * removed node is the weighted sum of its copies, and a point load there is
+ * shared among the copies with the same weights). Errors: ESTATE (no corner
+ * set removed). */
+int sfrom_corner_map(sfrom_t* h, int64_t* new_of_old, int64_t* corner, int64_t* hang_ptr, int64_t* hang_node,
+                     double* hang_weight);
+
 /* ---------------------------------------------------------------------------
  * Off-line stage (Alg. alg1red stage 1)
  * ------------------------------------------------------------------------ */
@@ -220,6 +257,17 @@ int sfrom_build(sfrom_t* h, const sfrom_build_opts* opts);
  * skeleton nodes with complete piece bases, which makes block 2 or 3 lose rank
  * exactly. Errors: EINVAL. */
 int sfrom_set_breakdown_policy(sfrom_t* h, int32_t reduce_m);
+
+/* Correction at the removed corner nodes after every on-line step (App. D,
+ * Remark solcorr), for a partition after sfrom_remove_corner_set: with the
+ * new piece state y^{n+1}, the value at each copy l of a removed node k is
+ * u_l = S_p(l, :) y_p, the node's value is ubar_k = sum_l w_l u_l
+ * (w_l = b'_l / b_k), delta_l = ubar_k - u_l for all copies first, then
+ * y_p += S_p(l, :)^T delta_l for every copy l in piece p. Traces are read
+ * after the correction (by the receivers kernel). enable: 0 (default) or 1.
+ * Takes effect from the next sfrom_run; sfrom_run_noalloc refuses to run
+ * while it is on. Errors: EINVAL, ESTATE (no corner set removed). */
+int sfrom_set_corner_correction(sfrom_t* h, int32_t enable);
 
 /* Replace cell `cell`'s S-fraction by m blocks Ghat^k and G^k (each b x b
  * symmetric, column-major, stored consecutively: Ghat[k*b*b ...]); b must

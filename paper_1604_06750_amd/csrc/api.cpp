@@ -131,6 +131,15 @@ void drop_graph(sfrom_t* h) {
   h->graph_key.clear();
 }
 
+void free_corner_stage(sfrom_t* h) {
+  auto& cs = h->cstage;
+  dfree(cs.d_hptr); dfree(cs.d_hbp); dfree(cs.d_pptr); dfree(cs.d_plist); dfree(cs.d_pbp);
+  dfree(cs.d_hdof); dfree(cs.d_soff); dfree(cs.d_pdof);
+  dfree(cs.d_srow); dfree(cs.d_hw); dfree(cs.d_delta);
+  cs.ready = false;
+  cs.delta_ns = -1;
+}
+
 void free_rom(sfrom_t* h) {
   if (h->device < 0) { h->built = false; return; }
   drop_graph(h);
@@ -143,6 +152,7 @@ void free_rom(sfrom_t* h) {
   dfree(h->d_y[0]); dfree(h->d_y[1]); dfree(h->d_h[0]); dfree(h->d_h[1]); dfree(h->d_phi); dfree(h->d_flag);
   for (auto& bk : h->buckets) dfree(bk.d_list);
   h->buckets.clear();
+  free_corner_stage(h);
   h->built = false;
   h->rom_imported = false;
   h->lam_rom = -1.0;
@@ -929,10 +939,79 @@ void alloc_state(sfrom_t* h, int ns) {
 }
 
 // ROM-side device inputs/outputs and state for n_s sources
+// Device arrays of the App. D correction from the corner map and the built
+// ROM's piece bases: per copy its piece's dof rows and its basis row, per
+// piece holding copies the list of its copies.
+void stage_corners(sfrom_t* h) {
+  auto& cs = h->cstage;
+  const auto& cm = h->cmap;
+  REQUIRE(!cm.corner.empty(), SFROM_ESTATE, "no corner set was removed: call sfrom_remove_corner_set");
+  const int64_t nc = (int64_t)cm.hnode.size();
+  REQUIRE(nc < ((int64_t)1 << 31), SFROM_EINVAL, "too many hanging nodes");
+  std::vector<int32_t> hptr(cm.hptr.begin(), cm.hptr.end()), hbp(nc);
+  std::vector<int64_t> hdof(nc), soff(nc);
+  std::vector<double> srow, hw(nc);
+  std::vector<std::vector<int32_t>> by_piece(h->pieces.size());
+  for (int64_t t = 0; t < nc; ++t) {
+    const int64_t l = cm.hnode[t];
+    REQUIRE(l >= 0 && l < h->n, SFROM_ESTATE, "corner map does not match the pencil");
+    const int32_t p = h->piece_of_node[l];
+    REQUIRE(p >= 0, SFROM_ESTATE, "a hanging node lies in no piece");
+    const sfrom_impl::PieceDef& pd = h->pieces[p];
+    const int64_t kp = (int64_t)pd.gnode.size();
+    const int64_t r = h->pos_in_piece[l];
+    hdof[t] = h->piece_dof_off[p];
+    hbp[t] = pd.b;
+    soff[t] = (int64_t)srow.size();
+    for (int j = 0; j < pd.b; ++j) srow.push_back(pd.S[r + j * kp]);
+    hw[t] = cm.hweight[t];
+    by_piece[p].push_back((int32_t)t);
+  }
+  std::vector<int32_t> pptr{0}, plist, pbp;
+  std::vector<int64_t> pdof;
+  for (size_t p = 0; p < by_piece.size(); ++p) {
+    if (by_piece[p].empty()) continue;
+    for (int32_t t : by_piece[p]) plist.push_back(t);
+    pptr.push_back((int32_t)plist.size());
+    pdof.push_back(h->piece_dof_off[p]);
+    pbp.push_back(h->pieces[p].b);
+  }
+  free_corner_stage(h);
+  cs.ncorner = (int32_t)cm.corner.size();
+  cs.npiece = (int32_t)pdof.size();
+  cs.ncopy = nc;
+  cs.d_hptr = dupload(h, hptr); cs.d_hbp = dupload(h, hbp); cs.d_hdof = dupload(h, hdof);
+  cs.d_soff = dupload(h, soff);
+  cs.d_pptr = dupload(h, pptr); cs.d_plist = dupload(h, plist); cs.d_pdof = dupload(h, pdof);
+  cs.d_pbp = dupload(h, pbp);
+  if (srow.empty()) srow.push_back(0.0);
+  if (h->prec == SFROM_F64) {
+    cs.d_srow = dupload(h, srow);
+    cs.d_hw = dupload(h, hw);
+  } else {
+    std::vector<float> f(srow.begin(), srow.end()), g(hw.begin(), hw.end());
+    cs.d_srow = dupload(h, f);
+    cs.d_hw = dupload(h, g);
+  }
+  cs.ready = true;
+}
+
 void prepare_online(sfrom_t* h) {
   const int ns = h->src.count;
   REQUIRE(ns > 0, SFROM_ESTATE, "no sources: call sfrom_set_sources");
   const size_t eb = prec_bytes(h->prec);
+  if (h->corner_corr) {
+    if (!h->cstage.ready) {
+      drop_graph(h);
+      stage_corners(h);
+    }
+    if (h->cstage.delta_ns != ns) {
+      drop_graph(h);
+      dfree(h->cstage.d_delta);
+      h->cstage.d_delta = dalloc<unsigned char>(h, (size_t)std::max<int64_t>(h->cstage.ncopy, 1) * ns * eb);
+      h->cstage.delta_ns = ns;
+    }
+  }
   if (h->src_dirty) {
     drop_graph(h);   // the captured run reads the source arrays replaced here
     // dense reduced sources for pieces that carry a source
@@ -991,6 +1070,9 @@ void prepare_online(sfrom_t* h) {
       // separate receivers kernel, one thread per receiver, is faster
       h->rec_fused = *std::max_element(pptr.begin(), pptr.end()) <= MAX_FUSED_RECEIVERS;
     }
+    // with the corner correction the traces are read after it, by the
+    // receivers kernel
+    if (h->corner_corr) h->rec_fused = false;
     if (h->rec_fused) {
       const int np = (int)h->pieces.size();
       std::vector<int32_t> pptr(np + 1, 0), plist(h->rec.count);
@@ -1109,6 +1191,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   void* noalloc_base = nullptr;
   if (noalloc) {
     REQUIRE(w_on_device && traces_on_device, SFROM_EINVAL, "sfrom_run_noalloc takes device pointers only");
+    REQUIRE(!h->corner_corr, SFROM_ESTATE, "sfrom_run_noalloc does not apply the corner correction: disable it");
     REQUIRE(!h->masses_dirty && !h->src_dirty && !h->rec_dirty && h->state_ns == h->src.count && h->src.count > 0,
             SFROM_ESTATE,
             "the on-line stage is not prepared for the current ROM, sources and receivers: call sfrom_run once first");
@@ -1183,6 +1266,15 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
     }
     return hipSuccess;
   };
+  CornerArgs ca{};
+  if (h->corner_corr) {
+    const auto& cs = h->cstage;
+    ca.ncorner = cs.ncorner; ca.npiece = cs.npiece; ca.ns = ns; ca.prec = h->prec;
+    ca.hptr = cs.d_hptr; ca.hdof = cs.d_hdof; ca.hbp = cs.d_hbp; ca.soff = cs.d_soff;
+    ca.srow = cs.d_srow; ca.hw = cs.d_hw;
+    ca.pptr = cs.d_pptr; ca.plist = cs.d_plist; ca.pdof = cs.d_pdof; ca.pbp = cs.d_pbp;
+    ca.delta = cs.d_delta;
+  }
   const bool graph = h->use_graph && !h->profiling && n_steps > 0 && !noalloc;
   std::vector<int64_t> key;
   if (graph) {
@@ -1195,6 +1287,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
            (int64_t)(intptr_t)h->d_src, (int64_t)(intptr_t)h->d_rval,
            (int64_t)ns, (int64_t)nr, (int64_t)a.cell_variant, (int64_t)(intptr_t)h->d_blocks};
     for (const StepArgs& ab : ba) key.push_back(ab.cell_variant);
+    key.push_back(h->corner_corr ? (int64_t)(intptr_t)h->cstage.d_delta : 0);
     if (h->graph_exec && key == h->graph_key) {
       HIPCHK(hipGraphLaunch(h->graph_exec, h->stream));
       h->graph_launches++;
@@ -1220,6 +1313,10 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
       const bool sample = profiling && s % h->prof_every == 0;
       timed(h, 0, sample, [&] { return cell_phase(a, ls); });
       timed(h, 1, sample, [&] { return launch_piece_phase(a, ls); });
+      if (h->corner_corr) {
+        ca.y = a.y_old;   // level n + 1
+        HIPCHK(launch_corner_correction(ca, ls));
+      }
       if (!h->rec_fused) timed(h, 2, sample, [&] { return launch_receivers(a, ls); });
       cur = 1 - cur;
       if (profiling && ((s + 1) % 1024) == 0) collect_events(h);
@@ -1884,6 +1981,8 @@ int sfrom_set_pencil(sfrom_t* h, int64_t n, const int64_t* rowptr, const int32_t
   h->grid_u[0] = h->grid_u[1] = h->grid_u[2] = 0;
   h->src = Columns();
   h->rec = Columns();
+  h->cmap = sfrom::CornerMap();
+  h->corner_corr = false;
   API_END(h)
 }
 
@@ -2214,6 +2313,18 @@ int sfrom_set_graph(sfrom_t* h, int32_t enable) {
   REQUIRE(h->device >= 0, SFROM_EDEVICE, "host-only handle");
   h->use_graph = enable != 0;
   if (!h->use_graph && h->graph_exec) { hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; h->graph_key.clear(); }
+  API_END(h)
+}
+
+int sfrom_set_corner_correction(sfrom_t* h, int32_t enable) {
+  API_BEGIN(h)
+  REQUIRE(enable == 0 || enable == 1, SFROM_EINVAL, "enable must be 0 or 1");
+  REQUIRE(!enable || !h->cmap.corner.empty(), SFROM_ESTATE, "no corner set was removed: call sfrom_remove_corner_set");
+  if ((enable != 0) != h->corner_corr) {
+    drop_graph(h);
+    h->corner_corr = enable != 0;
+    h->rec_dirty = true;
+  }
   API_END(h)
 }
 

@@ -735,3 +735,275 @@ extern "C" int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int
     return SFROM_ENOMEM;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Corner-set removal with hanging nodes (App. B; the 2D example of Sec. 3)
+// ---------------------------------------------------------------------------
+//
+// Readings (the paper leaves these open or states them inconsistently):
+// * Corner set: the nodes held by three or more cells.
+// * Pairs of a corner node k: the pairs {i, j} of cells holding k that also
+//   share a node outside the corner set (faces in the Cartesian case; the
+//   four copies of the 2D example); if some cell holding k lies in none of
+//   them, every pair of cells holding k. One hanging node per pair, held by
+//   the pair's two cells only.
+// * Entries: App. B copies each cell's whole row of k into every copy,
+//   which repeats links in the rows of k's neighbours (A' indefinite) and
+//   multiplies the corner mass. Here cell c's entries at k are shared
+//   equally among its n_c(k) copies: a link of weight w to a node l outside
+//   the corner set gives w / n_c(k) per copy; a link between two corner
+//   nodes joins the copies of the same pair, w / |Q| for each of the Q pairs
+//   both have in c (all n_c(k) n_c(l) copy pairs at w / (n_c(k) n_c(l)) if
+//   they share none); the row sum of c's row k goes to each copy's diagonal
+//   as d_k / n_c(k), minus the weights of the copy's links; the mass is
+//   b_c(k) / n_c(k). With E copying each old value to its copies,
+//   E^T A' E = A and E^T B' E = B.
+// * Numbering: old nodes ascending; a kept node gets one new id, a corner
+//   node one per pair (pairs in lexicographic order). Row sums and diagonal
+//   updates run over each cell row in ascending old column order. Each
+//   cell keeps its local order, a corner node's copies in its place.
+// * App. D weights of the copies l of k: b'_l / b_k (they sum to one).
+
+namespace {
+
+struct Copy {
+  int32_t pi, pj;     // the pair (-1, -1 for a kept node)
+  int64_t id;         // new global id
+};
+
+}  // namespace
+
+extern "C" int sfrom_remove_corner_set(sfrom_t* h, int64_t* n_new, int32_t* n_corner, int64_t* n_hanging) {
+  if (!h) return SFROM_EINVAL;
+  try {
+    if (h->n <= 0 || h->cells.empty()) gfail(SFROM_ESTATE, "no partition defined");
+    for (size_t c = 0; c < h->cells.size(); ++c)
+      if (!h->cells[c].defined) gfail(SFROM_ESTATE, "cell " + std::to_string(c) + " is not defined");
+    if (!h->cmap.corner.empty()) gfail(SFROM_ESTATE, "the corner set was already removed");
+    const int64_t n0 = h->n;
+    const int nc = (int)h->cells.size();
+    std::vector<std::vector<int32_t>> owners(n0);
+    for (int c = 0; c < nc; ++c)
+      for (int64_t g : h->cells[c].gnode) owners[g].push_back(c);
+    std::vector<std::pair<int32_t, int32_t>> iface;
+    for (int64_t g = 0; g < n0; ++g)
+      if (owners[g].size() == 2) iface.push_back({owners[g][0], owners[g][1]});
+    std::sort(iface.begin(), iface.end());
+    iface.erase(std::unique(iface.begin(), iface.end()), iface.end());
+    auto is_iface = [&](int32_t i, int32_t j) { return std::binary_search(iface.begin(), iface.end(), std::make_pair(i, j)); };
+    std::vector<int64_t> corner;
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> cpairs;
+    std::vector<int32_t> corner_of(n0, -1);
+    for (int64_t g = 0; g < n0; ++g) {
+      const auto& own = owners[g];
+      if (own.size() < 3) continue;
+      std::vector<std::pair<int32_t, int32_t>> allp, pairs;
+      for (size_t a = 0; a < own.size(); ++a)
+        for (size_t b = a + 1; b < own.size(); ++b) allp.push_back({own[a], own[b]});
+      for (auto& pr : allp)
+        if (is_iface(pr.first, pr.second)) pairs.push_back(pr);
+      bool covered = true;
+      for (int32_t c : own) {
+        bool in = false;
+        for (auto& pr : pairs) in |= pr.first == c || pr.second == c;
+        covered &= in;
+      }
+      corner_of[g] = (int32_t)corner.size();
+      corner.push_back(g);
+      cpairs.push_back(covered ? pairs : allp);
+    }
+    if (n_corner) *n_corner = (int32_t)corner.size();
+    if (corner.empty()) {
+      if (n_new) *n_new = n0;
+      if (n_hanging) *n_hanging = 0;
+      h->err.clear();
+      return SFROM_OK;
+    }
+    std::vector<int64_t> new_of_old(n0, -1), cbase(corner.size());
+    int64_t nid = 0;
+    for (int64_t g = 0; g < n0; ++g) {
+      if (corner_of[g] >= 0) {
+        cbase[corner_of[g]] = nid;
+        nid += (int64_t)cpairs[corner_of[g]].size();
+      } else {
+        new_of_old[g] = nid++;
+      }
+    }
+    const int64_t n1 = nid;
+    if (n1 >= ((int64_t)1 << 31)) gfail(SFROM_EINVAL, "pencil too large after the corner-set removal");
+    auto copies = [&](int32_t c, int64_t g, std::vector<Copy>& out) {
+      out.clear();
+      const int32_t k = corner_of[g];
+      if (k < 0) {
+        out.push_back({-1, -1, new_of_old[g]});
+        return;
+      }
+      const auto& pr = cpairs[k];
+      for (size_t q = 0; q < pr.size(); ++q)
+        if (pr[q].first == c || pr[q].second == c) out.push_back({pr[q].first, pr[q].second, cbase[k] + (int64_t)q});
+    };
+    struct NewCell {
+      std::vector<int64_t> gn;
+      std::vector<int32_t> rp{0}, col;
+      std::vector<double> a, b;
+    };
+    std::vector<NewCell> ncell(nc);
+    std::vector<Copy> cr, cl;
+    for (int c = 0; c < nc; ++c) {
+      const sfrom_impl::CellDef& cd = h->cells[c];
+      NewCell& out = ncell[c];
+      std::vector<std::vector<Copy>> cps(cd.n);
+      std::vector<int32_t> first(cd.n + 1, 0);
+      for (int r = 0; r < cd.n; ++r) {
+        copies(c, cd.gnode[r], cps[r]);
+        first[r + 1] = first[r] + (int32_t)cps[r].size();
+        for (const Copy& x : cps[r]) out.gn.push_back(x.id);
+      }
+      out.b.resize(first[cd.n]);
+      std::vector<std::tuple<int64_t, int32_t, double>> row;
+      std::vector<std::pair<int32_t, double>> nrow;
+      for (int r = 0; r < cd.n; ++r) {
+        const int64_t g = cd.gnode[r];
+        row.clear();
+        for (int t = cd.rowptr[r]; t < cd.rowptr[r + 1]; ++t) row.emplace_back(cd.gnode[cd.col[t]], cd.col[t], cd.a[t]);
+        std::sort(row.begin(), row.end());
+        double d = 0.0;
+        for (auto& e : row) d += std::get<2>(e);
+        const auto& cg = cps[r];
+        const int ng = (int)cg.size();
+        for (int q = 0; q < ng; ++q) {
+          nrow.clear();
+          double diag = d / ng;
+          for (auto& e : row) {
+            const int32_t l = std::get<1>(e);
+            if (l == r) continue;
+            const double w = std::get<2>(e);
+            const auto& cq = cps[l];
+            const int nl = (int)cq.size();
+            const bool kc = corner_of[g] >= 0, lc = corner_of[std::get<0>(e)] >= 0;
+            auto push = [&](int ql, double wt) {
+              nrow.push_back({first[l] + ql, wt});
+              diag -= wt;
+            };
+            if (kc && lc) {
+              int nq = 0, match = -1;
+              for (int a = 0; a < ng; ++a)
+                for (int b = 0; b < nl; ++b)
+                  if (cg[a].pi == cq[b].pi && cg[a].pj == cq[b].pj) {
+                    ++nq;
+                    if (a == q) match = b;
+                  }
+              if (nq > 0) {
+                if (match >= 0) push(match, w / nq);
+              } else {
+                for (int b = 0; b < nl; ++b) push(b, w / (ng * nl));
+              }
+            } else if (kc) {
+              push(0, w / ng);
+            } else if (lc) {
+              for (int b = 0; b < nl; ++b) push(b, w / nl);
+            } else {
+              push(0, w);
+            }
+          }
+          nrow.push_back({first[r] + q, diag});
+          std::sort(nrow.begin(), nrow.end());
+          for (auto& e : nrow) { out.col.push_back(e.first); out.a.push_back(e.second); }
+          out.rp.push_back((int32_t)out.col.size());
+          out.b[first[r] + q] = cd.b[r] / ng;
+        }
+      }
+    }
+    // the pencil: sum of the cells (each new node lies in at most two)
+    std::vector<std::vector<std::pair<int32_t, double>>> grow(n1);
+    std::vector<double> b1(n1, 0.0);
+    for (int c = 0; c < nc; ++c) {
+      const NewCell& x = ncell[c];
+      for (size_t r = 0; r < x.gn.size(); ++r) {
+        b1[x.gn[r]] += x.b[r];
+        for (int t = x.rp[r]; t < x.rp[r + 1]; ++t) grow[x.gn[r]].push_back({(int32_t)x.gn[x.col[t]], x.a[t]});
+      }
+    }
+    std::vector<int64_t> rp1{0};
+    std::vector<int32_t> col1;
+    std::vector<double> a1;
+    for (int64_t g = 0; g < n1; ++g) {
+      auto& rw = grow[g];
+      std::stable_sort(rw.begin(), rw.end(), [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+        return x.first < y.first;
+      });
+      for (size_t t = 0; t < rw.size(); ++t) {
+        if (!col1.empty() && (int64_t)col1.size() > rp1.back() && col1.back() == rw[t].first) a1.back() += rw[t].second;
+        else { col1.push_back(rw[t].first); a1.push_back(rw[t].second); }
+      }
+      rp1.push_back((int64_t)col1.size());
+      std::vector<std::pair<int32_t, double>>().swap(rw);
+    }
+    sfrom::CornerMap cm;
+    cm.n_old = n0;
+    cm.new_of_old = new_of_old;
+    cm.corner = corner;
+    cm.hptr.push_back(0);
+    for (size_t k = 0; k < corner.size(); ++k) {
+      for (size_t q = 0; q < cpairs[k].size(); ++q) {
+        const int64_t l = cbase[k] + (int64_t)q;
+        cm.hnode.push_back(l);
+        cm.hweight.push_back(b1[l] / h->b[corner[k]]);
+      }
+      cm.hptr.push_back((int64_t)cm.hnode.size());
+    }
+    // replace the pencil and the partition; pieces get the normalised
+    // constant vector as a one-column basis until bases are set
+    int rc = sfrom_set_pencil(h, n1, rp1.data(), col1.data(), a1.data(), b1.data());
+    if (rc != SFROM_OK) return rc;
+    std::vector<std::vector<int32_t>> own1(n1);
+    for (int c = 0; c < nc; ++c) {
+      const NewCell& x = ncell[c];
+      rc = sfrom_add_cell(h, c, (int32_t)x.gn.size(), x.gn.data(), x.rp.data(), x.col.data(), x.a.data(), x.b.data());
+      if (rc != SFROM_OK) return rc;
+      for (int64_t g : x.gn) own1[g].push_back(c);
+    }
+    std::map<std::vector<int32_t>, std::vector<int64_t>> groups;
+    for (int64_t g = 0; g < n1; ++g)
+      if (own1[g].size() >= 2) groups[own1[g]].push_back(g);
+    std::vector<const std::vector<int64_t>*> pieces;
+    for (auto& kv : groups) pieces.push_back(&kv.second);
+    std::sort(pieces.begin(), pieces.end(), [](const std::vector<int64_t>* x, const std::vector<int64_t>* y) {
+      return x->front() < y->front();
+    });
+    for (int p = 0; p < (int)pieces.size(); ++p) {
+      const auto& nodes = *pieces[p];
+      std::vector<double> S(nodes.size(), 1.0 / std::sqrt((double)nodes.size()));
+      rc = sfrom_add_piece(h, p, (int32_t)nodes.size(), nodes.data(), 1, S.data());
+      if (rc != SFROM_OK) return rc;
+    }
+    h->cmap = std::move(cm);
+    if (n_new) *n_new = n1;
+    if (n_hanging) *n_hanging = (int64_t)h->cmap.hnode.size();
+    h->err.clear();
+    return SFROM_OK;
+  } catch (const GFail& f) {
+    h->err = f.msg;
+    return f.code;
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return SFROM_ENOMEM;
+  }
+}
+
+extern "C" int sfrom_corner_map(sfrom_t* h, int64_t* new_of_old, int64_t* corner, int64_t* hang_ptr,
+                                int64_t* hang_node, double* hang_weight) {
+  if (!h) return SFROM_EINVAL;
+  const auto& cm = h->cmap;
+  if (cm.corner.empty()) {
+    h->err = "no corner set was removed: call sfrom_remove_corner_set";
+    return SFROM_ESTATE;
+  }
+  h->err.clear();
+  if (new_of_old) std::copy(cm.new_of_old.begin(), cm.new_of_old.end(), new_of_old);
+  if (corner) std::copy(cm.corner.begin(), cm.corner.end(), corner);
+  if (hang_ptr) std::copy(cm.hptr.begin(), cm.hptr.end(), hang_ptr);
+  if (hang_node) std::copy(cm.hnode.begin(), cm.hnode.end(), hang_node);
+  if (hang_weight) std::copy(cm.hweight.begin(), cm.hweight.end(), hang_weight);
+  return SFROM_OK;
+}

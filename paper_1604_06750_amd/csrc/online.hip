@@ -813,6 +813,67 @@ hipError_t launch_receivers(const StepArgs& a, hipStream_t st) {
   return rec_impl<float, float>(a, st);
 }
 
+// Correction at the corner-set nodes (App. D). Kernel 1: one thread per
+// (corner node, source) computes the copies' values from their pieces'
+// coefficients twice (for the weighted mean, then for the differences), so
+// that it needs no per-copy storage beyond delta.
+template <typename T>
+__global__ __launch_bounds__(256) void k_corner_delta(CornerArgs c) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)c.ncorner * c.ns) return;
+  const int k = (int)(gid / c.ns), s = (int)(gid % c.ns);
+  const int ns = c.ns;
+  const T* __restrict__ y = reinterpret_cast<const T*>(c.y);
+  const T* __restrict__ srow = reinterpret_cast<const T*>(c.srow);
+  const T* __restrict__ hw = reinterpret_cast<const T*>(c.hw);
+  T* __restrict__ delta = reinterpret_cast<T*>(c.delta);
+  auto value = [&](int t) {
+    const T* row = srow + c.soff[t];
+    const T* yp = y + c.hdof[t] * ns + s;
+    T u = 0;
+    for (int j = 0; j < c.hbp[t]; ++j) u += row[j] * yp[(int64_t)j * ns];
+    return u;
+  };
+  T ubar = 0;
+  for (int t = c.hptr[k]; t < c.hptr[k + 1]; ++t) ubar += hw[t] * value(t);
+  for (int t = c.hptr[k]; t < c.hptr[k + 1]; ++t) delta[(int64_t)t * ns + s] = ubar - value(t);
+}
+
+// Kernel 2: one thread per (piece holding copies, source); every copy lies in
+// exactly one piece, so each dof row is written by one thread.
+template <typename T>
+__global__ __launch_bounds__(256) void k_corner_apply(CornerArgs c) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)c.npiece * c.ns) return;
+  const int q = (int)(gid / c.ns), s = (int)(gid % c.ns);
+  const int ns = c.ns;
+  T* __restrict__ y = reinterpret_cast<T*>(c.y);
+  const T* __restrict__ srow = reinterpret_cast<const T*>(c.srow);
+  const T* __restrict__ delta = reinterpret_cast<const T*>(c.delta);
+  T* yp = y + c.pdof[q] * ns + s;
+  for (int j = 0; j < c.pbp[q]; ++j) {
+    T acc = 0;
+    for (int e = c.pptr[q]; e < c.pptr[q + 1]; ++e) {
+      const int t = c.plist[e];
+      acc += srow[c.soff[t] + j] * delta[(int64_t)t * ns + s];
+    }
+    yp[(int64_t)j * ns] += acc;
+  }
+}
+
+template <typename T>
+static hipError_t corner_impl(const CornerArgs& c, hipStream_t st) {
+  const int64_t n1 = (int64_t)c.ncorner * c.ns, n2 = (int64_t)c.npiece * c.ns;
+  if (n1 > 0) hipLaunchKernelGGL((k_corner_delta<T>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, c);
+  if (n2 > 0) hipLaunchKernelGGL((k_corner_apply<T>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_corner_correction(const CornerArgs& c, hipStream_t st) {
+  if (c.prec == SFROM_F64) return corner_impl<double>(c, st);
+  return corner_impl<float>(c, st);
+}
+
 // Sets *flag when any of the n state values is NaN or infinite (leap-frog
 // divergence). The flag is written with a vector atomic by one lane per wave.
 template <typename T>

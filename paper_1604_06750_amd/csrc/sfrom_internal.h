@@ -219,6 +219,28 @@ struct StepArgs {
   int32_t nlist;
 };
 hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
+// Correction at the corner-set nodes (App. D) on the piece state y (level
+// n + 1, after the piece phase): for corner node k with hanging copies
+// t = hptr[k] .. hptr[k+1], u_t = S_p(row of t, :) y_p and
+// delta_t = sum_t' w_t' u_t' - u_t (kernel 1); then for each piece q holding
+// copies, y_q += sum over its copies t of S_q(row of t, :)^T delta_t
+// (kernel 2). Values (rows, weights, delta, y) are in the state precision.
+struct CornerArgs {
+  int32_t ncorner, npiece, ns, prec;
+  const int32_t* hptr;    // ncorner + 1
+  const int64_t* hdof;    // per copy: first dof row of its piece
+  const int32_t* hbp;     // per copy: b_p of its piece
+  const int64_t* soff;    // per copy: offset of its basis row in srow
+  const void* srow;       // basis rows, b_p values per copy
+  const void* hw;         // per copy: weight b'_l / b_k
+  const int32_t* pptr;    // npiece + 1: copies of each piece that holds copies
+  const int32_t* plist;   // copy ids, ascending within a piece
+  const int64_t* pdof;    // per such piece: first dof row
+  const int32_t* pbp;     // per such piece: b_p
+  void* delta;            // ncopies x ns
+  void* y;                // piece state, n_piece_dofs x ns
+};
+hipError_t launch_corner_correction(const CornerArgs& c, hipStream_t st);
 // the three parts of a step, for per-kernel timing
 hipError_t launch_cell_phase(const StepArgs& a, hipStream_t st);
 hipError_t launch_piece_phase(const StepArgs& a, hipStream_t st);
@@ -327,6 +349,32 @@ struct sfrom {
   // pencil and the global ROM an assembly of the cells' ROMs, so the bound
   // also bounds the ROM's largest eigenvalue (used by the CFL check).
   double lam_cells = -1.0;
+
+  // Corner-set removal (App. B): for each removed node of the pencil before
+  // the removal (old numbering, ascending) its hanging copies (new
+  // numbering) and their weights b'_l / b_k; old nodes kept map one to one
+  struct CornerMap {
+    int64_t n_old = 0;
+    std::vector<int64_t> new_of_old;   // n_old, -1 at removed nodes
+    std::vector<int64_t> corner;       // removed old nodes, ascending
+    std::vector<int64_t> hptr;         // corner.size() + 1
+    std::vector<int64_t> hnode;        // copies, new numbering
+    std::vector<double> hweight;
+  };
+  CornerMap cmap;
+  // App. D correction after every on-line step, and its device arrays
+  // (staged from the built ROM's piece bases on the first run)
+  bool corner_corr = false;
+  struct CornerStage {
+    bool ready = false;
+    int32_t ncorner = 0, npiece = 0;
+    int64_t ncopy = 0;
+    int32_t *d_hptr = nullptr, *d_hbp = nullptr, *d_pptr = nullptr, *d_plist = nullptr, *d_pbp = nullptr;
+    int64_t *d_hdof = nullptr, *d_soff = nullptr, *d_pdof = nullptr;
+    void *d_srow = nullptr, *d_hw = nullptr, *d_delta = nullptr;
+    int32_t delta_ns = -1;
+  };
+  CornerStage cstage;
 
   // a cell whose rational Krylov or Lanczos block k (>= 2) loses rank is
   // rebuilt with m_i = k - 1 instead of failing the build

@@ -68,6 +68,9 @@ _SIGS = {
     "sfrom_partition_graph": [_P, C.c_int32, C.c_double, C.c_double],
     "sfrom_set_breakdown_policy": [_P, C.c_int32],
     "sfrom_gramian_bases": [_P, C.c_double, C.c_double, C.c_int32, C.c_int32],
+    "sfrom_remove_corner_set": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
+    "sfrom_corner_map": [_P, _P, _P, _P, _P, _P],
+    "sfrom_set_corner_correction": [_P, C.c_int32],
     "sfrom_build": [_P, C.POINTER(sfrom_build_opts)],
     "sfrom_import_rom": [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P],
     "sfrom_export_rom": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P],
@@ -231,6 +234,29 @@ def sfrom_set_breakdown_policy(h, reduce_m):
 
 def sfrom_gramian_bases(h, omega_max, eps, max_modes, depth):
     _check(h, _lib.sfrom_gramian_bases(h, float(omega_max), float(eps), int(max_modes), int(depth)))
+
+
+def sfrom_remove_corner_set(h):
+    """Returns (n_new, n_corner, n_hanging)."""
+    n1 = C.c_int64(); nk = C.c_int32(); nh = C.c_int64()
+    _check(h, _lib.sfrom_remove_corner_set(h, C.byref(n1), C.byref(nk), C.byref(nh)))
+    return n1.value, nk.value, nh.value
+
+
+def sfrom_corner_map(h, n_old, n_corner, n_hanging):
+    """Returns (new_of_old, corner, hang_ptr, hang_node, hang_weight)."""
+    new_of_old = np.empty(n_old, np.int64)
+    corner = np.empty(n_corner, np.int64)
+    ptr = np.empty(n_corner + 1, np.int64)
+    node = np.empty(n_hanging, np.int64)
+    wt = np.empty(n_hanging, np.float64)
+    _check(h, _lib.sfrom_corner_map(h, new_of_old.ctypes.data, corner.ctypes.data, ptr.ctypes.data,
+                                    node.ctypes.data, wt.ctypes.data))
+    return new_of_old, corner, ptr, node, wt
+
+
+def sfrom_set_corner_correction(h, enable):
+    _check(h, _lib.sfrom_set_corner_correction(h, int(enable)))
 
 
 def sfrom_build(h, m, shift, online_prec=SFROM_F32, m_per_cell=None, cells_per_batch=0):
