@@ -134,6 +134,7 @@ void drop_graph(sfrom_t* h) {
 void free_corner_stage(sfrom_t* h) {
   auto& cs = h->cstage;
   dfree(cs.d_hptr); dfree(cs.d_hbp); dfree(cs.d_pptr); dfree(cs.d_plist); dfree(cs.d_pbp);
+  dfree(cs.d_rowq); dfree(cs.d_rowj);
   dfree(cs.d_hdof); dfree(cs.d_soff); dfree(cs.d_pdof);
   dfree(cs.d_srow); dfree(cs.d_hw); dfree(cs.d_delta);
   cs.ready = false;
@@ -967,11 +968,15 @@ void stage_corners(sfrom_t* h) {
     hw[t] = cm.hweight[t];
     by_piece[p].push_back((int32_t)t);
   }
-  std::vector<int32_t> pptr{0}, plist, pbp;
+  std::vector<int32_t> pptr{0}, plist, pbp, rowq, rowj;
   std::vector<int64_t> pdof;
   for (size_t p = 0; p < by_piece.size(); ++p) {
     if (by_piece[p].empty()) continue;
     for (int32_t t : by_piece[p]) plist.push_back(t);
+    for (int j = 0; j < h->pieces[p].b; ++j) {
+      rowq.push_back((int32_t)pdof.size());
+      rowj.push_back(j);
+    }
     pptr.push_back((int32_t)plist.size());
     pdof.push_back(h->piece_dof_off[p]);
     pbp.push_back(h->pieces[p].b);
@@ -979,7 +984,9 @@ void stage_corners(sfrom_t* h) {
   free_corner_stage(h);
   cs.ncorner = (int32_t)cm.corner.size();
   cs.npiece = (int32_t)pdof.size();
+  cs.nrow = (int32_t)rowq.size();
   cs.ncopy = nc;
+  cs.d_rowq = dupload(h, rowq); cs.d_rowj = dupload(h, rowj);
   cs.d_hptr = dupload(h, hptr); cs.d_hbp = dupload(h, hbp); cs.d_hdof = dupload(h, hdof);
   cs.d_soff = dupload(h, soff);
   cs.d_pptr = dupload(h, pptr); cs.d_plist = dupload(h, plist); cs.d_pdof = dupload(h, pdof);
@@ -1269,7 +1276,9 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   CornerArgs ca{};
   if (h->corner_corr) {
     const auto& cs = h->cstage;
-    ca.ncorner = cs.ncorner; ca.npiece = cs.npiece; ca.ns = ns; ca.prec = h->prec;
+    ca.ncorner = cs.ncorner; ca.npiece = cs.npiece; ca.nrow = cs.nrow; ca.ns = ns; ca.prec = h->prec;
+    ca.ncopy = cs.ncopy;
+    ca.rowq = cs.d_rowq; ca.rowj = cs.d_rowj;
     ca.hptr = cs.d_hptr; ca.hdof = cs.d_hdof; ca.hbp = cs.d_hbp; ca.soff = cs.d_soff;
     ca.srow = cs.d_srow; ca.hw = cs.d_hw;
     ca.pptr = cs.d_pptr; ca.plist = cs.d_plist; ca.pdof = cs.d_pdof; ca.pbp = cs.d_pbp;

@@ -813,57 +813,74 @@ hipError_t launch_receivers(const StepArgs& a, hipStream_t st) {
   return rec_impl<float, float>(a, st);
 }
 
-// Correction at the corner-set nodes (App. D). Kernel 1: one thread per
-// (corner node, source) computes the copies' values from their pieces'
-// coefficients twice (for the weighted mean, then for the differences), so
-// that it needs no per-copy storage beyond delta.
+// Correction at the corner-set nodes (App. D), in three short kernels so
+// that no thread walks a long chain of dependent loads. Kernel 1: one thread
+// per (copy, source) writes the copy's value u_t = S_p(row, :) y_p into delta.
+template <typename T>
+__global__ __launch_bounds__(256) void k_corner_value(CornerArgs c) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= c.ncopy * c.ns) return;
+  const int t = (int)(gid / c.ns), s = (int)(gid % c.ns);
+  const int ns = c.ns;
+  const T* __restrict__ row = reinterpret_cast<const T*>(c.srow) + c.soff[t];
+  const T* __restrict__ yp = reinterpret_cast<const T*>(c.y) + c.hdof[t] * ns + s;
+  const int bp = c.hbp[t];
+  T u0 = 0, u1 = 0;
+  int j = 0;
+  for (; j + 1 < bp; j += 2) {
+    u0 += row[j] * yp[(int64_t)j * ns];
+    u1 += row[j + 1] * yp[(int64_t)(j + 1) * ns];
+  }
+  if (j < bp) u0 += row[j] * yp[(int64_t)j * ns];
+  reinterpret_cast<T*>(c.delta)[(int64_t)t * ns + s] = u0 + u1;
+}
+
+// Kernel 2: one thread per (removed node, source) replaces its copies'
+// values by delta_t = sum_t' w_t' u_t' - u_t.
 template <typename T>
 __global__ __launch_bounds__(256) void k_corner_delta(CornerArgs c) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)c.ncorner * c.ns) return;
   const int k = (int)(gid / c.ns), s = (int)(gid % c.ns);
   const int ns = c.ns;
-  const T* __restrict__ y = reinterpret_cast<const T*>(c.y);
-  const T* __restrict__ srow = reinterpret_cast<const T*>(c.srow);
   const T* __restrict__ hw = reinterpret_cast<const T*>(c.hw);
   T* __restrict__ delta = reinterpret_cast<T*>(c.delta);
-  auto value = [&](int t) {
-    const T* row = srow + c.soff[t];
-    const T* yp = y + c.hdof[t] * ns + s;
-    T u = 0;
-    for (int j = 0; j < c.hbp[t]; ++j) u += row[j] * yp[(int64_t)j * ns];
-    return u;
-  };
   T ubar = 0;
-  for (int t = c.hptr[k]; t < c.hptr[k + 1]; ++t) ubar += hw[t] * value(t);
-  for (int t = c.hptr[k]; t < c.hptr[k + 1]; ++t) delta[(int64_t)t * ns + s] = ubar - value(t);
+  for (int t = c.hptr[k]; t < c.hptr[k + 1]; ++t) ubar += hw[t] * delta[(int64_t)t * ns + s];
+  for (int t = c.hptr[k]; t < c.hptr[k + 1]; ++t) delta[(int64_t)t * ns + s] = ubar - delta[(int64_t)t * ns + s];
 }
 
-// Kernel 2: one thread per (piece holding copies, source); every copy lies in
-// exactly one piece, so each dof row is written by one thread.
+// Kernel 3: one thread per (dof row of a piece holding copies, source); every
+// copy lies in exactly one piece, so each dof row is written by one thread.
 template <typename T>
 __global__ __launch_bounds__(256) void k_corner_apply(CornerArgs c) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (int64_t)c.npiece * c.ns) return;
-  const int q = (int)(gid / c.ns), s = (int)(gid % c.ns);
+  if (gid >= (int64_t)c.nrow * c.ns) return;
+  const int r = (int)(gid / c.ns), s = (int)(gid % c.ns);
   const int ns = c.ns;
+  const int q = c.rowq[r], j = c.rowj[r];
   T* __restrict__ y = reinterpret_cast<T*>(c.y);
   const T* __restrict__ srow = reinterpret_cast<const T*>(c.srow);
   const T* __restrict__ delta = reinterpret_cast<const T*>(c.delta);
-  T* yp = y + c.pdof[q] * ns + s;
-  for (int j = 0; j < c.pbp[q]; ++j) {
-    T acc = 0;
-    for (int e = c.pptr[q]; e < c.pptr[q + 1]; ++e) {
-      const int t = c.plist[e];
-      acc += srow[c.soff[t] + j] * delta[(int64_t)t * ns + s];
-    }
-    yp[(int64_t)j * ns] += acc;
+  T a0 = 0, a1 = 0;
+  int e = c.pptr[q];
+  const int e1 = c.pptr[q + 1];
+  for (; e + 1 < e1; e += 2) {
+    const int t0 = c.plist[e], t1 = c.plist[e + 1];
+    a0 += srow[c.soff[t0] + j] * delta[(int64_t)t0 * ns + s];
+    a1 += srow[c.soff[t1] + j] * delta[(int64_t)t1 * ns + s];
   }
+  if (e < e1) {
+    const int t0 = c.plist[e];
+    a0 += srow[c.soff[t0] + j] * delta[(int64_t)t0 * ns + s];
+  }
+  y[(c.pdof[q] + j) * ns + s] += a0 + a1;
 }
 
 template <typename T>
 static hipError_t corner_impl(const CornerArgs& c, hipStream_t st) {
-  const int64_t n1 = (int64_t)c.ncorner * c.ns, n2 = (int64_t)c.npiece * c.ns;
+  const int64_t n0 = c.ncopy * c.ns, n1 = (int64_t)c.ncorner * c.ns, n2 = (int64_t)c.nrow * c.ns;
+  if (n0 > 0) hipLaunchKernelGGL((k_corner_value<T>), dim3((unsigned)((n0 + 255) / 256)), dim3(256), 0, st, c);
   if (n1 > 0) hipLaunchKernelGGL((k_corner_delta<T>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, c);
   if (n2 > 0) hipLaunchKernelGGL((k_corner_apply<T>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, c);
   return hipGetLastError();

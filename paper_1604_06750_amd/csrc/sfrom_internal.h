@@ -222,11 +222,16 @@ hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
 // Correction at the corner-set nodes (App. D) on the piece state y (level
 // n + 1, after the piece phase): for corner node k with hanging copies
 // t = hptr[k] .. hptr[k+1], u_t = S_p(row of t, :) y_p and
-// delta_t = sum_t' w_t' u_t' - u_t (kernel 1); then for each piece q holding
+// delta_t = sum_t' w_t' u_t' - u_t (kernels 1 and 2: values per copy, then
+// means and differences per removed node); then for each piece q holding
 // copies, y_q += sum over its copies t of S_q(row of t, :)^T delta_t
-// (kernel 2). Values (rows, weights, delta, y) are in the state precision.
+// (kernel 3, one thread per dof row of such a piece and source). Values
+// (rows, weights, delta, y) are in the state precision.
 struct CornerArgs {
-  int32_t ncorner, npiece, ns, prec;
+  int32_t ncorner, npiece, nrow, ns, prec;
+  int64_t ncopy;
+  const int32_t* rowq;    // nrow: piece (index into pptr) of each dof row
+  const int32_t* rowj;    // nrow: the row's index j < b_p within its piece
   const int32_t* hptr;    // ncorner + 1
   const int64_t* hdof;    // per copy: first dof row of its piece
   const int32_t* hbp;     // per copy: b_p of its piece
@@ -367,9 +372,10 @@ struct sfrom {
   bool corner_corr = false;
   struct CornerStage {
     bool ready = false;
-    int32_t ncorner = 0, npiece = 0;
+    int32_t ncorner = 0, npiece = 0, nrow = 0;
     int64_t ncopy = 0;
     int32_t *d_hptr = nullptr, *d_hbp = nullptr, *d_pptr = nullptr, *d_plist = nullptr, *d_pbp = nullptr;
+    int32_t *d_rowq = nullptr, *d_rowj = nullptr;
     int64_t *d_hdof = nullptr, *d_soff = nullptr, *d_pdof = nullptr;
     void *d_srow = nullptr, *d_hw = nullptr, *d_delta = nullptr;
     int32_t delta_ns = -1;
