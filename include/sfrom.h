@@ -184,6 +184,25 @@ int sfrom_partition_graph(sfrom_t* h, int32_t n_cells, double alpha, double beta
  * large), ENONFINITE, ENOMEM. */
 int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int32_t max_modes, int32_t depth);
 
+/* As sfrom_gramian_bases, with G taken from the spectral projector of eq.
+ * trgrstep instead of the eigenpairs: Z = B^{-1/2} (I + sign(X)) / 2 B^{-1/2}
+ * with X = (omega_max^2 I - C) / s, C = B^{-1/2} (-A) B^{-1/2} of the local
+ * pencil and s = max(omega_max^2, h - omega_max^2) (h a Gershgorin bound of
+ * C), sign(X) by Zolotarev's best rational approximation of the sign
+ * function on [-1, -delta] U [delta, 1] with n_poles partial fractions and
+ * delta = gamma omega_max^2 / s (eigenvalues within gamma omega_max^2 of
+ * omega_max^2 get weights between 0 and 1), G = R Z R^T on the piece rows.
+ * Each partial fraction is one complex symmetric band solve per piece node
+ * (LDL^T without pivoting in reverse Cuthill-McKee order, valid because
+ * i (X - i beta I) has a positive definite Hermitian part), so the local
+ * pencil has no size limit; eps must exceed the approximant's error (about
+ * 4 exp(-pi^2 n_poles / log(4 / delta))) or spurious modes are kept. The
+ * Jacobi elliptic functions come from the arithmetic-geometric mean.
+ * Errors: as sfrom_gramian_bases, and EINVAL for n_poles outside [1, 64] or
+ * gamma outside (0, 1). */
+int sfrom_gramian_bases_zolotarev(sfrom_t* h, double omega_max, double eps, int32_t max_modes, int32_t depth,
+                                  int32_t n_poles, double gamma);
+
 /* Remove the corner set of the current partition with hanging nodes (App. B,
  * eq. nocorners; the 2D example of Sec. 3): every node held by three or more
  * cells is replaced by one hanging node per pair of its cells that share a

@@ -39,6 +39,7 @@
 #include <atomic>
 #include <cfloat>
 #include <cmath>
+#include <complex>
 #include <deque>
 #include <map>
 #include <numeric>
@@ -504,9 +505,186 @@ Sub union_pencil(const sfrom_t* h, const std::vector<int32_t>& cells) {
   return u;
 }
 
-// S (k_p x b_p column-major) of one piece.
+// ---------------------------------------------------------------------------
+// Zolotarev route to the spectral projector (eq. trgrstep)
+// ---------------------------------------------------------------------------
+
+// K(k) = pi / (2 AGM(1, k')).
+double agm_ellipk(double k) {
+  double a = 1.0, b = std::sqrt(1.0 - k * k);
+  for (int it = 0; it < 64 && std::fabs(a - b) > 1e-16 * a; ++it) {
+    const double an = 0.5 * (a + b);
+    b = std::sqrt(a * b);
+    a = an;
+  }
+  return M_PI / (2.0 * a);
+}
+
+// sn and cn of argument u, modulus k, by the arithmetic-geometric mean
+// (descending Landen transformation).
+void jacobi_sn_cn(double u, double k, double& sn, double& cn) {
+  std::vector<double> a{1.0}, b{std::sqrt(1.0 - k * k)}, c{k};
+  for (int it = 0; it < 64 && std::fabs(c.back()) > 1e-17; ++it) {
+    const double an = 0.5 * (a.back() + b.back());
+    c.push_back(0.5 * (a.back() - b.back()));
+    b.push_back(std::sqrt(a.back() * b.back()));
+    a.push_back(an);
+  }
+  const int N = (int)a.size() - 1;
+  double phi = std::ldexp(a[N] * u, N);
+  for (int n = N; n > 0; --n) phi = 0.5 * (phi + std::asin(c[n] * std::sin(phi) / a[n]));
+  sn = std::sin(phi);
+  cn = std::cos(phi);
+}
+
+// Zolotarev's best rational approximation of sign(x) on [-1, -delta] U
+// [delta, 1] with n partial fractions: Z(x) = M x sum_j a_j / (x^2 + beta2_j),
+// beta2_j = c_{2j-1}, c_i = delta^2 sn^2 / cn^2 (i K' / (2n); k'); M makes
+// the error equioscillate on [delta, 1] (from the extrema on a dense
+// geometric grid).
+void zolotarev_sign(int n, double delta, double& M, std::vector<double>& beta2, std::vector<double>& a) {
+  const double kp = std::sqrt(1.0 - delta * delta);
+  const double Kp = agm_ellipk(kp);
+  std::vector<double> c(2 * n, 0.0);
+  for (int i = 1; i < 2 * n; ++i) {
+    double sn, cn;
+    jacobi_sn_cn(i * Kp / (2 * n), kp, sn, cn);
+    c[i] = delta * delta * sn * sn / (cn * cn);
+  }
+  beta2.assign(n, 0.0);
+  a.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) beta2[j] = c[2 * j + 1];
+  for (int j = 0; j < n; ++j) {
+    double num = 1.0, den = 1.0;
+    for (int i = 1; i < n; ++i) num *= c[2 * i] - beta2[j];
+    for (int i = 0; i < n; ++i)
+      if (i != j) den *= beta2[i] - beta2[j];
+    a[j] = num / den;
+  }
+  const int NG = 20001;
+  double fmax = -1e300, fmin = 1e300;
+  for (int g = 0; g < NG; ++g) {
+    const double x = std::exp(std::log(delta) * (1.0 - (double)g / (NG - 1)));
+    double f = 0.0;
+    for (int j = 0; j < n; ++j) f += a[j] / (x * x + beta2[j]);
+    f *= x;
+    fmax = std::max(fmax, f);
+    fmin = std::min(fmin, f);
+  }
+  M = 2.0 / (fmax + fmin);
+}
+
+// Rows `rows` of Z_w = sum_{lambda <= w^2} z z^T (z B-orthonormal) for the
+// local pencil: Z_w = B^{-1/2} (I + sign(X)) / 2 B^{-1/2}, X = (w^2 I - C) / s,
+// C = B^{-1/2} (-A) B^{-1/2}, sign(X) by Zolotarev's approximant; each term
+// is Im[(X - i beta I)^{-1}] / beta, one complex symmetric band solve
+// (LDL^T without pivoting: i (X - i beta I) has Hermitian part beta I > 0)
+// in reverse Cuthill-McKee order. Returns -G (k_p x k_p) for the basis step.
+std::vector<double> gramian_zolotarev(const Sub& sl, const std::vector<int>& rows, double omega_max, int npole,
+                                      double gamma) {
+  using cd = std::complex<double>;
+  const int n = sl.n(), kp = (int)rows.size();
+  const double w2 = omega_max * omega_max;
+  std::vector<double> r(n);
+  for (int k = 0; k < n; ++k) r[k] = 1.0 / std::sqrt(sl.b[k]);
+  double hi = 0.0;   // Gershgorin bound of C
+  for (int k = 0; k < n; ++k) {
+    double row = 0.0;
+    for (int t = sl.rp[k]; t < sl.rp[k + 1]; ++t) {
+      const double c = -(sl.a[t] * r[k]) * r[sl.col[t]];
+      row += sl.col[t] == k ? c : std::fabs(c);
+    }
+    hi = std::max(hi, row);
+  }
+  const double sc = std::max(w2, hi - w2);
+  const double delta = std::min(gamma * w2 / sc, 0.5);
+  double M;
+  std::vector<double> beta2, coef;
+  zolotarev_sign(npole, delta, M, beta2, coef);
+  // X in reverse Cuthill-McKee order, lower band
+  const std::vector<int> perm = rcm(sl);
+  std::vector<int> inv(n);
+  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
+  int w = 0;
+  for (int k = 0; k < n; ++k)
+    for (int t = sl.rp[k]; t < sl.rp[k + 1]; ++t) w = std::max(w, std::abs(inv[k] - inv[sl.col[t]]));
+  auto xval = [&](int k, int t) {
+    const double c = -(sl.a[t] * r[k]) * r[sl.col[t]];
+    return sl.col[t] == k ? (w2 - c) / sc : -c / sc;
+  };
+  const size_t W1 = (size_t)w + 1;
+  std::vector<double> acc((size_t)n * kp, 0.0);   // sum_j a_j (X^2 + beta_j^2)^{-1} E, permuted rows
+  std::vector<cd> L((size_t)n * W1), y(n);
+  for (int j = 0; j < npole; ++j) {
+    const double beta = std::sqrt(beta2[j]);
+    std::fill(L.begin(), L.end(), cd(0.0, 0.0));
+    for (int k = 0; k < n; ++k)
+      for (int t = sl.rp[k]; t < sl.rp[k + 1]; ++t) {
+        const int i = inv[k], l = inv[sl.col[t]];
+        if (l <= i) L[(size_t)i * W1 + (i - l)] += cd(xval(k, t), 0.0);
+      }
+    for (int i = 0; i < n; ++i) L[(size_t)i * W1] -= cd(0.0, beta);
+    // right-looking band LDL^T: L[i][0] holds d_i, L[i][i-k] the multiplier l_ik
+    std::vector<cd> lk(W1);
+    for (int k = 0; k < n; ++k) {
+      const cd d = L[(size_t)k * W1];
+      const int iend = std::min(n - 1, k + w);
+      for (int i = k + 1; i <= iend; ++i) lk[i - k] = L[(size_t)i * W1 + (i - k)] / d;
+      for (int i = k + 1; i <= iend; ++i) {
+        const cd li = lk[i - k] * d;
+        if (li == cd(0.0, 0.0)) continue;
+        for (int jj = k + 1; jj <= i; ++jj) L[(size_t)i * W1 + (i - jj)] -= li * lk[jj - k];
+      }
+      for (int i = k + 1; i <= iend; ++i) L[(size_t)i * W1 + (i - k)] = lk[i - k];
+    }
+    for (int q = 0; q < kp; ++q) {
+      std::fill(y.begin(), y.end(), cd(0.0, 0.0));
+      const int e = inv[rows[q]];
+      y[e] = cd(r[rows[q]], 0.0);
+      for (int i = e + 1; i < n; ++i) {      // forward: y_i -= sum_k l_ik y_k
+        cd s(0.0, 0.0);
+        for (int k = std::max(e, i - w); k < i; ++k) s += L[(size_t)i * W1 + (i - k)] * y[k];
+        y[i] -= s;
+      }
+      for (int i = 0; i < n; ++i) y[i] /= L[(size_t)i * W1];
+      for (int i = n - 1; i >= 0; --i) {      // back: x_i -= sum_l l_li x_l
+        cd s(0.0, 0.0);
+        const int lend = std::min(n - 1, i + w);
+        for (int l = i + 1; l <= lend; ++l) s += L[(size_t)l * W1 + (l - i)] * y[l];
+        y[i] -= s;
+      }
+      const double f = coef[j] / beta;
+      for (int i = 0; i < n; ++i) acc[(size_t)i * kp + q] += f * y[i].imag();
+    }
+  }
+  // rows of Z_w: r_row / 2 (E + M X acc) at the piece rows
+  std::vector<double> G((size_t)kp * kp, 0.0);
+  for (int q = 0; q < kp; ++q) {
+    const int k = rows[q];
+    std::vector<double> xa(kp, 0.0);
+    for (int t = sl.rp[k]; t < sl.rp[k + 1]; ++t) {
+      const double x = xval(k, t);
+      const double* ar = &acc[(size_t)inv[sl.col[t]] * kp];
+      for (int s2 = 0; s2 < kp; ++s2) xa[s2] += x * ar[s2];
+    }
+    for (int s2 = 0; s2 < kp; ++s2) {
+      const double e = (s2 == q) ? r[k] : 0.0;
+      G[(size_t)q * kp + s2] = r[k] * 0.5 * (e + M * xa[s2]);
+    }
+  }
+  for (int q = 0; q < kp; ++q)
+    for (int s2 = 0; s2 <= q; ++s2) {
+      const double v = 0.5 * (G[(size_t)q * kp + s2] + G[(size_t)s2 * kp + q]);
+      G[(size_t)q * kp + s2] = G[(size_t)s2 * kp + q] = -v;
+    }
+  return G;
+}
+
+// S (k_p x b_p column-major) of one piece; npole > 0 takes G from the
+// Zolotarev projector, else from the eigenpairs of the local pencil.
 std::vector<double> piece_gramian_basis(const sfrom_t* h, int p, const std::vector<int32_t>& cells, double omega_max,
-                                        double eps, int max_modes, int depth, int& bp) {
+                                        double eps, int max_modes, int depth, int& bp, int npole = 0,
+                                        double gamma = 0.0) {
   const auto& pc = h->pieces[p];
   const int kp = (int)pc.gnode.size();
   if (kp == 1) { bp = 1; return {1.0}; }
@@ -528,6 +706,13 @@ std::vector<double> piece_gramian_basis(const sfrom_t* h, int p, const std::vect
     }
   }
   const int n = sl.n();
+  std::vector<int> rows(kp);
+  for (int q = 0; q < kp; ++q)
+    rows[q] = (int)(std::lower_bound(sl.nodes.begin(), sl.nodes.end(), pc.gnode[q]) - sl.nodes.begin());
+  std::vector<double> G;
+  if (npole > 0) {
+    G = gramian_zolotarev(sl, rows, omega_max, npole, gamma);
+  } else {
   if (n > GRAMIAN_MAX_NODES)
     gfail(SFROM_EINVAL, "piece " + std::to_string(p) + ": local pencil of " + std::to_string(n) +
                             " nodes exceeds the dense limit " + std::to_string(GRAMIAN_MAX_NODES) + " (lower depth)");
@@ -543,20 +728,18 @@ std::vector<double> piece_gramian_basis(const sfrom_t* h, int p, const std::vect
   std::vector<double> lam, Y;
   sym_eig_lowest(n, C, -1, omega_max * omega_max, lam, Y);
   const int nr = (int)lam.size();
-  std::vector<int> rows(kp);
-  for (int q = 0; q < kp; ++q)
-    rows[q] = (int)(std::lower_bound(sl.nodes.begin(), sl.nodes.end(), pc.gnode[q]) - sl.nodes.begin());
   std::vector<double> V((size_t)kp * nr);  // restricted B-orthonormal eigenvectors, column-major
   for (int j = 0; j < nr; ++j)
     for (int q = 0; q < kp; ++q) V[q + (size_t)j * kp] = Y[rows[q] + (size_t)j * n] * r[rows[q]];
   // eigenvectors of G = V V^T, largest first
-  std::vector<double> G((size_t)kp * kp, 0.0);
+  G.assign((size_t)kp * kp, 0.0);
   for (int q = 0; q < kp; ++q)
     for (int s = 0; s <= q; ++s) {
       double acc = 0.0;
       for (int j = 0; j < nr; ++j) acc += V[q + (size_t)j * kp] * V[s + (size_t)j * kp];
       G[(size_t)q * kp + s] = G[(size_t)s * kp + q] = -acc;   // lowest of -G = largest of G
     }
+  }
   std::vector<double> mu, U;
   const int want = std::min(kp, std::max(1, max_modes));
   sym_eig_lowest(kp, G, want, 0.0, mu, U);
@@ -673,7 +856,10 @@ extern "C" int sfrom_partition_graph(sfrom_t* h, int32_t n_cells, double alpha, 
   }
 }
 
-extern "C" int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int32_t max_modes, int32_t depth) {
+namespace {
+
+int gramian_bases_impl(sfrom_t* h, double omega_max, double eps, int32_t max_modes, int32_t depth, int32_t npole,
+                       double gamma) {
   if (!h) return SFROM_EINVAL;
   try {
     if (h->n <= 0 || h->cells.empty() || h->pieces.empty()) gfail(SFROM_ESTATE, "no partition defined");
@@ -699,7 +885,8 @@ extern "C" int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int
         const int p = next.fetch_add(1);
         if (p >= np) return;
         try {
-          S[p] = piece_gramian_basis(h, p, node_cells[h->pieces[p].gnode[0]], omega_max, eps, max_modes, depth, bp[p]);
+          S[p] = piece_gramian_basis(h, p, node_cells[h->pieces[p].gnode[0]], omega_max, eps, max_modes, depth, bp[p],
+                                     npole, gamma);
         } catch (const GFail& f) {
           err_code[p] = f.code;
           err_msg[p] = f.msg;
@@ -734,6 +921,22 @@ extern "C" int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int
     h->err = "host allocation failed";
     return SFROM_ENOMEM;
   }
+}
+
+}  // namespace
+
+extern "C" int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int32_t max_modes, int32_t depth) {
+  return gramian_bases_impl(h, omega_max, eps, max_modes, depth, 0, 0.0);
+}
+
+extern "C" int sfrom_gramian_bases_zolotarev(sfrom_t* h, double omega_max, double eps, int32_t max_modes,
+                                             int32_t depth, int32_t n_poles, double gamma) {
+  if (!h) return SFROM_EINVAL;
+  if (n_poles < 1 || n_poles > 64 || !(gamma > 0.0 && gamma < 1.0)) {
+    h->err = "n_poles must lie in [1, 64] and gamma in (0, 1)";
+    return SFROM_EINVAL;
+  }
+  return gramian_bases_impl(h, omega_max, eps, max_modes, depth, n_poles, gamma);
 }
 
 // ---------------------------------------------------------------------------

@@ -68,6 +68,7 @@ _SIGS = {
     "sfrom_partition_graph": [_P, C.c_int32, C.c_double, C.c_double],
     "sfrom_set_breakdown_policy": [_P, C.c_int32],
     "sfrom_gramian_bases": [_P, C.c_double, C.c_double, C.c_int32, C.c_int32],
+    "sfrom_gramian_bases_zolotarev": [_P, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_double],
     "sfrom_remove_corner_set": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
     "sfrom_corner_map": [_P, _P, _P, _P, _P, _P],
     "sfrom_set_corner_correction": [_P, C.c_int32],
@@ -234,6 +235,11 @@ def sfrom_set_breakdown_policy(h, reduce_m):
 
 def sfrom_gramian_bases(h, omega_max, eps, max_modes, depth):
     _check(h, _lib.sfrom_gramian_bases(h, float(omega_max), float(eps), int(max_modes), int(depth)))
+
+
+def sfrom_gramian_bases_zolotarev(h, omega_max, eps, max_modes, depth, n_poles, gamma):
+    _check(h, _lib.sfrom_gramian_bases_zolotarev(h, float(omega_max), float(eps), int(max_modes), int(depth),
+                                                 int(n_poles), float(gamma)))
 
 
 def sfrom_remove_corner_set(h):
