@@ -288,6 +288,20 @@ int sfrom_set_breakdown_policy(sfrom_t* h, int32_t reduce_m);
  * while it is on. Errors: EINVAL, ESTATE (no corner set removed). */
 int sfrom_set_corner_correction(sfrom_t* h, int32_t enable);
 
+/* Persistent on-line stage (Alg. alg1red stage 2 as one kernel): with
+ * enable = 1, sfrom_run executes all its steps in one cooperative launch of
+ * as many workgroups as the device holds at once; each step runs the cell
+ * phase over all (cell, 64-source tile) items, a grid barrier, the piece
+ * phase (eq. bdrytstep) over all (piece, source) items and a grid barrier,
+ * with receivers that read several pieces computed beside the next step's
+ * cell phase. Same arithmetic as the default path (one cell-kernel geometry
+ * for every cell instead of per-bucket autotuned variants). Requires FP32 or
+ * FP64 on-line blocks, b_i <= 144 and b_p <= 16, and no corner correction
+ * (EINVAL / ESTATE at sfrom_run otherwise); not captured in a graph, not
+ * used by sfrom_run_noalloc, no per-kernel profile. Default 0. Errors:
+ * EINVAL. */
+int sfrom_set_persistent(sfrom_t* h, int32_t enable);
+
 /* Replace cell `cell`'s S-fraction by m blocks Ghat^k and G^k (each b x b
  * symmetric, column-major, stored consecutively: Ghat[k*b*b ...]); b must
  * equal the cell's boundary dimension. Requires a built ROM; piece masses

@@ -1241,6 +1241,13 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   a.traces = d_tr;
   a.d_cell_list = nullptr;
   a.nlist = a.ncell;
+  // persistent mode: one cooperative launch for all n_steps steps
+  const bool persist = h->persistent && n_steps > 0 && !noalloc;
+  if (persist) {
+    REQUIRE(persistent_supported(a), SFROM_EINVAL,
+            "the persistent kernel takes FP32 or FP64 on-line blocks, b_i <= 144 and b_p <= 16");
+    REQUIRE(!h->corner_corr, SFROM_ESTATE, "the persistent kernel does not apply the corner correction");
+  }
   // one cell-phase launch per bucket of cells with the same strip count
   // (matrix-core precisions), each with its own autotuned variant
   const bool use_buckets = a.prec != SFROM_F64 && a.max_b <= 256 && h->buckets.size() > 1;
@@ -1284,7 +1291,7 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
     ca.pptr = cs.d_pptr; ca.plist = cs.d_plist; ca.pdof = cs.d_pdof; ca.pbp = cs.d_pbp;
     ca.delta = cs.d_delta;
   }
-  const bool graph = h->use_graph && !h->profiling && n_steps > 0 && !noalloc;
+  const bool graph = h->use_graph && !h->profiling && n_steps > 0 && !noalloc && !persist;
   std::vector<int64_t> key;
   if (graph) {
     double dtv = dt;
@@ -1315,7 +1322,17 @@ void run(sfrom_t* h, int64_t n_steps, double dt, const double* w, int w_on_devic
   {
     const int cur0 = h->cur;
     int cur = cur0;
-    for (int64_t s = 0; s < n_steps; ++s) {
+    if (persist) {
+      PersistArgs pa{};
+      pa.n_steps = n_steps;
+      pa.cur0 = cur0;
+      pa.rec_fused = h->rec_fused ? 1 : 0;
+      pa.y[0] = h->d_y[0]; pa.y[1] = h->d_y[1];
+      pa.h[0] = h->d_h[0]; pa.h[1] = h->d_h[1];
+      HIPCHK(launch_persistent(a, pa, ls));
+      cur = (cur0 + (int)(n_steps & 1)) & 1;
+    }
+    for (int64_t s = 0; s < n_steps && !persist; ++s) {
       a.y_cur = h->d_y[cur]; a.y_old = h->d_y[1 - cur];
       a.h_cur = h->d_h[cur]; a.h_old = h->d_h[1 - cur];
       a.step = s; a.trace_step = s;
@@ -2334,6 +2351,14 @@ int sfrom_set_corner_correction(sfrom_t* h, int32_t enable) {
     h->corner_corr = enable != 0;
     h->rec_dirty = true;
   }
+  API_END(h)
+}
+
+int sfrom_set_persistent(sfrom_t* h, int32_t enable) {
+  API_BEGIN(h)
+  REQUIRE(enable == 0 || enable == 1, SFROM_EINVAL, "enable must be 0 or 1");
+  if ((enable != 0) != h->persistent) drop_graph(h);
+  h->persistent = enable != 0;
   API_END(h)
 }
 

@@ -34,6 +34,7 @@
 // phases goes through the Phi^1 scratch in HBM, summed in a fixed order (no
 // atomics), so results are deterministic.
 
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
@@ -303,21 +304,21 @@ __device__ inline bool last_chunk_of_layer(const StripPos& p, int m, int nch) {
   return p.ch == nch - 1 && (p.t == 2 || (p.t == 1 && p.l == m - 1));
 }
 
-template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, int PM>
-__global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp, int ntile) {
+// One (cell, source tile) work item `bid` of the cell phase, by one
+// workgroup of 64 NCH threads with the layer tiles in `lds_raw`.
+template <int NCH, int CT, int R, bool HO, int TS, bool LEAN, int PM>
+__device__ inline void cell_mfma_body(const StepArgs& a, int kp, int ntile, int bid, unsigned char* lds_raw) {
   using T = typename Prec<PM>::T;
   using TB = typename Prec<PM>::TB;
   using V4 = typename Prec<PM>::V4;
   using ACC = typename Prec<PM>::ACC;
   constexpr int NS = 16 * CT;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
   // Workgroups are dealt to the 8 XCDs round-robin; the source tiles of one
   // cell are placed 8 workgroup ids apart so that they land on the same XCD
   // close in time and share its L2 copy of the cell's blocks.
   int cell, tile;
   {
-    const int bid = blockIdx.x;
     const int grp = bid / (8 * ntile), r = bid % (8 * ntile);
     tile = r / 8;
     cell = grp * 8 + r % 8;
@@ -536,6 +537,12 @@ __global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp
 }
 
 template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, int PM>
+__global__ __launch_bounds__(64 * NCH, MINW) void k_cell_mfma(StepArgs a, int kp, int ntile) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cell_mfma_body<NCH, CT, R, HO, TS, LEAN, PM>(a, kp, ntile, blockIdx.x, lds_raw);
+}
+
+template <int NCH, int CT, int R, bool HO, int TS, int MINW, bool LEAN, int PM>
 static void launch_mfma(const StepArgs& a, hipStream_t st) {
   constexpr int NS = 16 * CT;
   const int kp = 16 * NCH + 4;
@@ -673,15 +680,16 @@ __device__ inline void piece_receivers(const StepArgs& a, int p, int s) {
   }
 }
 
-template <typename T, typename TA, int MAXB, bool UNI>
-__global__ __launch_bounds__(256) void k_piece_phase(StepArgs a) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Work item gid = (piece, source) of the piece phase. With `uni` (n_s a
+// multiple of 64 and 64 consecutive items per wavefront) a wavefront holds one
+// piece, so its descriptor, incidence list and inverse mass are read through
+// the scalar cache.
+template <typename T, typename TA, int MAXB>
+__device__ inline void piece_item(const StepArgs& a, int64_t gid, bool uni) {
   if (gid >= (int64_t)a.npiece * a.ns) return;
   int p = (int)(gid / a.ns);
   const int s = (int)(gid % a.ns);
-  // n_s a multiple of 64: one piece per wavefront, so its descriptor,
-  // incidence list and inverse mass are read through the scalar cache
-  if constexpr (UNI) p = __builtin_amdgcn_readfirstlane(p);
+  if (uni) p = __builtin_amdgcn_readfirstlane(p);
   const OnlinePiece pc = a.d_pieces[p];
   // the unrolled bodies hold NC x rows flux values in registers: edge lines
   // (4 cells) up to 9 rows, corner points (8 cells) up to 4; wider pieces of
@@ -725,10 +733,14 @@ __global__ __launch_bounds__(256) void k_piece_phase(StepArgs a) {
   if (a.d_prec_ptr) piece_receivers<T, TA>(a, p, s);
 }
 
-// Receivers: one thread per (receiver, source) over the new piece state.
+template <typename T, typename TA, int MAXB, bool UNI>
+__global__ __launch_bounds__(256) void k_piece_phase(StepArgs a) {
+  piece_item<T, TA, MAXB>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, UNI);
+}
+
+// Work item gid = (receiver, source) of the receivers: the new piece state.
 template <typename T, typename TA>
-__global__ __launch_bounds__(256) void k_receivers(StepArgs a) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void receiver_item(const StepArgs& a, int64_t gid) {
   if (gid >= (int64_t)a.nrec * a.ns) return;
   const int r = (int)(gid / a.ns), s = (int)(gid % a.ns);
   const T* y = reinterpret_cast<const T*>(a.y_old);   // holds level n+1 now
@@ -736,6 +748,110 @@ __global__ __launch_bounds__(256) void k_receivers(StepArgs a) {
   for (int64_t k = a.d_rptr[r]; k < a.d_rptr[r + 1]; ++k) acc += (TA)a.d_rval[k] * (TA)y[a.d_rrow[k] * a.ns + s];
   reinterpret_cast<T*>(a.traces)[(a.trace_step * a.nrec + r) * a.ns + s] = (T)acc;
 }
+
+template <typename T, typename TA>
+__global__ __launch_bounds__(256) void k_receivers(StepArgs a) {
+  receiver_item<T, TA>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent on-line kernel: one cooperative launch runs many leapfrog steps.
+// Each step: the cell phase over all (cell, 64-source tile) items, strided
+// over the resident workgroups (with the receivers of the previous step when
+// they are not fused), a grid barrier, the piece phase over all (piece,
+// source) items, a grid barrier. The launch is cooperative, so every
+// workgroup is resident and every thread reaches every barrier.
+// ---------------------------------------------------------------------------
+
+template <int NCH, int PM, int MAXB, int TS, int MINW, bool LEAN>
+__global__ __launch_bounds__(64 * NCH, MINW) void k_persistent(StepArgs a, int kp, int ntile, PersistArgs pa) {
+  using T = typename Prec<PM>::T;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int ncb = ((a.nlist + 7) / 8) * 8 * ntile;
+  const int64_t npi = (int64_t)a.npiece * a.ns, nri = (int64_t)a.nrec * a.ns;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool uni = a.ns % 64 == 0;
+  StepArgs b = a;
+  for (int64_t s = 0; s < pa.n_steps; ++s) {
+    const int cur = (pa.cur0 + (int)(s & 1)) & 1;
+    b.y_cur = pa.y[cur]; b.y_old = pa.y[1 - cur];
+    b.h_cur = pa.h[cur]; b.h_old = pa.h[1 - cur];
+    b.step = s; b.trace_step = s;
+    if (!pa.rec_fused && s > 0) {
+      // the previous step's new level is this step's current level
+      StepArgs r = b;
+      r.y_old = b.y_cur;
+      r.trace_step = s - 1;
+      for (int64_t gid = g0; gid < nri; gid += stride) receiver_item<T, T>(r, gid);
+    }
+    for (int bid = blockIdx.x; bid < ncb; bid += gridDim.x) {
+      cell_mfma_body<NCH, 4, 4, false, TS, LEAN, PM>(b, kp, ntile, bid, lds_raw);
+      __syncthreads();   // the next item rewrites the layer tiles
+    }
+    grid.sync();
+    for (int64_t gid = g0; gid < npi; gid += stride) piece_item<T, T, MAXB>(b, gid, uni);
+    grid.sync();
+  }
+  if (!pa.rec_fused && pa.n_steps > 0) {
+    StepArgs r = b;   // b.y_old holds the last step's new level
+    for (int64_t gid = g0; gid < nri; gid += stride) receiver_item<T, T>(r, gid);
+  }
+}
+
+template <int NCH, int PM, int MAXB>
+static hipError_t launch_persistent_t(const StepArgs& a, const PersistArgs& pa, hipStream_t st) {
+  constexpr int ES = sizeof(typename Prec<PM>::T);
+  constexpr int B3 = tile_bytes(NCH, 3, 64, ES), B2 = tile_bytes(NCH, 2, 64, ES);
+  static_assert(B2 <= LDS_BYTES, "two layer tiles must fit");
+  constexpr int TS = B3 <= LDS_BYTES ? 3 : 2;
+  constexpr int MINW = lds_waves(NCH, TS == 3 ? B3 : B2);
+  constexpr bool LEAN = TS == 2;
+  const void* fn = reinterpret_cast<const void*>(&k_persistent<NCH, PM, MAXB, TS, MINW, LEAN>);
+  const int kp = 16 * NCH + 4;
+  const size_t lds = (size_t)TS * 64 * kp * ES;
+  const int ntile = (a.ns + 63) / 64;
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * NCH, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const int grid = per_cu * prop.multiProcessorCount;
+  StepArgs a1 = a;
+  PersistArgs p1 = pa;
+  int kp1 = kp, nt1 = ntile;
+  void* args[] = {&a1, &kp1, &nt1, &p1};
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(64 * NCH), args, (unsigned)lds, st);
+}
+
+template <int NCH, int PM>
+static hipError_t persistent_bp(const StepArgs& a, const PersistArgs& pa, hipStream_t st) {
+  if (a.max_bp <= 4) return launch_persistent_t<NCH, PM, 4>(a, pa, st);
+  if (a.max_bp <= 9) return launch_persistent_t<NCH, PM, 9>(a, pa, st);
+  return launch_persistent_t<NCH, PM, 16>(a, pa, st);
+}
+
+template <int PM>
+static hipError_t persistent_nch(const StepArgs& a, const PersistArgs& pa, hipStream_t st) {
+  const int need = (a.max_b + 15) / 16;
+  if (need <= 4) return persistent_bp<4, PM>(a, pa, st);
+  if (need <= 7) return persistent_bp<7, PM>(a, pa, st);
+  return persistent_bp<9, PM>(a, pa, st);
+}
+
+bool persistent_supported(const StepArgs& a) {
+  return (a.prec == SFROM_F32 || a.prec == SFROM_F64) && a.max_b <= 144 && a.max_bp <= 16 && a.ns > 0;
+}
+
+hipError_t launch_persistent(const StepArgs& a, const PersistArgs& pa, hipStream_t st) {
+  if (!persistent_supported(a)) return hipErrorInvalidValue;
+  if (a.prec == SFROM_F64) return persistent_nch<2>(a, pa, st);
+  return persistent_nch<0>(a, pa, st);
+}
+
 
 int cell_tile(const StepArgs& a, size_t acc_bytes) {
   // largest power-of-two source tile (<= 64) whose LDS fits in 64 KiB

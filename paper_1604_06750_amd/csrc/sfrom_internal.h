@@ -219,6 +219,18 @@ struct StepArgs {
   int32_t nlist;
 };
 hipError_t launch_online_step(const StepArgs& a, hipStream_t st);
+// Persistent on-line kernel (one cooperative launch for n_steps steps): the
+// two state levels of the piece dofs and hidden layers, the level that holds
+// step 0's current state, and whether the piece phase computes the traces.
+struct PersistArgs {
+  int64_t n_steps;
+  int32_t cur0, rec_fused;
+  void* y[2];
+  void* h[2];
+};
+// FP32 or FP64, max_b <= 144 and max_bp <= 16
+bool persistent_supported(const StepArgs& a);
+hipError_t launch_persistent(const StepArgs& a, const PersistArgs& pa, hipStream_t st);
 // Correction at the corner-set nodes (App. D) on the piece state y (level
 // n + 1, after the piece phase): for corner node k with hanging copies
 // t = hptr[k] .. hptr[k+1], u_t = S_p(row of t, :) y_p and
@@ -367,6 +379,8 @@ struct sfrom {
     std::vector<double> hweight;
   };
   CornerMap cmap;
+  // on-line steps of a run in one cooperative persistent launch
+  bool persistent = false;
   // App. D correction after every on-line step, and its device arrays
   // (staged from the built ROM's piece bases on the first run)
   bool corner_corr = false;

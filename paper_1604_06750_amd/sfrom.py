@@ -72,6 +72,7 @@ _SIGS = {
     "sfrom_remove_corner_set": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
     "sfrom_corner_map": [_P, _P, _P, _P, _P, _P],
     "sfrom_set_corner_correction": [_P, C.c_int32],
+    "sfrom_set_persistent": [_P, C.c_int32],
     "sfrom_build": [_P, C.POINTER(sfrom_build_opts)],
     "sfrom_import_rom": [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P],
     "sfrom_export_rom": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P],
@@ -259,6 +260,10 @@ def sfrom_corner_map(h, n_old, n_corner, n_hanging):
     _check(h, _lib.sfrom_corner_map(h, new_of_old.ctypes.data, corner.ctypes.data, ptr.ctypes.data,
                                     node.ctypes.data, wt.ctypes.data))
     return new_of_old, corner, ptr, node, wt
+
+
+def sfrom_set_persistent(h, enable):
+    _check(h, _lib.sfrom_set_persistent(h, int(enable)))
 
 
 def sfrom_set_corner_correction(h, enable):
