@@ -806,13 +806,14 @@ def main():
     online_graph_ms = e0.elapsed_time(e1)
     graph_same = bool(np.array_equal(tr.double().cpu().numpy(), rom_tr))
     S.sfrom_set_graph(h, False)
-    # the same on-line run as one persistent cooperative launch (one warm-up
-    # run of 10 steps, then one timed run), where its limits allow
+    # the same on-line run as one persistent cooperative launch (one short
+    # warm-up run, then one timed run), where its limits allow
     persist = None
     if args.prec in ("f32", "f64") and S.sfrom_get_info(h)["max_b"] <= 144:
         S.sfrom_set_persistent(h, 1)
         S.sfrom_reset(h)
-        S.sfrom_run(h, 10, dt, w[:10], tr[:10])
+        k = min(10, nt)
+        S.sfrom_run(h, k, dt, w[:k], tr[:k])
         S.sfrom_reset(h)
         torch.cuda.synchronize()
         e0.record(stream)
