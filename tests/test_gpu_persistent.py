@@ -5,12 +5,14 @@ same seeded inputs: b = 98 with 16 sources (the source count not a multiple
 of 64) in FP64 (1e-10) and FP32 (1e-4), b = 56 with 64 sources and a
 receiver column spanning two pieces (the receivers computed beside the next
 step's cell phase; FP64 within 1e-12 of the default path), a run split in
-two continuing the state of the first, and the refusals (BF16 blocks)."""
+two continuing the state of the first, per-cell layer counts 1..4, and the
+refusals (BF16 blocks)."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import pipeline
+from oracle.rom_cell import build_cell
 
 pytestmark = pytest.mark.gpu
 
@@ -33,14 +35,14 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
 
 
-def _run(wl, prec, dt, w, persistent, split=None, receivers=None):
+def _run(wl, prec, dt, w, persistent, split=None, receivers=None, m_per_cell=None):
     S, P = _lib()
     h = S.sfrom_create(0, torch.cuda.current_stream().cuda_stream)
     try:
         P.setup(h, wl)
         if receivers is not None:
             S.sfrom_set_receivers(h, *receivers, project=False)
-        S.sfrom_build(h, wl.m, wl.shift, prec)
+        S.sfrom_build(h, wl.m, wl.shift, prec, m_per_cell=m_per_cell)
         S.sfrom_set_persistent(h, int(persistent))
         info = S.sfrom_get_info(h)
         dtype = np.float64 if prec == S.SFROM_F64 else np.float32
@@ -98,6 +100,25 @@ def test_persistent_receivers_across_pieces_b56(dev):
     b = _run(wl, S.SFROM_F64, run.dt, run.w, False, receivers=recv)
     print(f"persistent vs default (receivers kernel): {rel(a, b):.2e}")
     assert np.abs(b).max() > 0 and rel(a, b) <= 1e-12
+
+
+def test_persistent_uneven_layers(dev):
+    """Per-cell layer counts 1..4 (every branch of the strip sequence) in the
+    persistent kernel: FP64 within 1e-10 of the oracle and equal to the
+    default path."""
+    S, P = _lib()
+    print("[persistent] per-cell m 1..4", flush=True)
+    wl = synth.workload("tiny", modes_face=4, modes_edge=2, m=3, n_steps=200)
+    run = pipeline.setup(wl)
+    mpc = np.array([1, 2, 3, 4, 4, 3, 2, 1], np.int32)
+    for i in range(len(run.part.cells)):
+        Ai, bi = run.part.cell_operator(i, wl.sigma, wl.rho)
+        run.blocks[i] = build_cell(Ai, bi, run.part.cell_W(i), wl.shift, int(mpc[i]))
+    ref = pipeline.rom_traces(run)
+    a = _run(wl, S.SFROM_F64, run.dt, run.w, True, m_per_cell=mpc)
+    b = _run(wl, S.SFROM_F64, run.dt, run.w, False, m_per_cell=mpc)
+    print(f"persistent uneven m: vs oracle {rel(a, ref):.2e}, vs default {rel(a, b):.2e}")
+    assert rel(a, ref) <= 1e-10 and rel(a, b) <= 1e-13
 
 
 def test_persistent_refusals(dev):
