@@ -195,11 +195,12 @@ int sfrom_gramian_bases(sfrom_t* h, double omega_max, double eps, int32_t max_mo
  * Each partial fraction is one complex symmetric band solve per piece node
  * (LDL^T without pivoting in reverse Cuthill-McKee order, valid because
  * i (X - i beta I) has a positive definite Hermitian part), so the local
- * pencil has no size limit; eps must exceed the approximant's error (about
+ * pencil has no dense size limit (its band factor and solution columns must
+ * fit in 2 GiB per piece); eps must exceed the approximant's error (about
  * 4 exp(-pi^2 n_poles / log(4 / delta))) or spurious modes are kept. The
  * Jacobi elliptic functions come from the arithmetic-geometric mean.
- * Errors: as sfrom_gramian_bases, and EINVAL for n_poles outside [1, 64] or
- * gamma outside (0, 1). */
+ * Errors: as sfrom_gramian_bases, and EINVAL for n_poles outside [1, 64],
+ * gamma outside (0, 1) or a piece above the memory limit. */
 int sfrom_gramian_bases_zolotarev(sfrom_t* h, double omega_max, double eps, int32_t max_modes, int32_t depth,
                                   int32_t n_poles, double gamma);
 

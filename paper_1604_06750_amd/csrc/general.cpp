@@ -509,6 +509,10 @@ Sub union_pencil(const sfrom_t* h, const std::vector<int32_t>& cells) {
 // Zolotarev route to the spectral projector (eq. trgrstep)
 // ---------------------------------------------------------------------------
 
+// Host memory of one piece's band solves (each of up to 16 worker threads
+// holds one piece at a time).
+constexpr double ZOLOTAREV_MAX_BYTES = 2.0 * 1024 * 1024 * 1024;
+
 // K(k) = pi / (2 AGM(1, k')).
 double agm_ellipk(double k) {
   double a = 1.0, b = std::sqrt(1.0 - k * k);
@@ -613,6 +617,13 @@ std::vector<double> gramian_zolotarev(const Sub& sl, const std::vector<int>& row
     return sl.col[t] == k ? (w2 - c) / sc : -c / sc;
   };
   const size_t W1 = (size_t)w + 1;
+  // band factor (complex) and accumulated columns of one piece, per thread
+  const double bytes = (double)n * (double)W1 * 16.0 + (double)n * kp * 8.0;
+  if (bytes > ZOLOTAREV_MAX_BYTES)
+    gfail(SFROM_EINVAL, "local pencil of " + std::to_string(n) + " nodes with half bandwidth " + std::to_string(w) +
+                            " needs " + std::to_string((long long)(bytes / 1048576.0)) +
+                            " MiB for the band solves, above the per-piece limit of " +
+                            std::to_string((long long)(ZOLOTAREV_MAX_BYTES / 1048576.0)) + " MiB (lower depth)");
   std::vector<double> acc((size_t)n * kp, 0.0);   // sum_j a_j (X^2 + beta_j^2)^{-1} E, permuted rows
   std::vector<cd> L((size_t)n * W1), y(n);
   for (int j = 0; j < npole; ++j) {
