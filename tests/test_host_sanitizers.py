@@ -1,5 +1,6 @@
 """The host C++ of the library (partition set-up, split checks, column
-restriction, general partition, Gramian bases, argument validation) under
+restriction, general partition, Gramian bases by eigenpairs and by the
+Zolotarev projector, corner-set removal, argument validation) under
 AddressSanitizer and UndefinedBehaviorSanitizer: the library is rebuilt
 with both sanitizers on its host code (build.build_sanitized) and the
 host-only ABI tests run against it in a child process with the ASan runtime
@@ -28,7 +29,7 @@ def test_host_abi_under_asan_and_ubsan():
         "maps = open('/proc/self/maps').read()\n"
         "assert 'libclang_rt.asan' in maps and sfrom.LIB_PATH in maps\n"
         "sys.exit(pytest.main(['-x', '-q', '-p', 'no:cacheprovider', 'tests/test_abi_host.py', "
-        "'tests/test_abi_general.py']))\n")
+        "'tests/test_abi_general.py', 'tests/test_abi_corners.py']))\n")
     r = subprocess.run([sys.executable, "-c", script], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=1500)
     print(r.stdout[-2000:])
