@@ -7,7 +7,9 @@ sources and receivers on old nodes, one source and several receivers on
 removed corner nodes (a load there is shared among the copies by the
 weights b'_l / b_k, a reading is their weighted sum). Checks: FP64 traces
 within 1e-9 and FP32 within 1e-4 of the oracle, with the correction off and
-on, and the corrected run differs from the uncorrected one."""
+on, and the corrected run differs from the uncorrected one; and a seeded
+3000-node unstructured pencil in 6 cells (whole-union bases, one cell at
+m_i = 1 where its Krylov block loses rank) with the correction on."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -48,16 +50,13 @@ def _build_largest_m(Ai, bi, W, shift, m):
             m = int(str(e).split("block ")[1].split()[0]) - 1
 
 
-@pytest.fixture(scope="module")
-def case():
-    sig, rho = synth.acoustic_medium((16, 16, 16), 21, ell_sigma=5.0, ell_rho=2.0)
-    A, b = fine.assemble_acoustic(sig, rho)
+def _make_case(A, b, n_cells, omega, eps, modes, depth, seed, n_src, n_rec):
     A = sp.csr_matrix(A); A.sort_indices()
-    P = dc.GeneralPartition(A, b, 8)
+    P = dc.GeneralPartition(A, b, n_cells)
     H = cn.HangingPartition(P)
     ops = {i: (s.nodes, s.A, s.b) for i, s in enumerate(H.subs)}
-    H.set_bases(gr.gramian_bases(H, ops, OMEGA, EPS, MODES, DEPTH))
-    shift = -OMEGA ** 2 / 10.0
+    H.set_bases(gr.gramian_bases(H, ops, omega, eps, modes, depth))
+    shift = -omega ** 2 / 10.0
     blocks, m_cell = {}, []
     for i in range(len(H.subs)):
         Ai, bi = H.cell_operator(i)
@@ -65,17 +64,31 @@ def case():
         m_cell.append(mi)
     rom = GlobalROM(H, blocks)
     skel_old = np.sort(np.concatenate([pc.nodes for pc in P.pieces]))
-    rng = np.random.Generator(np.random.PCG64(5))
-    src = np.unique(np.concatenate([rng.choice(skel_old, 3, replace=False), H.corner_nodes[:1]]))
-    rec = np.unique(np.concatenate([rng.choice(skel_old, 12, replace=False), H.corner_nodes[:4]]))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    src = np.unique(np.concatenate([rng.choice(skel_old, n_src, replace=False), H.corner_nodes[:1]]))
+    rec = np.unique(np.concatenate([rng.choice(skel_old, n_rec, replace=False), H.corner_nodes[:4]]))
     F, Qr = H.old_reduced_columns(rom, src), H.old_reduced_columns(rom, rec)
     dt = fine.cfl_dt(A, b, 0.5)
-    w = synth.ricker(300, dt, OMEGA / (2.0 * np.pi * 2.5))
+    w = synth.ricker(300, dt, omega / (2.0 * np.pi * 2.5))
     c = type("Case", (), {})()
     c.A, c.b, c.H, c.src, c.rec, c.dt, c.w, c.shift, c.m_cell = A, b, H, src, rec, dt, w, shift, m_cell
+    c.n_cells, c.gram = n_cells, (omega, eps, modes, depth)
     c.ref = rom.leapfrog(F, Qr, w, dt)
     c.refc = cn.leapfrog_corrected(H, rom, F, Qr, w, dt)
     return c
+
+
+@pytest.fixture(scope="module")
+def case():
+    sig, rho = synth.acoustic_medium((16, 16, 16), 21, ell_sigma=5.0, ell_rho=2.0)
+    A, b = fine.assemble_acoustic(sig, rho)
+    return _make_case(A, b, 8, OMEGA, EPS, MODES, DEPTH, 5, 3, 12)
+
+
+@pytest.fixture(scope="module")
+def graph_case():
+    A, b, _ = synth.geometric_graph(3000, 6, 7)
+    return _make_case(A, b, 6, 0.45, 1e-6, 5, -1, 6, 3, 10)
 
 
 def _point_columns(H, nodes):
@@ -95,13 +108,14 @@ def _gpu(c, prec, correct):
     h = S.sfrom_create(0, torch.cuda.current_stream().cuda_stream)
     try:
         S.sfrom_set_pencil(h, c.A.indptr.astype(np.int64), c.A.indices.astype(np.int32), c.A.data, c.b)
-        S.sfrom_partition_graph(h, 8)
+        S.sfrom_partition_graph(h, c.n_cells)
         n1, nk, nh = S.sfrom_remove_corner_set(h)
         assert (n1, nk, nh) == (c.H.n, len(c.H.corner_nodes), len(c.H.hang_node))
-        S.sfrom_gramian_bases(h, OMEGA, EPS, MODES, DEPTH)
+        S.sfrom_gramian_bases(h, *c.gram)
         S.sfrom_set_sources(h, *_point_columns(c.H, c.src))
         S.sfrom_set_receivers(h, *_point_columns(c.H, c.rec))
         S.sfrom_build(h, M, c.shift, prec, m_per_cell=np.array(c.m_cell, np.int32))
+        assert [len(S.sfrom_export_rom(h, i)[0]) for i in range(c.n_cells)] == list(c.m_cell)
         S.sfrom_set_corner_correction(h, int(correct))
         tr = np.zeros((len(c.w), len(c.rec), len(c.src)), np.float64 if prec == S.SFROM_F64 else np.float32)
         S.sfrom_run(h, len(c.w), c.dt, c.w, tr)
@@ -128,3 +142,17 @@ def test_hanging_nodes_match_oracle(dev, case, correct):
           f"corrected vs uncorrected oracle {_rel(case.refc, case.ref):.2e}")
     assert np.abs(ref).max() > 0 and _rel(case.refc, case.ref) > 1e-6
     assert e <= 1e-9 and per <= 1e-8 and e32 <= 1e-4
+
+
+def test_hanging_nodes_unstructured_graph(dev, graph_case):
+    """The same on a seeded 3000-node unstructured pencil in 6 cells (whole
+    union Gramian bases), with the correction on."""
+    S = _lib()
+    c = graph_case
+    tr = _gpu(c, S.SFROM_F64, True)
+    e = _rel(tr, c.refc)
+    tr32 = _gpu(c, S.SFROM_F32, True)
+    e32 = _rel(tr32, c.refc)
+    print(f"graph, corner correction on: m_i {c.m_cell}, {len(c.H.corner_nodes)} removed nodes, "
+          f"{len(c.H.hang_node)} copies; FP64 {e:.2e}, FP32 {e32:.2e}")
+    assert len(c.H.corner_nodes) > 0 and e <= 1e-9 and e32 <= 1e-4
