@@ -405,8 +405,11 @@ int sfrom_save(sfrom_t* h, const char* path);
  * of the handle without building; the saved state continues at the next
  * sfrom_run when the handle has as many sources as were saved, so that n
  * steps, save, load and n more steps equal 2n steps bitwise. Sources and
- * receivers are not part of the checkpoint. A failure after the file has
- * been validated leaves no ROM. Errors: EINVAL, EDEVICE, ENOMEM. */
+ * receivers are not part of the checkpoint. A partition whose corner set was
+ * removed is set up again by repeating sfrom_remove_corner_set (the removal
+ * is deterministic; it also restores the corner map) before the load. A
+ * failure after the file has been validated leaves no ROM. Errors: EINVAL,
+ * EDEVICE, ENOMEM. */
 int sfrom_load(sfrom_t* h, const char* path);
 
 /* Zero the fine-grid state. */
