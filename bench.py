@@ -194,6 +194,24 @@ def extra_setting(S, problem, synth, args, stream, dev, tdt, prec, nt, dt, w, fi
         cell_ms, cell_n = S.sfrom_profile_read(h, S.KERNEL_CELL)
         S.sfrom_profile(h, False)
         rom = tr.double().cpu().numpy()
+        # on-line run alone: default launches and one persistent launch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        online = {}
+        for mode in (0, 1):
+            if mode and not (args.prec in ("f32", "f64") and info["max_b"] <= 144):
+                continue
+            S.sfrom_set_persistent(h, mode)
+            S.sfrom_reset(h)
+            k = min(10, nt)
+            S.sfrom_run(h, k, dt, w[:k], tr[:k])
+            S.sfrom_reset(h)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            S.sfrom_run(h, nt, dt, w, tr)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            online["persistent" if mode else "default"] = round(ns * nt / (e0.elapsed_time(e1) / 1e3), 1)
+        S.sfrom_set_persistent(h, 0)
         S.sfrom_fine_reset(h)
         t64 = torch.zeros((nt, nr, ns), dtype=torch.float64, device=dev)
         S.sfrom_fine_run(h, nt, dt, w, t64, S.SFROM_F64)
@@ -205,7 +223,7 @@ def extra_setting(S, problem, synth, args, stream, dev, tdt, prec, nt, dt, w, fi
         return {"modes": "4 face + 2 edge + 1 corner", "m": 4, "max_b": info["max_b"],
                 "job_source_steps_per_s": round(ns * nt / t, 1), "rel_l2_vs_fine_fp64": err,
                 "meets_gate": bool(err <= GATE), "speedup_job_vs_fine": round(ns * nt / t / fine_ssps, 3),
-                "cell_phase_avg_ms": round(avg, 4),
+                "cell_phase_avg_ms": round(avg, 4), "online_source_steps_per_s": online,
                 "cell_phase_hbm_frac_at_algorithmic_bytes": round(bytes_ / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     finally:
         S.sfrom_destroy(h)
@@ -282,7 +300,7 @@ def paper_shaped(S, problem, synth, stream, dev, cell=32, ncell=8, ppw=40.0, mf=
                 "fine_source_steps_per_s": ssps(fine_ms), "build_ms": round(job_ms - online_ms, 1),
                 "online_ms": round(online_ms, 1), "fine_ms": round(fine_ms, 1),
                 "speedup_job_vs_fine": round(fine_ms / job_ms, 3), "speedup_online_vs_fine": round(fine_ms / online_ms, 3),
-                "cell_phase_avg_ms": round(avg, 4),
+                "cell_phase_avg_ms": round(avg, 4), "online_source_steps_per_s": online,
                 "cell_phase_tflops": round(flops / (avg * 1e-3) / 1e12, 2),
                 "cell_phase_hbm_gbs_at_algorithmic_bytes": round(bytes_ / (avg * 1e-3) / 1e9, 1)}
     finally:
