@@ -405,6 +405,43 @@ __device__ void wg_copy(int rows, int cols, const double* A, int lda, double* B,
   __syncthreads();
 }
 
+// B = A^T (n x n, distinct storage)
+__device__ void wg_transpose(int n, const double* A, int lda, double* B, int ldb) {
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+    const int i = idx % n, j = idx / n;
+    B[j + (int64_t)i * ldb] = A[i + (int64_t)j * lda];
+  }
+  __syncthreads();
+}
+
+// X (rows x n) <- X L^{-1} for lower L (n x n): solves q L = x row-wise,
+// last column first.
+__device__ void wg_trsm_right_l(int rows, int n, const double* L, int ldl, double* X, int ldx) {
+  for (int r = threadIdx.x; r < rows; r += NT) {
+    for (int j = n - 1; j >= 0; --j) {
+      double s = X[r + (int64_t)j * ldx];
+      for (int l = j + 1; l < n; ++l) s -= X[r + (int64_t)l * ldx] * L[l + (int64_t)j * ldl];
+      X[r + (int64_t)j * ldx] = s / L[j + (int64_t)j * ldl];
+    }
+  }
+  __syncthreads();
+}
+
+// 1 if every diagonal entry of the n x n matrix is nonzero and finite
+__device__ int wg_diag_ok(int n, const double* A, int lda) {
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) s_ok = 1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double d = A[i + (int64_t)i * lda];
+    if (!(d != 0.0) || !isfinite(d)) s_ok = 0;
+  }
+  __syncthreads();
+  const int ok = s_ok;
+  __syncthreads();
+  return ok;
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -924,6 +961,13 @@ __global__ __launch_bounds__(NT, 3) void k_lanczos(BuildBatch bb) {
 
 // K5: S-fraction blocks from (alpha_k, beta_k) (eq. GammaTrans, corrected).
 // Output at out_off: Ghat^1..Ghat^m then G^1..G^m.
+// No general inverse is formed: with H_k = G_k^{-T},
+//   H_1 = beta_1^{-1} (beta_1 upper triangular, G_1 = beta_1^T),
+//   Ghat^k = G_k G_k^T,  G^k = -H_k (alpha_k H_k^T) - G^{k-1},
+//   G_{k+1} = (G_k^T G^k)^{-1} beta_{k+1}^T = (G^k)^{-1} H_k beta_{k+1}^T
+//     (a Cholesky solve with the factor of G^k that the SPD check computes),
+//   H_{k+1} = (G_{k+1}^{-1})^T = G^k G_k beta_{k+1}^{-1}
+//     (a triangular solve), so every step is a product or a triangular solve.
 // 3 waves per SIMD: a few spilled registers buy a third resident workgroup
 // per CU for this chain of small dependent products
 __global__ __launch_bounds__(NT, 3) void k_sfraction(BuildBatch bb) {
@@ -936,31 +980,29 @@ __global__ __launch_bounds__(NT, 3) void k_sfraction(BuildBatch bb) {
   double* out = bb.d_work + c.out_off;
   double* Ghat = out;
   double* G = out + m * bb2;
-  // scratch in the av region: Gk, Ginv, T1, Mt, Minv, W, fac, chol
+  // scratch in the av region: Gk, H (= G_k^{-T}), T1, Y, P, Bt, ch
   double* base = bb.d_work + c.av_off;
   double* Gk = base;
-  double* Ginv = Gk + bb2;
-  double* T1 = Ginv + bb2;
-  double* Mt = T1 + bb2;
-  double* Minv = Mt + bb2;
-  double* Wk = Minv + bb2;
-  double* fac = Wk + bb2;
-  double* ch = fac + b;
-  // G_1 = beta_1^T
-  for (int idx = threadIdx.x; idx < b * b; idx += NT) {
-    const int r = idx % b, cc = idx / b;
-    Gk[r + (int64_t)cc * b] = beta[cc + (int64_t)r * b];
-  }
+  double* H = Gk + bb2;
+  double* T1 = H + bb2;
+  double* Y = T1 + bb2;
+  double* P = Y + bb2;
+  double* Bt = P + bb2;
+  double* ch = Bt + bb2;
+  // G_1 = beta_1^T; H_1 = I beta_1^{-1} (right solve with beta_1^T as L^T)
+  wg_transpose(b, beta, b, Gk, b);
+  if (!wg_diag_ok(b, Gk, b)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
+  for (int idx = threadIdx.x; idx < b * b; idx += NT) H[idx] = (idx % b == idx / b) ? 1.0 : 0.0;
   __syncthreads();
+  wg_trsm_right_lt(b, b, Gk, b, H, b);
   for (int k = 0; k < m; ++k) {
     double* Gh = Ghat + k * bb2;
     double* Gc = G + k * bb2;
     wg_gemm<false, true>(b, b, b, 1.0, Gk, b, Gk, b, 0.0, Gh, b);
     wg_symmetrize(b, Gh, b);
-    if (!wg_inverse(b, Gk, b, Ginv, b, Wk, fac)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
-    wg_gemm<false, false>(b, b, b, 1.0, alpha + k * bb2, b, Ginv, b, 0.0, T1, b);
+    wg_gemm<false, true>(b, b, b, 1.0, alpha + k * bb2, b, H, b, 0.0, T1, b);
     if (k > 0) wg_copy(b, b, G + (k - 1) * bb2, b, Gc, b);
-    wg_gemm<true, false>(b, b, b, -1.0, Ginv, b, T1, b, (k > 0) ? -1.0 : 0.0, Gc, b);
+    wg_gemm<false, false>(b, b, b, -1.0, H, b, T1, b, (k > 0) ? -1.0 : 0.0, Gc, b);
     wg_symmetrize(b, Gc, b);
     // SPD checks of the pivots (eq. S-fraction); the deepest G^m of a
     // floating cell is only semidefinite to rounding and is not checked.
@@ -969,13 +1011,23 @@ __global__ __launch_bounds__(NT, 3) void k_sfraction(BuildBatch bb) {
     double r2 = 1.0;
     if (k < m - 1) {
       wg_copy(b, b, Gc, b, ch, b);
-      r2 = wg_potrf(b, ch, b);
+      r2 = wg_potrf(b, ch, b);      // ch: lower Cholesky factor L of G^k
     }
     if (!(r1 > 0.0) || !(r2 > 0.0)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
     if (k < m - 1) {
-      wg_gemm<true, false>(b, b, b, 1.0, Gk, b, Gc, b, 0.0, Mt, b);
-      if (!wg_inverse(b, Mt, b, Minv, b, Wk, fac)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
-      wg_gemm<false, true>(b, b, b, 1.0, Minv, b, beta + (k + 1) * bb2, b, 0.0, Gk, b);
+      const double* bn = beta + (k + 1) * bb2;
+      wg_transpose(b, bn, b, Bt, b);                                   // beta_{k+1}^T, lower
+      if (!wg_diag_ok(b, Bt, b)) { if (threadIdx.x == 0) c.status = ST_NOTSPD; return; }
+      // Y = H_k beta_{k+1}^T; G_{k+1}^T = Y^T L^{-T} L^{-1}
+      wg_gemm<false, false>(b, b, b, 1.0, H, b, Bt, b, 0.0, Y, b);
+      wg_transpose(b, Y, b, T1, b);
+      wg_trsm_right_lt(b, b, ch, b, T1, b);
+      wg_trsm_right_l(b, b, ch, b, T1, b);
+      // P = G^k G_k, then H_{k+1} = P beta_{k+1}^{-1}
+      wg_gemm<false, false>(b, b, b, 1.0, Gc, b, Gk, b, 0.0, P, b);
+      wg_trsm_right_lt(b, b, Bt, b, P, b);
+      wg_transpose(b, T1, b, Gk, b);
+      wg_copy(b, b, P, b, H, b);
     }
   }
   // finite check
