@@ -82,14 +82,18 @@ def test_remove_corner_set_acoustic():
         S.sfrom_destroy(h)
 
 
-def test_remove_corner_set_unstructured_graph():
-    A, b, _ = synth.geometric_graph(1500, 6, 5)
-    P = dc.GeneralPartition(A, b, 5)
+@pytest.mark.parametrize("n,cells,seed", [(1500, 5, 5), (3000, 6, 7)])
+def test_remove_corner_set_unstructured_graph(n, cells, seed):
+    """Two seeded graphs; the second has a corner node whose copies take
+    every pair of its cells (one of them shares no plain interface node with
+    the others)."""
+    A, b, _ = synth.geometric_graph(n, 6, seed)
+    P = dc.GeneralPartition(A, b, cells)
     H = cn.HangingPartition(P)
     S = _lib()
     h = _handle(A, b)
     try:
-        S.sfrom_partition_graph(h, 5)
+        S.sfrom_partition_graph(h, cells)
         _check(h, P, H)
     finally:
         S.sfrom_destroy(h)

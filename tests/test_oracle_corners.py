@@ -30,7 +30,7 @@ from oracle import divconq as dc
 from oracle import fine
 
 
-def voxel_partition(nvox_cell, ncell, sigma=1.0, rho=1.0, literal=False):
+def voxel_partition(nvox_cell, ncell, sigma=1.0, rho=1.0):
     """Uniform voxel grid in len(ncell) dimensions (Neumann), cells of
     nvox_cell voxels per axis: each voxel gives every one of its edges the
     weight sigma / 2^(d-1) and every corner the mass rho / 2^d; a cell's
@@ -95,15 +95,39 @@ def _check_conservation(P, H):
     assert not kept[H.corner_nodes].any() and kept.sum() + len(H.corner_nodes) == P.n
 
 
-@pytest.mark.parametrize("case", ["acoustic", "graph"])
+def _fallback_nodes(P):
+    """Corner nodes one of whose cells shares no node outside the corner set
+    with another of its cells (every pair of its cells gets a copy)."""
+    owners = cn.owner_sets(P.subs, P.n)
+    iface = {tuple(o) for o in owners if len(o) == 2}
+    out = []
+    for k, own in enumerate(owners):
+        if len(own) < 3:
+            continue
+        pairs = [(own[a], own[c]) for a in range(len(own)) for c in range(a + 1, len(own)) if (own[a], own[c]) in iface]
+        if {x for pr in pairs for x in pr} != set(own):
+            out.append(k)
+    return out
+
+
+@pytest.mark.parametrize("case", ["acoustic", "graph", "graph_fallback"])
 def test_conservation_and_pairwise_pieces(case):
     if case == "acoustic":
         P = _acoustic_partition()
-    else:
+    elif case == "graph":
         A, b, _ = synth.geometric_graph(1500, 6, 5)
         P = dc.GeneralPartition(A, b, 5)
+    else:
+        A, b, _ = synth.geometric_graph(3000, 6, 7)
+        P = dc.GeneralPartition(A, b, 6)
+        fb = _fallback_nodes(P)
+        assert len(fb) >= 1
+        own = cn.owner_sets(P.subs, P.n)
+        pairs_all = len(own[fb[0]]) * (len(own[fb[0]]) - 1) // 2
     H = cn.HangingPartition(P)
     assert len(H.corner_nodes) > 0
+    if case == "graph_fallback":
+        assert len(H.pairs[fb[0]]) == pairs_all
     _check_conservation(P, H)
     for s in H.subs:
         assert np.linalg.eigvalsh(s.A.toarray()).max() <= 1e-12 * np.abs(s.A.data).max()
