@@ -3,8 +3,9 @@ sfrom_corner_map; App. B) with the oracle (oracle/corners.py) on host-only
 handles: the new pencil, every cell's operator and masses (by global node)
 and the corner map bit for bit (the library takes the same quotients and
 sums in the same order), the pair pieces' node sets, and Gramian bases on
-the new pieces (projectors within 1e-9); plus the error paths and a
-partition without a corner set."""
+the new pieces (projectors within 1e-9); the removal on a Cartesian voxel
+set-up checked from the library's own outputs (E^T A' E = A); plus the
+error paths and a partition without a corner set."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -123,5 +124,44 @@ def test_no_corner_set_and_errors():
         after = S.sfrom_export_pencil(h)
         assert all(np.array_equal(x, y) for x, y in zip(before, after))
         S.sfrom_set_corner_correction(h, 0)
+    finally:
+        S.sfrom_destroy(h)
+
+
+def test_remove_corner_set_on_voxel_partition():
+    """The removal on the Cartesian set-up (2 x 2 x 2 cells of 8^3 voxels):
+    from the library's own outputs, E^T A' E and E^T B' E equal the pencil
+    before the removal (E built from the corner map), every piece is held by
+    two cells, and edge nodes get 4 copies, the centre node 12."""
+    S = _lib()
+    sig, rho = synth.acoustic_medium((16, 16, 16), 9, ell_sigma=4.0, ell_rho=2.0)
+    h = S.sfrom_create(-1, 0)
+    try:
+        S.sfrom_setup_voxel_acoustic(h, sig, rho, ([8], [8], [8]), 4, 2)
+        rp0, cl0, a0, b0 = S.sfrom_export_pencil(h)
+        n0 = len(b0)
+        A0 = sp.csr_matrix((a0, cl0, rp0), shape=(n0, n0))
+        n1, nk, nh = S.sfrom_remove_corner_set(h)
+        new_of_old, corner, ptr, node, wt = S.sfrom_corner_map(h, n0, nk, nh)
+        rp1, cl1, a1, b1 = S.sfrom_export_pencil(h)
+        A1 = sp.csr_matrix((a1, cl1, rp1), shape=(n1, n1))
+        rows = list(new_of_old[new_of_old >= 0]) + list(node)
+        cols = list(np.where(new_of_old >= 0)[0]) + list(np.repeat(corner, np.diff(ptr)))
+        E = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n1, n0))
+        D = (E.T @ A1 @ E - A0).tocoo()
+        assert np.abs(D.data).max(initial=0.0) <= 1e-13 * np.abs(a0).max()
+        assert np.abs(E.T @ b1 - b0).max() <= 1e-15 * b0.max()
+        assert np.abs(np.add.reduceat(wt, ptr[:-1]) - 1.0).max() <= 1e-14
+        counts = sorted(set(np.diff(ptr).tolist()))
+        assert counts == [4, 12], counts
+        info = S.sfrom_get_info(h)
+        own = {}
+        for i in range(info["n_cells"]):
+            for g in S.sfrom_export_cell(h, i)["global_node"]:
+                own[int(g)] = own.get(int(g), 0) + 1
+        assert max(own.values()) == 2
+        for p in range(info["n_pieces"]):
+            g, _ = S.sfrom_export_piece(h, p)
+            assert all(own[int(x)] == 2 for x in g)
     finally:
         S.sfrom_destroy(h)
