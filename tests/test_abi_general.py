@@ -206,3 +206,30 @@ def test_zolotarev_route_has_no_dense_limit():
         _check_zolotarev(h, P, 0.6, 1e-4, 8, -1, 10, 0.05)
     finally:
         S.sfrom_destroy(h)
+
+
+def test_zolotarev_bases_on_voxel_partition():
+    """The Zolotarev route on the Cartesian set-up (2 x 2 x 2 cells of 8^3
+    voxels, whole-union pencils) against the oracle's route on the oracle's
+    voxel partition: the same basis sizes and projectors within 1e-8."""
+    from oracle import zolotarev as zo
+    from oracle.partition import CartesianPartition
+    S = _lib()
+    sig, rho = synth.acoustic_medium((16, 16, 16), 9, ell_sigma=4.0, ell_rho=2.0)
+    cuts = ([8], [8], [8])
+    part = CartesianPartition((16, 16, 16), cuts, 4, 2)
+    ops = {i: (c.nodes,) + part.cell_operator(i, sig, rho) for i, c in enumerate(part.cells)}
+    ref = zo.gramian_bases_zolotarev(part, ops, 0.9, 1e-4, 8, -1, 12, 0.05)
+    h = S.sfrom_create(-1, 0)
+    try:
+        S.sfrom_setup_voxel_acoustic(h, sig, rho, cuts, 4, 2)
+        S.sfrom_gramian_bases_zolotarev(h, 0.9, 1e-4, 8, -1, 12, 0.05)
+        worst = 0.0
+        for p, pc in enumerate(part.pieces):
+            g, Sb = S.sfrom_export_piece(h, p)
+            assert np.array_equal(g, pc.nodes)
+            assert Sb.shape[1] == ref[p].shape[1], p
+            worst = max(worst, np.abs(Sb @ Sb.T - ref[p] @ ref[p].T).max())
+        assert worst <= 1e-8, worst
+    finally:
+        S.sfrom_destroy(h)
