@@ -734,8 +734,8 @@ def main():
                     help="also run one elementwise kernel reading and writing 1 GiB (PMC byte calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of "
-              "this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); runs across several GPUs are not "
+              "implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
