@@ -10,7 +10,7 @@ Readings (the paper leaves these choices open):
 
 * Adjacency is the nonzero pattern of the subdomain's own operator: k and l
   are adjacent iff a_kl != 0 (Sec. 2); a node is adjacent to itself.
-* Choice of the set O of Prop. 1 (step 3 of Alg. 2): a breadth-first level
+* Choice of the set O of Prop. 1 in Alg. 2: a breadth-first level
   structure of the subdomain's graph rooted at a pseudo-peripheral node. The
   root search starts at the subdomain's smallest node and moves to the
   node of smallest degree (then smallest index) in the last level while the
@@ -23,9 +23,9 @@ Readings (the paper leaves these choices open):
   O_2 = Omega \\ A(O) is levels j + 2 and beyond, O_1 = Omega \\ A(O_2) is
   levels 0..j and Gamma is level j + 1. A subdomain of depth < 2 is not
   split.
-* Step 1 of Alg. 2: split the subdomain with the most nodes (ties: the
-  lowest position) among those that can be split; step 2 swaps it with the
-  last position p; step 5 puts the O_1 side at p and the O_2 side at p + 1.
+* Alg. 2 splits the subdomain with the most nodes (ties: the lowest
+  position) among those that can be split, after swapping it with the last
+  position p, and puts the O_1 side at p and the O_2 side at p + 1.
 * alpha_kl = alpha and beta_k = beta are constants (1/2 by default, the
   balancing choice of the one- and two-domain examples of Sec. 2).
 * Pieces of the skeleton: nodes that belong to two or more subdomains,
@@ -99,17 +99,17 @@ def alg1_split(A, b, O1, O2, Gamma, alpha=0.5, beta=0.5):
                     raise ValueError("coupling between O_1 and O_2 (Prop. 1 violated)")
                 continue
             placed = False
-            for i in range(2):                 # step 1: pairs touching O_i
+            for i in range(2):                 # entries at a node of O_i
                 if O[i][k] or O[i][l]:
                     ent[i][k][l] = a
                     placed = True
             if placed:
                 continue
-            if k != l:                         # step 2: Gamma-Gamma links
+            if k != l:                         # links inside Gamma, split by alpha
                 al = alpha(k, l) if callable(alpha) else alpha
                 ent[0][k][l] = al * a
                 ent[1][k][l] = (1.0 - al) * a
-    # step 3: Gamma diagonals in proportion to the off-diagonal sums
+    # Gamma diagonals in proportion to the off-diagonal sums
     for k in np.where(Gamma)[0]:
         s = [sum(abs(v) for l, v in ent[i][k].items() if l != k) for i in range(2)]
         akk = float(A[k, k])
@@ -210,7 +210,7 @@ def alg2_partition(A, b, n_cells: int, alpha=0.5, beta=0.5,
     while len(subs) < n_cells:
         order = sorted(range(len(subs)), key=lambda i: (-len(subs[i].nodes), i))
         found = None
-        for i in order:                        # step 1
+        for i in order:                        # the largest splittable subdomain
             O = pick(subs[i])
             if O is not None:
                 found = (i, O)
@@ -219,11 +219,11 @@ def alg2_partition(A, b, n_cells: int, alpha=0.5, beta=0.5,
             raise ValueError(f"no subdomain can be split further ({len(subs)} of {n_cells})")
         i, O = found
         p = len(subs) - 1
-        subs[i], subs[p] = subs[p], subs[i]    # step 2
+        subs[i], subs[p] = subs[p], subs[i]    # moved to the last position
         s = subs[p]
-        O1, O2, G = prop1_split(s.A, O)        # step 3
-        (n1, A1, b1), (n2, A2, b2) = alg1_split(s.A, s.b, O1, O2, G, alpha, beta)   # step 4
-        subs[p] = Subdomain(s.nodes[n1], A1, b1)                                    # step 5
+        O1, O2, G = prop1_split(s.A, O)        # Prop. 1 sets
+        (n1, A1, b1), (n2, A2, b2) = alg1_split(s.A, s.b, O1, O2, G, alpha, beta)   # Alg. 1 split
+        subs[p] = Subdomain(s.nodes[n1], A1, b1)                                    # O_1 side in place
         subs.append(Subdomain(s.nodes[n2], A2, b2))
     return subs
 

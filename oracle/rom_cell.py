@@ -143,7 +143,7 @@ def sfraction(alphas, betas):
 
 
 def build_cell(A, b, W, s, m):
-    """Off-line stage of one cell (Alg. alg1red, steps 1.1-1.3)."""
+    """Off-line stage of one cell (Alg. alg1red, stage 1)."""
     V = rational_krylov(A, b, W, s, m)
     Am, Sm = project(A, V, W)
     alphas, betas = block_lanczos(Am, Sm, m)

@@ -158,7 +158,7 @@ std::vector<char> prop1(const Sub& s, const std::vector<char>& O) {
   return code;
 }
 
-// Alg. 1 (steps 1-3) and eq. alg1B: the two split operators.
+// Alg. 1 and eq. alg1B: the two split operators.
 void alg1(const Sub& s, const std::vector<char>& code, double alpha, double beta, Sub out[2]) {
   const int n = s.n();
   for (int i = 0; i < 2; ++i) {
@@ -192,7 +192,7 @@ void alg1(const Sub& s, const std::vector<char>& code, double alpha, double beta
             else if (code[l] == 3) sum[q] += std::fabs((q == 0 ? alpha : 1.0 - alpha) * v);
           }
         }
-        if (own) {                        // step 1
+        if (own) {                        // entries at a node of this side
           o.col.push_back(pos[l]);
           o.a.push_back(v);
         } else if (both_gamma) {
@@ -200,12 +200,12 @@ void alg1(const Sub& s, const std::vector<char>& code, double alpha, double beta
           if (l == k) {
             diag_at = (int64_t)o.a.size();
             o.a.push_back(0.0);
-          } else {                        // step 2
+          } else {                        // links inside Gamma, split by alpha
             o.a.push_back((i == 0 ? alpha : 1.0 - alpha) * v);
           }
         }
       }
-      if (code[k] == 3) {                 // step 3
+      if (code[k] == 3) {                 // Gamma diagonal from the off-diagonal sums
         if (diag_at < 0) gfail(SFROM_EINVAL, "missing diagonal entry");
         double akk = 0.0;
         for (int t = s.rp[k]; t < s.rp[k + 1]; ++t)
@@ -788,7 +788,7 @@ extern "C" int sfrom_partition_graph(sfrom_t* h, int32_t n_cells, double alpha, 
   try {
     if (h->n <= 0) gfail(SFROM_ESTATE, "no pencil: call sfrom_set_pencil first");
     if (n_cells < 2) gfail(SFROM_EINVAL, "n_cells must be at least 2");
-    if (!(alpha >= 0.0 && alpha <= 1.0)) gfail(SFROM_EINVAL, "alpha must lie in [0, 1] (Alg. 1, step 2)");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) gfail(SFROM_EINVAL, "alpha must lie in [0, 1] (Alg. 1)");
     if (!(beta > 0.0 && beta < 1.0)) gfail(SFROM_EINVAL, "beta must lie in (0, 1) (eq. alg1B)");
     if (h->n >= ((int64_t)1 << 31)) gfail(SFROM_EINVAL, "pencil too large for a general partition");
     Sub whole;

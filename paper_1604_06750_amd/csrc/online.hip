@@ -21,11 +21,11 @@
 //   cell phase   a_l = C_{l-1}^T X_{l-1} + D_l X_l + C_l X_{l+1}
 //                Phi^1 = a_0 (the flux G^1 (U^2 - U^1) into the pieces),
 //                X_l <- 2X_l - X_l,old + dt^2 a_l,  l >= 1
-//                (Alg. alg1red step 2.2)
+//                (Alg. alg1red, stage 2: the cells' hidden layers)
 //   piece phase  r_p = sum over the cells owning p of their Phi^1 slice
-//                      + w^n g_p                            (step 2.1)
+//                      + w^n g_p                            (the exchange)
 //                y_p <- 2y_p - y_p,old + dt^2 M_p^{-1} r_p   (eq. bdrytstep,
-//                M_p = sum_i [(Ghat_i^1)^{-1}]_pp; step 2.3)
+//                M_p = sum_i [(Ghat_i^1)^{-1}]_pp)
 //   receivers    trace = sum_p q_p^T y_p                     (eq. solatrec)
 //
 // Blocks of a cell are stored in the order D_0, C_0, D_1, C_1, ..., D_{m-1},
